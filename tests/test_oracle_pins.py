@@ -1,0 +1,532 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+rational arithmetic, closed forms, identities of the TDI combinations,
+physical limits, symmetries and brute force on tiny grids.  Citations are to
+arXiv:2204.06633.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tdi_terms
+from paper_2204_06633_amd import inputs
+
+C = inputs.C_LIGHT
+
+
+def _static_orbits(positions, ltt=None, t_begin=0.0, t_end=1e5):
+    s = inputs.make_orbit_samples("static", t_begin, t_end, positions=positions, ltt=ltt)
+    return oracle.Orbits.from_samples(s)
+
+
+def _equilateral(side, z=0.0, centre=(1.0e11, 2.0e10), rot=0.3):
+    """Static equilateral triangle in the plane z, clockwise seen from +z."""
+    r = side / math.sqrt(3.0)
+    pts = []
+    for k in range(3):
+        a = rot - 2.0 * math.pi * k / 3.0
+        pts.append([centre[0] + r * math.cos(a), centre[1] + r * math.sin(a), z])
+    return np.array(pts)
+
+
+# ---------------------------------------------------------------------------
+# P1: Lagrange interpolation reproduces polynomials of degree <= order exactly
+#     (Sec. IV.E: centred Lagrange polynomials of user-defined order)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order", [1, 3, 5, 9, 15, 25, 31])
+def test_lagrange_reproduces_polynomials(order):
+    rng = np.random.default_rng(order)
+    half = (order + 1) // 2
+    n = order + 1 + 10
+    for deg in sorted({0, 1, order // 2, order}):
+        coeffs = [Fraction(float(c)) for c in rng.uniform(-1, 1, deg + 1)]
+        scale = Fraction(n)
+
+        def P(x):
+            return sum(c * (x / scale) ** k for k, c in enumerate(coeffs))
+
+        f = np.array([float(P(Fraction(j))) for j in range(n)])
+        for _ in range(5):
+            j0 = int(rng.integers(half - 1, n - half))
+            eps = float(rng.uniform(0, 1))
+            exact = float(P(Fraction(j0) + Fraction(eps)))
+            got = oracle.interp(f, order, j0, eps)
+            tol = 1e-13 * max(1.0, np.max(np.abs(f)))
+            assert abs(got - exact) <= tol, (deg, j0, eps, got, exact)
+
+
+@pytest.mark.parametrize("order", [1, 5, 25])
+def test_lagrange_weights_integer_position_is_identity(order):
+    w = oracle.lagrange_weights(order, 0.0)
+    e = np.zeros(order + 1)
+    e[(order + 1) // 2 - 1] = 1.0
+    assert np.array_equal(w, e)
+
+
+def test_interpolation_rejects_stencil_outside_series():
+    f = np.arange(30.0)
+    with pytest.raises(IndexError):
+        oracle.interp(f, 25, 11, 0.5)      # needs f[-1]
+    with pytest.raises(IndexError):
+        oracle.interp(f, 25, 17, 0.5)      # needs f[30]
+    oracle.interp(f, 25, 12, 0.5)
+    oracle.interp(f, 25, 16, 0.5)
+
+
+# ---------------------------------------------------------------------------
+# P3: sinusoids vs direct evaluation, within the Lagrange remainder bound
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("order,f,dt", [(25, 3e-3, 10.0), (25, 1e-2, 10.0), (9, 3e-3, 10.0),
+                                        (25, 1e-2, 15.0)])
+def test_interpolation_of_sinusoid_within_remainder_bound(order, f, dt):
+    rng = np.random.default_rng(7)
+    w = 2 * math.pi * f * dt
+    n = 200
+    j = np.arange(n)
+    samples = np.cos(w * j + 0.3)
+    # |R| <= w^(n+1) / (n+1)! * max |prod (eps - x_m)| for |f^(n+1)| <= w^(n+1)
+    taps = order + 1
+    half = taps // 2
+    eps_grid = np.linspace(0, 1, 101)
+    nodes = np.arange(taps) - (half - 1)
+    prod_max = max(abs(np.prod(e - nodes)) for e in eps_grid)
+    bound = w ** taps / math.factorial(taps) * prod_max + 1e-14
+    for _ in range(20):
+        j0 = int(rng.integers(half, n - half - 1))
+        eps = float(rng.uniform(0, 1))
+        got = oracle.interp(samples, order, j0, eps)
+        exact = math.cos(w * (j0 + eps) + 0.3)
+        assert abs(got - exact) <= bound, (got, exact, bound)
+
+
+# ---------------------------------------------------------------------------
+# Sky basis (Sec. IV.A): orthonormal, direct (u, v, k)
+# ---------------------------------------------------------------------------
+
+def test_sky_basis_is_direct_orthonormal():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        lam, beta = rng.uniform(0, 2 * math.pi), math.asin(rng.uniform(-1, 1))
+        k, u, v = oracle.sky_basis(lam, beta)
+        M = np.stack([u, v, k])
+        assert np.allclose(M @ M.T, np.eye(3), atol=1e-15)
+        assert np.allclose(np.cross(u, v), k, atol=1e-15)
+        # k points from the source towards the SSB
+        src = np.array([math.cos(beta) * math.cos(lam), math.cos(beta) * math.sin(lam),
+                        math.sin(beta)])
+        assert np.allclose(k, -src, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P2: integer delays -> pure index arithmetic, brute force on a tiny grid
+# ---------------------------------------------------------------------------
+
+def test_projection_integer_delays_brute_force():
+    """Static triangle in z = 0, source at the ecliptic pole (beta = pi/2):
+    k = -z, so k.x = 0 and k.n = 0; arms of 3 light-seconds with dt = 1 s.
+    Then y_ij[q] = (H_ij[q - 3] - H_ij[q]) / 2 exactly, with
+    xi+ = -cos 2(lam - a), xix = -sin 2(lam - a) for an arm at angle a."""
+    dt = 1.0
+    # centred on the origin: cos(pi/2) ~ 6e-17 then leaves k.x ~ 1e-16 s
+    pos = _equilateral(3.0 * C, z=0.0, centre=(0.0, 0.0))
+    orb = _static_orbits(pos, ltt=[3.0] * 6)
+    rng = np.random.default_rng(11)
+    n_h = 80
+    hp, hc = rng.standard_normal(n_h), rng.standard_normal(n_h)
+    lam = 0.7
+    q = np.arange(20, 60)
+    y = oracle.project_links(orb, 5000.0, dt, hp, hc, lam, math.pi / 2, 25, q)
+    for l, (r, e) in enumerate(tdi_terms.LINKS):
+        n = pos[r - 1] - pos[e - 1]
+        a = math.atan2(n[1], n[0])
+        xp, xc = -math.cos(2 * (lam - a)), -math.sin(2 * (lam - a))
+        H = xp * hp + xc * hc
+        expect = 0.5 * (H[q - 3] - H[q])
+        assert np.allclose(y[l], expect, rtol=0, atol=1e-14 * np.max(np.abs(H))), l
+
+
+# ---------------------------------------------------------------------------
+# P5: equal constant arms -> X1 = (1 - D^2)[y13 + D y31 - y12 - D y21],
+#     X2 = (1 - D^4) X1 (identities of eqs. tdi1 / tdi2 with all L equal)
+# P6: static unequal arms, y_ij = D_ij p_j - p_i -> X1 = X2 = 0
+#     (laser-noise cancellation, the purpose of TDI, Sec. I and IV.C)
+# Polynomial link series of degree <= order make the interpolation exact.
+# ---------------------------------------------------------------------------
+
+def _poly(rng, deg=6):
+    c = rng.uniform(-1, 1, deg + 1)
+    return lambda t: np.polyval(c, t / 50.0)
+
+
+@pytest.mark.parametrize("L,dt", [(8.0, 1.0), (8.3391, 1.0), (8.3391, 0.5)])
+def test_equal_arm_tdi_identities(L, dt):
+    rng = np.random.default_rng(5)
+    orb = _static_orbits(_equilateral(L * C), ltt=[L] * 6)
+    polys = {link: _poly(rng) for link in tdi_terms.LINKS}
+    n_y = int(8 * L / dt) + 80
+    t0_y = 1000.0
+    tt = lambda j: np.asarray(j, dtype=np.float64) * dt          # time since y[0]
+    y = np.stack([polys[lk](tt(np.arange(n_y))) for lk in tdi_terms.LINKS])
+    p = np.arange(n_y - 30, n_y - 14)
+    got1 = oracle.tdi_xyz(orb, t0_y, dt, y, 1, 25, p)
+    got2 = oracle.tdi_xyz(orb, t0_y, dt, y, 2, 25, p)
+    Y = lambda i, j, s: polys[(i, j)](s)
+
+    def inner(s):          # y13 + D y31 - y12 - D y21 at time s
+        return Y(1, 3, s) + Y(3, 1, s - L) - Y(1, 2, s) - Y(2, 1, s - L)
+
+    def X1(s):
+        return inner(s) - inner(s - 2 * L)
+
+    s = tt(p)
+    scale = np.max(np.abs(y))
+    assert np.allclose(got1[0], X1(s), rtol=0, atol=1e-12 * scale)
+    assert np.allclose(got2[0], X1(s) - X1(s - 4 * L), rtol=0, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("gen", [1, 2])
+def test_static_unequal_arms_cancel_laser_noise(gen):
+    rng = np.random.default_rng(9)
+    ltt = [8.21, 8.47, 8.05, 8.36, 8.12, 8.58]        # all different
+    orb = _static_orbits(_equilateral(8.3 * C), ltt=ltt)
+    dt = 1.0
+    lasers = [_poly(rng, 8) for _ in range(3)]
+    n_y = 160
+    s = np.arange(n_y) * dt
+    y = np.empty((6, n_y))
+    for l, (i, j) in enumerate(tdi_terms.LINKS):
+        y[l] = lasers[j - 1](s - ltt[l]) - lasers[i - 1](s)
+    p = np.arange(80, 140)
+    out = oracle.tdi_xyz(orb, 0.0, dt, y, gen, 25, p)
+    assert np.max(np.abs(out)) <= 1e-12 * np.max(np.abs(y))
+    # a single wrong delay breaks the cancellation
+    bad = list(ltt)
+    bad[0], bad[5] = bad[5], bad[0]
+    orb_bad = _static_orbits(_equilateral(8.3 * C), ltt=bad)
+    out_bad = oracle.tdi_xyz(orb_bad, 0.0, dt, y, gen, 25, p)
+    assert np.max(np.abs(out_bad)) > 1e-6 * np.max(np.abs(y))
+
+
+# ---------------------------------------------------------------------------
+# P7: cyclic relabelling of the spacecraft maps X -> Y -> Z (Sec. IV.C)
+# ---------------------------------------------------------------------------
+
+def test_cyclic_relabelling_maps_channels():
+    rng = np.random.default_rng(2)
+    s = inputs.make_orbit_samples("keplerian", 0.0, 4e5)
+    orb = oracle.Orbits.from_samples(s)
+    # relabel: new spacecraft i is old spacecraft sigma(i) = i + 1 (mod 3)
+    sig = {1: 2, 2: 3, 3: 1}
+    x2 = s.x[:, [1, 2, 0], :]
+    ltt2 = np.empty_like(s.ltt)
+    for l, (i, j) in enumerate(tdi_terms.LINKS):
+        ltt2[:, l] = s.ltt[:, tdi_terms.LINKS.index((sig[i], sig[j]))]
+    orb2 = oracle.Orbits(s.t0, s.dt, x2, ltt2)
+    dt = 10.0
+    n_y = 300
+    y = rng.standard_normal((6, n_y))
+    y2 = np.empty_like(y)
+    for l, (i, j) in enumerate(tdi_terms.LINKS):
+        y2[l] = y[tdi_terms.LINKS.index((sig[i], sig[j]))]
+    p = np.arange(40, 280)
+    a = oracle.tdi_xyz(orb, 1e5, dt, y, 2, 25, p)
+    b = oracle.tdi_xyz(orb2, 1e5, dt, y2, 2, 25, p)
+    assert np.allclose(b[0], a[1], rtol=0, atol=1e-13)
+    assert np.allclose(b[1], a[2], rtol=0, atol=1e-13)
+    assert np.allclose(b[2], a[0], rtol=0, atol=1e-13)
+
+
+def test_linearity_in_h():
+    s = inputs.make_orbit_samples("keplerian", 0.0, 3e4)
+    orb = oracle.Orbits.from_samples(s)
+    rng = np.random.default_rng(4)
+    n = 400
+    h1, h2, h3, h4 = (rng.standard_normal(n) for _ in range(4))
+    q = np.arange(100, 300)
+    args = (orb, 0.0, 10.0)
+    a = oracle.project_links(*args, h1, h2, 1.0, 0.4, 25, q)
+    b = oracle.project_links(*args, h3, h4, 1.0, 0.4, 25, q)
+    c = oracle.project_links(*args, 2.0 * h1 - 3.0 * h3, 2.0 * h2 - 3.0 * h4, 1.0, 0.4, 25, q)
+    assert np.allclose(c, 2.0 * a - 3.0 * b, rtol=0, atol=1e-13 * np.max(np.abs(c)))
+
+
+# ---------------------------------------------------------------------------
+# Physical limits of the link response (Sec. IV.B)
+# ---------------------------------------------------------------------------
+
+def test_long_wavelength_limit():
+    """For omega*L << 1 the link response tends to -(L/2) dH/dt at the
+    arm's retarded time, whatever the sky position (first-order expansion of
+    the two retarded times); the relative remainder is O(omega L)."""
+    dt = 10.0
+    s = inputs.make_orbit_samples("keplerian", 0.0, 2e5)
+    orb = oracle.Orbits.from_samples(s)
+    f = 2e-5
+    n = 600
+    t0_h = 50000.0
+    t = t0_h + np.arange(n) * dt
+    w = 2 * math.pi * f
+    hp, hc = np.cos(w * t), 0.5 * np.sin(w * t + 0.2)
+    q = np.arange(200, 400, 13)
+    for lam, beta in [(0.3, 0.2), (4.0, -1.1), (2.2, 1.4)]:
+        y = oracle.project_links(orb, t0_h, dt, hp, hc, lam, beta, 25, q)
+        k, u, v = oracle.sky_basis(lam, beta)
+        for i, qq in enumerate(q):
+            x, L = orb.state(t0_h + qq * dt)
+            for l, (r, e) in enumerate(tdi_terms.LINKS):
+                nv = x[r - 1] - x[e - 1]
+                nv /= np.linalg.norm(nv)
+                xp = np.dot(u, nv) ** 2 - np.dot(v, nv) ** 2
+                xc = 2 * np.dot(u, nv) * np.dot(v, nv)
+                # derivative at the retarded time of the arm's midpoint
+                tq = t0_h + qq * dt - np.dot(k, 0.5 * (x[r - 1] + x[e - 1])) / C
+                dH = xp * (-w * math.sin(w * tq)) + xc * 0.5 * w * math.cos(w * tq + 0.2)
+                approx = -0.5 * L[l] * dH
+                assert abs(y[l, i] - approx) <= 2e-3 * w * L[l], (lam, beta, l)
+
+
+def test_source_along_an_arm_is_regular():
+    """As k.n_ij -> 1 the two retarded times coincide and the 0/0 stays
+    finite, |y| <~ omega L |h|; a swapped emitter/receiver would blow up."""
+    dt = 1.0
+    pos = _equilateral(8.3 * C, z=0.0, centre=(0.0, 0.0))
+    orb = _static_orbits(pos)
+    n12 = (pos[0] - pos[1]) / np.linalg.norm(pos[0] - pos[1])
+    # choose the sky so that k = -e_r is (almost) n12
+    er = -n12
+    beta = math.asin(er[2])
+    lam = math.atan2(er[1], er[0]) + 2e-4
+    k, _, _ = oracle.sky_basis(lam, beta)
+    assert 0 < 1 - np.dot(k, n12) < 1e-7
+    n = 400
+    f = 1e-2
+    t0_h = 1000.0
+    t = t0_h + np.arange(n) * dt
+    hp = np.cos(2 * math.pi * f * t)
+    hc = np.sin(2 * math.pi * f * t)
+    y = oracle.project_links(orb, t0_h, dt, hp, hc, lam, beta, 25, np.arange(100, 300))
+    assert np.max(np.abs(y[0])) < 2 * math.pi * f * 8.3
+
+
+# ---------------------------------------------------------------------------
+# P4: monochromatic source, closed form of the whole response.
+#   * static equal-arm constellation, any sky;
+#   * rigid rotating constellation for the projection (C1 orbits), equal
+#     constant delays for TDI (the hybrid template of Sec. V).
+# y_ij(t) is evaluated analytically from exact orbits and h, and X1, X2 from
+# the equal-arm factorisations; the oracle must match to rounding.
+# ---------------------------------------------------------------------------
+
+def _analytic_y(pos_fn, ltt_fn, k, u, v, hfun, s, t_ref):
+    """Closed-form y_ij at times t_ref + s.  All retarded times are formed
+    relative to t_ref, so absolute times ~1e6 s never limit the precision."""
+    out = np.empty((6, len(s)))
+    x = pos_fn(t_ref + s)
+    L = ltt_fn(t_ref + s)
+    for l, (r, e) in enumerate(tdi_terms.LINKS):
+        xr, xe = x[:, r - 1], x[:, e - 1]
+        nv = xr - xe
+        nv /= np.linalg.norm(nv, axis=-1)[:, None]
+        un, vn = nv @ u, nv @ v
+        xp, xc = un * un - vn * vn, 2 * un * vn
+        te = s - L[:, l] - (xe @ k) / C
+        tr = s - (xr @ k) / C
+        hpe, hce = hfun(te)
+        hpr, hcr = hfun(tr)
+        out[l] = (xp * (hpe - hpr) + xc * (hce - hcr)) / (2 * (1 - nv @ k))
+    return out
+
+
+def _x_equal_arm(yfun, L, s, gen):
+    """X1 / X2 from the equal-arm factorisation, y given as a function."""
+    ix = {lk: i for i, lk in enumerate(tdi_terms.LINKS)}
+
+    def inner(ss):
+        y_ = lambda lk, tt: yfun(tt)[ix[lk]]
+        return y_((1, 3), ss) + y_((3, 1), ss - L) - y_((1, 2), ss) - y_((2, 1), ss - L)
+
+    X1 = lambda ss: inner(ss) - inner(ss - 2 * L)
+    return X1(s) if gen == 1 else X1(s) - X1(s - 4 * L)
+
+
+@pytest.mark.parametrize("orbit_kind", ["static", "rigid"])
+def test_monochromatic_closed_form(orbit_kind):
+    params = (1e-22, 3e-3, 0.0, 0.9, 0.6, 1.1, 2.3, 0.4)
+    order, dt, n_out = 25, 10.0, 600
+    t_start = 2.0e6
+    L_eq = 2.5e9 / C
+    if orbit_kind == "static":
+        pos = _equilateral(2.5e9, z=3e9)
+        s_proj = inputs.make_orbit_samples("static", t_start - 5e4, t_start + 5e4,
+                                           positions=pos, ltt=[L_eq] * 6)
+        pos_fn = lambda t: np.broadcast_to(pos, (len(t), 3, 3))
+        ltt_fn = lambda t: np.full((len(t), 6), L_eq)
+    else:
+        # a 2e3 s coarse grid keeps the spline's own error (~(dt_o Omega)^4 a)
+        # below the comparison tolerance; the 1e4 s grid leaves ~3 cm
+        s_proj = inputs.make_orbit_samples("rigid", t_start - 5e4, t_start + 5e4,
+                                           dt_orbit=2e3)
+        pos_fn = inputs.rigid_orbits
+        ltt_fn = lambda t: inputs.light_travel_times(inputs.rigid_orbits, t)
+    s_tdi = inputs.make_orbit_samples("static", t_start - 5e4, t_start + 5e4,
+                                      positions=_equilateral(2.5e9), ltt=[L_eq] * 6)
+    orb_p, orb_t = oracle.Orbits.from_samples(s_proj), oracle.Orbits.from_samples(s_tdi)
+    grid = inputs.make_template_grid(s_proj, order, dt, t_start, n_out)
+    hp, hc = inputs.gb_polarizations(params, grid.waveform_times())
+    hfun = lambda trel: inputs.gb_polarizations(params, trel)
+    k, u, v = oracle.sky_basis(params[6], params[7])
+    yfun = lambda srel: _analytic_y(pos_fn, ltt_fn, k, u, v, hfun, srel, t_start)
+    s_out = np.arange(n_out) * dt
+    for gen in (1, 2):
+        got = oracle.response(orb_p, orb_t, grid, hp, hc, params[6], params[7], order, gen)
+        exp = _x_equal_arm(yfun, L_eq, s_out, gen)
+        err = np.linalg.norm(got[0] - exp) / np.linalg.norm(exp)
+        assert err < 1e-11, (orbit_kind, gen, err)
+
+
+# ---------------------------------------------------------------------------
+# P8: adjoint = transpose of the forward (dot-product test, brute force)
+# ---------------------------------------------------------------------------
+
+def _small_case(n_out=40, order=5, kind="keplerian", dt=10.0):
+    s = inputs.make_orbit_samples(kind, 1e5, 1e5 + 5e3)
+    orb = oracle.Orbits.from_samples(s)
+    grid = inputs.make_template_grid(s, order, dt, 1e5 + 200.0, n_out)
+    return orb, grid
+
+
+@pytest.mark.parametrize("gen,channels", [(1, "XYZ"), (2, "AET")])
+def test_adjoint_dot_product(gen, channels):
+    orb, grid = _small_case(n_out=300, order=25)
+    rng = np.random.default_rng(8)
+    hp, hc = rng.standard_normal(grid.n_h), rng.standard_normal(grid.n_h)
+    g = rng.standard_normal((3, grid.n_out))
+    fwd = oracle.response(orb, orb, grid, hp, hc, 1.3, -0.5, 25, gen, channels)
+    ghp, ghc = oracle.response_adjoint(orb, orb, grid, 1.3, -0.5, 25, gen, g, channels)
+    lhs = math.fsum((fwd * g).ravel().tolist())
+    rhs = math.fsum((ghp * hp).tolist()) + math.fsum((ghc * hc).tolist())
+    assert abs(lhs - rhs) <= 1e-13 * (np.linalg.norm(fwd) * np.linalg.norm(g))
+
+
+def test_adjoint_brute_force_transpose():
+    orb, grid = _small_case(n_out=12, order=5)
+    lam, beta, order, gen = 2.0, 0.3, 5, 2
+    cols = []
+    for pol in range(2):
+        for j in range(grid.n_h):
+            e = np.zeros(grid.n_h)
+            e[j] = 1.0
+            z = np.zeros(grid.n_h)
+            args = (e, z) if pol == 0 else (z, e)
+            cols.append(oracle.response(orb, orb, grid, *args, lam, beta, order, gen).ravel())
+    R = np.stack(cols, axis=1)                  # [3 n_out][2 n_h]
+    g = np.random.default_rng(1).standard_normal((3, grid.n_out))
+    ghp, ghc = oracle.response_adjoint(orb, orb, grid, lam, beta, order, gen, g)
+    expect = R.T @ g.ravel()
+    got = np.concatenate([ghp, ghc])
+    assert np.allclose(got, expect, rtol=0, atol=1e-14 * np.max(np.abs(expect)))
+
+
+# ---------------------------------------------------------------------------
+# P9: splines and synthetic orbits
+# ---------------------------------------------------------------------------
+
+def test_spline_reproduces_cubics_and_tracks_orbits():
+    t0, dt, n = 0.0, 1e4, 20
+    tk = t0 + dt * np.arange(n)
+    cub = lambda t: 3.0 + 2e-4 * t - 1e-9 * t ** 2 + 4e-14 * t ** 3
+    x = np.stack([cub(tk)] * 9, -1).reshape(n, 3, 3)
+    ltt = np.stack([cub(tk)] * 6, -1)
+    orb = oracle.Orbits(t0, dt, x, ltt)
+    for t in np.linspace(0, dt * (n - 1), 37):
+        xx, L = orb.state(t)
+        assert np.allclose(xx, cub(t), rtol=1e-14)
+        assert np.allclose(L, cub(t), rtol=1e-14)
+    s = inputs.make_orbit_samples("keplerian", 0.0, 4e5)
+    orb = oracle.Orbits.from_samples(s)
+    for t in np.linspace(1e5, 3e5, 23):
+        xx, _ = orb.state(t)
+        exact = inputs.keplerian_orbits(np.array([t]))[0]
+        assert np.max(np.abs(xx - exact)) < 1e-12 * inputs.AU
+
+
+def test_synthetic_orbits_geometry():
+    t = np.linspace(0, inputs.YEAR, 400)
+    xr = inputs.rigid_orbits(t)
+    for i, j in [(0, 1), (1, 2), (2, 0)]:
+        assert np.allclose(np.linalg.norm(xr[:, i] - xr[:, j], axis=-1), inputs.L_ARM,
+                           rtol=1e-14)
+    xk = inputs.keplerian_orbits(t)
+    arms = np.stack([np.linalg.norm(xk[:, i] - xk[:, j], axis=-1)
+                     for i, j in [(0, 1), (1, 2), (2, 0)]])
+    flex = (arms.max() - arms.min()) / arms.mean()
+    assert 0.008 < flex < 0.012
+    assert abs(arms.mean() / inputs.L_ARM - 1) < 0.01
+    for xx in (xr, xk):
+        # spacecraft 1, 2, 3 clockwise seen from +z (Sec. IV, Fig. 1)
+        cz = np.cross(xx[:, 1] - xx[:, 0], xx[:, 2] - xx[:, 0])[:, 2]
+        assert np.all(cz < 0)
+        # constellation plane at 60 degrees to the ecliptic (Sec. IV.D)
+        nrm = np.cross(xx[:, 1] - xx[:, 0], xx[:, 2] - xx[:, 0])
+        nrm /= np.linalg.norm(nrm, axis=-1)[:, None]
+        tilt = np.degrees(np.arccos(np.abs(nrm[:, 2])))
+        assert np.all(np.abs(tilt - 60.0) < 1.0)
+
+
+def test_light_time_solution():
+    t = np.linspace(0, inputs.YEAR, 50)
+    for fn in (inputs.rigid_orbits, inputs.keplerian_orbits):
+        L = inputs.light_travel_times(fn, t)
+        x = fn(t)
+        for l, (r, e) in enumerate(tdi_terms.LINKS):
+            xe = fn(t - L[:, l])[:, e - 1]
+            resid = np.linalg.norm(x[:, r - 1] - xe, axis=-1) / C - L[:, l]
+            assert np.max(np.abs(resid)) < 1e-14 * 10
+    L = inputs.light_travel_times(inputs.rigid_orbits, t)
+    assert np.all(np.abs(L - inputs.L_ARM / C) < 2e-3)
+
+
+# ---------------------------------------------------------------------------
+# P10: A, E, T and the likelihood
+# ---------------------------------------------------------------------------
+
+def test_aet_map_and_likelihood():
+    rng = np.random.default_rng(6)
+    xyz = rng.standard_normal((3, 50))
+    M = np.array([[-1 / math.sqrt(2), 0, 1 / math.sqrt(2)],
+                  [1 / math.sqrt(6), -2 / math.sqrt(6), 1 / math.sqrt(6)],
+                  [1 / math.sqrt(3), 1 / math.sqrt(3), 1 / math.sqrt(3)]])
+    assert np.allclose(oracle.aet(xyz), M @ xyz, atol=1e-15)
+    assert np.allclose(M @ M.T, np.eye(3), atol=1e-15)          # orthonormal
+    g = rng.standard_normal((3, 50))
+    assert np.allclose(oracle.aet_transpose(g), M.T @ g, atol=1e-15)
+    h = rng.standard_normal((3, 50))
+    assert oracle.loglike(h, h, 2.0) == 0.0
+    d = h + rng.standard_normal((3, 50))
+    h1 = h + 1e-3 * rng.standard_normal((3, 50))
+    diff = oracle.loglike_difference(h1, h, d, 2.0)
+    assert math.isclose(diff, oracle.loglike(h1, d, 2.0) - oracle.loglike(h, d, 2.0),
+                        rel_tol=1e-9)
+
+
+def test_tdi_term_lists_shape():
+    """Eq. (tdi1): 8 terms per channel (2 undelayed); eq. (tdi2): 16 terms;
+    across X, Y, Z the 42 delayed TDI-2 terms use 36 distinct delay sums."""
+    for gen, per in [(1, 8), (2, 16)]:
+        ts = tdi_terms.michelson_terms(gen)
+        assert len(ts) == 3 * per
+        assert sum(1 for t in ts if len(t.path) == 1) == 6
+        assert sum(t.sign for t in ts) == 0
+    ts = tdi_terms.michelson_terms(2)
+    sums = set()
+    for t in ts:
+        if len(t.path) > 1:
+            sums.add(tuple(sorted(tdi_terms.LINKS.index((a, b))
+                                  for a, b in zip(t.path[:-1], t.path[1:]))))
+    assert len(sums) == 36
