@@ -1,0 +1,144 @@
+/*
+ * lisaresp.h -- C ABI of the MI355X (gfx950) generic LISA time-domain
+ * response: projection of the GW polarisations onto the six constellation
+ * links, then first/second-generation Michelson TDI (arXiv:2204.06633,
+ * Sec. IV).  FP64 throughout.
+ *
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller
+ * unless marked [host].  The library allocates, frees and synchronises
+ * nothing in the compute calls (lr_orbits_init alone synchronises the stream
+ * once, after its host-to-device copy), so the compute calls may be recorded
+ * into a HIP graph.  Outputs must not overlap inputs.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; NULL is the null
+ * stream.  Work is enqueued in stream order; calls return as soon as it is
+ * enqueued.
+ *
+ * Errors.  Argument checks happen on the host before any launch.  Every
+ * call returns an lr_status; on failure lr_last_error() holds a message
+ * (thread-local, valid until the next failing call on the thread).  A HIP
+ * launch failure maps to LR_E_HIP with the runtime's text.
+ *
+ * Conventions (Sec. IV and Fig. 1).  Spacecraft 1..3, clockwise seen from
+ * +z.  Link l = 0..5 is (receiver, emitter) = 12, 23, 31, 13, 32, 21, and
+ * every per-link array is link-major: y[l * n + j].  Times are seconds,
+ * positions metres in the SSB ecliptic frame.  A uniformly sampled series
+ * s[j] sits at absolute time t0 + j * dt.
+ *
+ * Interpolation (Sec. IV.E).  Centred Lagrange interpolation of odd order
+ * 1..31 (order + 1 taps): a value at fractional index j0 + eps, eps in
+ * [0, 1), reads samples j0 - (order-1)/2 ... j0 + (order+1)/2.  Retarded
+ * positions are formed as an integer sample index minus (delay / dt), with
+ * the integer and fractional parts kept apart, so absolute times never limit
+ * the FP64 precision.  Stencils never leave the caller's arrays: calls whose
+ * padding is too small return LR_E_RANGE (see lr_projection_padding,
+ * lr_tdi_padding).
+ */
+#ifndef LISARESP_H
+#define LISARESP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LR_OK = 0,
+    LR_E_ARG = 1,          /* null/aliased pointer, bad size, non-finite scalar */
+    LR_E_RANGE = 2,        /* a stencil or an orbit evaluation leaves its data */
+    LR_E_UNSUPPORTED = 3,  /* even or out-of-range order, unknown generation */
+    LR_E_WORKSPACE = 4,    /* storage or workspace smaller than required */
+    LR_E_HIP = 5           /* the HIP runtime reported an error */
+} lr_status;
+
+/* TDI output channels: X,Y,Z; A,E,T; or X,Y,Z followed by A,E,T. */
+enum { LR_XYZ = 0, LR_AET = 1, LR_XYZ_AET = 2 };
+
+/* Text of a status code; never NULL. */
+const char *lr_status_str(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *lr_last_error(void);
+/* ABI version of this header (bumped on incompatible changes). */
+int lr_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Orbits.  The paper interpolates the orbit data once per run and keeps it
+ * for every evaluation (Sec. IV.E).  Here the 9 position series (x, y, z of
+ * spacecraft 1..3) and the 6 light travel times (link order above, at
+ * reception time) are fitted with not-a-knot cubic splines on their coarse
+ * uniform grid; kernels evaluate them at every sample time they need.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double t0;           /* absolute time of coarse sample 0 (s) */
+    double dt;           /* coarse spacing (s), > 0 */
+    int64_t n;           /* coarse samples, >= 4 */
+    const void *coef;    /* device storage written by lr_orbits_init */
+    double L_min, L_max; /* rigorous bounds of the light-time splines (s) */
+    double R_max;        /* rigorous bound of |x| over the position splines (m) */
+} lr_orbits;
+
+/* Bytes of device storage lr_orbits_init needs for n coarse samples. */
+size_t lr_orbits_bytes(int64_t n);
+
+/* Fit the splines on the host and copy the coefficients to d_storage (the
+ * caller keeps it alive while `out` is used).  x_sc [host][n][3][3] metres,
+ * ltt [host][n][6] seconds.  Synchronises `stream` once.  Errors: LR_E_ARG
+ * (n < 4, dt <= 0, non-finite data), LR_E_WORKSPACE (bytes too small),
+ * LR_E_HIP. */
+int lr_orbits_init(double t0, double dt, int64_t n, const double *x_sc, const double *ltt,
+                   void *d_storage, size_t bytes, lr_orbits *out, void *stream);
+
+/* Samples of h+/hx that lr_project_links needs before the first and after
+ * the last link sample it writes, for any sky position (from the orbit
+ * bounds and the stencil half-width). */
+int lr_projection_padding(const lr_orbits *orb, int order, double dt, int64_t *front,
+                          int64_t *back);
+
+/* Samples of y that lr_tdi_combine needs before the first and after the last
+ * output sample, for generation 1 (chains of <= 3 links) or 2 (<= 7). */
+int lr_tdi_padding(const lr_orbits *orb, int order, int generation, double dt, int64_t *front,
+                   int64_t *back);
+
+/* ------------------------------------------------------------------------
+ * Projection, Sec. IV.B, eq. (instrument response):
+ *   y_ij(t) = [H_ij(t - L_ij(t) - k.x_j(t)/c) - H_ij(t - k.x_i(t)/c)]
+ *             / (2 (1 - k.n_ij(t))),
+ *   H_ij = h+ xi+(u, v, n_ij) + hx xix(u, v, n_ij),
+ *   xi+ = (u.n)^2 - (v.n)^2,  xix = 2 (u.n)(v.n),
+ * with k = -e_r, u = -e_phi, v = -e_theta of the ecliptic sky position
+ * (lam, beta) (Sec. IV.A), n_ij = (x_i - x_j)/|x_i - x_j| and all orbit
+ * quantities at the reception time t.
+ *
+ * hp, hc: [n_h] at t0_h + j*dt.  Writes y[l * n_y + i] for the link sample
+ * at h-index y_start + i, i = 0..n_y-1.  Requires y_start - front >= 0 and
+ * y_start + n_y - 1 + back <= n_h - 1 (lr_projection_padding), and the orbit
+ * grid to cover the link sample times.  n_y = 0 is a no-op.
+ * ---------------------------------------------------------------------- */
+int lr_project_links(const lr_orbits *orb, double t0_h, double dt, int64_t n_h,
+                     const double *hp, const double *hc, double lam, double beta, int order,
+                     int64_t y_start, int64_t n_y, double *y, void *stream);
+
+/* ------------------------------------------------------------------------
+ * TDI, Sec. IV.C, eqs. (tdi1), (tdi2): Michelson X1 / X2 as signed sums of
+ * link series delayed by chained delays D_{i1..in} x(t) = x(t - sum_k
+ * L_{ik ik+1}(t)) (sums, all light times at the output time t); Y and Z by
+ * the cyclic relabelling 1->2->3->1; optionally A = (Z-X)/sqrt2,
+ * E = (X-2Y+Z)/sqrt6, T = (X+Y+Z)/sqrt3.
+ *
+ * y: [6][n_y] at t0_y + j*dt.  Writes out[c * n_out + i] for the sample
+ * at y-index out_start + i, c = X,Y,Z (LR_XYZ), A,E,T (LR_AET) or
+ * X,Y,Z,A,E,T (LR_XYZ_AET, out holds 6 rows).  Requires
+ * out_start - front >= 0 and out_start + n_out - 1 + back <= n_y - 1
+ * (lr_tdi_padding) and the orbit grid to cover the output times.
+ * ---------------------------------------------------------------------- */
+int lr_tdi_combine(const lr_orbits *orb, double t0_y, double dt, int64_t n_y, const double *y,
+                   int generation, int order, int channels, int64_t out_start, int64_t n_out,
+                   double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LISARESP_H */

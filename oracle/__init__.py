@@ -229,7 +229,18 @@ def response(orb_proj: Orbits, orb_tdi: Orbits, grid, hp, hc, lam, beta, order, 
     p = np.asarray(out_idx, dtype=np.int64) + grid.front_tdi
     t0_y = grid.t0_h + grid.y_start * grid.dt
     xyz = tdi_xyz(orb_tdi, t0_y, grid.dt, y, generation, order, p)
-    return aet(xyz) if channels == "AET" else xyz
+    return select_channels(xyz, channels)
+
+
+def select_channels(xyz, channels):
+    """X,Y,Z ("XYZ"), A,E,T ("AET") or both stacked ("XYZAET")."""
+    if channels == "XYZ":
+        return xyz
+    if channels == "AET":
+        return aet(xyz)
+    if channels == "XYZAET":
+        return np.concatenate([xyz, aet(xyz)])
+    raise ValueError(channels)
 
 
 # ---------------------------------------------------------------------------
@@ -270,6 +281,8 @@ def response_adjoint(orb_proj, orb_tdi, grid, lam, beta, order, generation, g_ou
     g = np.asarray(g_out, dtype=np.float64)
     if channels == "AET":
         g = aet_transpose(g)
+    elif channels == "XYZAET":
+        g = g[:3] + aet_transpose(g[3:])
     p = np.arange(grid.n_out) + grid.front_tdi
     t0_y = grid.t0_h + grid.y_start * grid.dt
     g_y = tdi_adjoint(orb_tdi, t0_y, grid.dt, grid.n_y, generation, order, p, g)

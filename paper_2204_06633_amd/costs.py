@@ -1,0 +1,59 @@
+"""Algorithmic FLOP and HBM-byte counts per output sample of each kernel.
+
+These are properties of the algorithm as the kernels implement it, not
+measurements: they turn measured kernel times into roofline fractions.
+FLOPs count an FMA as 2.  N = order + 1 interpolation taps.
+
+Lagrange weights by prefix / suffix products cost 5N FLOPs per retarded
+position (N differences eps - x_m, N prefix products, N suffix products, 2N
+products w_m = pre_m * suf_m * c_m); applying them to one series costs N FMAs
+(2N FLOPs).  Orbit splines cost one cubic (3 FMAs, 6 FLOPs) per series.
+"""
+from __future__ import annotations
+
+# Second-generation X, Y, Z: 48 terms, 6 undelayed, 42 delayed, whose delays
+# take 36 distinct values (delay groups); first generation: 24 terms, 6
+# undelayed, 18 delayed, 15 distinct delays.
+TDI_SHAPE = {1: dict(groups=15, delayed=18, direct=6, mean_links=2.0),
+             2: dict(groups=36, delayed=42, direct=6, mean_links=150.0 / 36.0)}
+
+
+def weights_flops(taps):
+    return 5 * taps
+
+
+def tdi_flops_per_sample(order, generation, channels="XYZ"):
+    n = order + 1
+    s = TDI_SHAPE[generation]
+    orbit = 6 * 6                                             # 6 light-time splines
+    delays = s["groups"] * (s["mean_links"] - 1 + 3)          # sums + split (mul, floor, sub)
+    weights = s["groups"] * weights_flops(n)
+    taps = s["delayed"] * 2 * n
+    direct = s["direct"]
+    aet = 0 if channels == "XYZ" else 12
+    return orbit + delays + weights + taps + direct + aet
+
+
+def projection_flops_per_sample(order):
+    n = order + 1
+    orbit = 15 * 6                                           # 9 positions + 6 light times
+    geometry = 3 * 6 + 3 * (3 + 6 + 2 + 3 + 3 * 5 + 4) + 6 * 5   # k.x, arms (n, xi, k.n), 1/(2(1-k.n))
+    positions = 9 * 4
+    weights = 9 * weights_flops(n)
+    taps = 9 * 2 * 2 * n                                     # h+ and hx per position
+    assemble = 6 * 7
+    return orbit + geometry + positions + weights + taps + assemble
+
+
+def tdi_bytes_per_sample(channels="XYZ"):
+    rows = 6 if channels == "XYZAET" else 3
+    return 6 * 8 + rows * 8                                  # read y, write channels
+
+
+def projection_bytes_per_sample():
+    return 2 * 8 + 6 * 8                                     # read h+, hx; write y
+
+
+# MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 FLOPs (FMA) x 2.4 GHz.
+FP64_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9                  # 78.6 TFLOP/s
+HBM_PEAK = 8.0e12                                            # bytes/s

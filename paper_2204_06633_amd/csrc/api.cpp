@@ -1,0 +1,310 @@
+// C-ABI host layer: argument validation, orbit spline fit, padding rules and
+// kernel dispatch.  See include/lisaresp.h for the contract of every call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lisaresp.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(LR_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+bool valid_order(int order) { return order >= 1 && order <= 31 && (order % 2) == 1; }
+
+// Byte ranges [a, a+na) and [b, b+nb) overlap.
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Not-a-knot cubic spline through y[0..n-1] on a uniform grid of spacing h.
+// Second derivatives M solve M[i-1] + 4 M[i] + M[i+1] = 6 (y[i+1] - 2 y[i] +
+// y[i-1]) / h^2 (i = 1..n-2) with third-derivative continuity at the second
+// and second-to-last knots, M[0] - 2 M[1] + M[2] = 0 (and mirror).  On a
+// uniform grid those conditions turn rows 1 and n-2 into 6 M = rhs, which
+// leaves a tridiagonal system for M[2..n-3] (Thomas algorithm).
+void fit_not_a_knot(const double* y, ptrdiff_t stride, int64_t n, double h, double* coef,
+                    ptrdiff_t cstride) {
+  std::vector<double> M(n), r(n);
+  for (int64_t i = 1; i + 1 < n; ++i)
+    r[i] = 6.0 * (y[(i + 1) * stride] - 2.0 * y[i * stride] + y[(i - 1) * stride]) / (h * h);
+  M[1] = r[1] / 6.0;
+  M[n - 2] = r[n - 2] / 6.0;
+  const int64_t m = n - 4;   // unknowns M[2..n-3]
+  if (m > 0) {
+    std::vector<double> cp(m), dp(m);
+    for (int64_t k = 0; k < m; ++k) {
+      const int64_t i = k + 2;
+      double rhs = r[i];
+      if (k == 0) rhs -= M[1];
+      if (k == m - 1) rhs -= M[n - 2];
+      const double sub = (k == 0) ? 0.0 : 1.0;
+      const double den = 4.0 - sub * (k == 0 ? 0.0 : cp[k - 1]);
+      cp[k] = 1.0 / den;
+      dp[k] = (rhs - sub * (k == 0 ? 0.0 : dp[k - 1])) / den;
+    }
+    M[m + 1] = dp[m - 1];
+    for (int64_t k = m - 2; k >= 0; --k) M[k + 2] = dp[k] - cp[k] * M[k + 3];
+  }
+  M[0] = 2.0 * M[1] - M[2];
+  M[n - 1] = 2.0 * M[n - 2] - M[n - 3];
+  for (int64_t i = 0; i + 1 < n; ++i) {
+    const double y0 = y[i * stride], y1 = y[(i + 1) * stride];
+    double* c = coef + i * cstride;
+    c[0] = y0;
+    c[1] = (y1 - y0) / h - h * (2.0 * M[i] + M[i + 1]) / 6.0;
+    c[2] = 0.5 * M[i];
+    c[3] = (M[i + 1] - M[i]) / (6.0 * h);
+  }
+}
+
+// Largest |p(u)| for u in [0, h] of a cubic, bounded by sum |c_k| h^k.
+double seg_abs_bound(const double* c, double h) {
+  return std::fabs(c[0]) + h * (std::fabs(c[1]) + h * (std::fabs(c[2]) + h * std::fabs(c[3])));
+}
+
+lr::OrbitView view_of(const lr_orbits* o) {
+  lr::OrbitView v;
+  v.coef = static_cast<const double*>(o->coef);
+  v.dt = o->dt;
+  v.inv_dt = 1.0 / o->dt;
+  v.nseg = o->n - 1;
+  return v;
+}
+
+int check_orbits(const lr_orbits* o) {
+  if (!o || !o->coef || o->n < 4 || !(o->dt > 0.0) || !is_finite(o->t0) || !is_finite(o->dt))
+    return fail(LR_E_ARG, "orbits not initialised");
+  return LR_OK;
+}
+
+// Every time t0 + j*dt, j in [j0, j1], lies on the orbit grid.
+int check_orbit_span(const lr_orbits* o, double t_off, double dt, int64_t j0, int64_t j1) {
+  const double span = (double)(o->n - 1) * o->dt;
+  const double a = t_off + (double)j0 * dt, b = t_off + (double)j1 * dt;
+  if (!(a >= 0.0) || !(b <= span))
+    return fail(LR_E_RANGE, "sample times [%.17g, %.17g] s leave the orbit grid [0, %.17g] s "
+                            "(relative to its first sample)", a, b, span);
+  return LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lr_status_str(int s) {
+  switch (s) {
+    case LR_OK: return "LR_OK";
+    case LR_E_ARG: return "LR_E_ARG: invalid argument";
+    case LR_E_RANGE: return "LR_E_RANGE: stencil or orbit evaluation outside the data";
+    case LR_E_UNSUPPORTED: return "LR_E_UNSUPPORTED: unsupported order, generation or mode";
+    case LR_E_WORKSPACE: return "LR_E_WORKSPACE: storage or workspace too small";
+    case LR_E_HIP: return "LR_E_HIP: HIP runtime error";
+    default: return "unknown lr_status";
+  }
+}
+
+const char* lr_last_error(void) { return g_err.c_str(); }
+
+int lr_abi_version(void) { return 1; }
+
+size_t lr_orbits_bytes(int64_t n) {
+  if (n < 4) return 0;
+  return (size_t)(n - 1) * lr::kSegStride * sizeof(double);
+}
+
+int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
+                   void* d_storage, size_t bytes, lr_orbits* out, void* stream) {
+  if (!out || !x_sc || !ltt || !d_storage) return fail(LR_E_ARG, "null pointer");
+  if (n < 4) return fail(LR_E_ARG, "need at least 4 coarse orbit samples (got %lld)", (long long)n);
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0)) return fail(LR_E_ARG, "bad orbit grid t0/dt");
+  if (bytes < lr_orbits_bytes(n))
+    return fail(LR_E_WORKSPACE, "orbit storage %zu bytes < %zu", bytes, lr_orbits_bytes(n));
+  for (int64_t i = 0; i < n * 9; ++i)
+    if (!is_finite(x_sc[i])) return fail(LR_E_ARG, "non-finite spacecraft position");
+  for (int64_t i = 0; i < n * 6; ++i)
+    if (!is_finite(ltt[i])) return fail(LR_E_ARG, "non-finite light travel time");
+
+  const int64_t nseg = n - 1;
+  std::vector<double> coef((size_t)nseg * lr::kSegStride, 0.0);
+  for (int s = 0; s < 9; ++s)
+    fit_not_a_knot(x_sc + s, 9, n, dt, coef.data() + 4 * s, lr::kSegStride);
+  for (int l = 0; l < 6; ++l)
+    fit_not_a_knot(ltt + l, 6, n, dt, coef.data() + 4 * (9 + l), lr::kSegStride);
+
+  double rmax = 0.0, lmax = -INFINITY, lmin = INFINITY;
+  for (int64_t k = 0; k < nseg; ++k) {
+    const double* seg = coef.data() + k * lr::kSegStride;
+    for (int sc = 0; sc < 3; ++sc) {
+      double r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double b = seg_abs_bound(seg + 4 * (3 * sc + c), dt);
+        r2 += b * b;
+      }
+      rmax = std::max(rmax, std::sqrt(r2));
+    }
+    for (int l = 0; l < 6; ++l) {
+      const double* c = seg + 4 * (9 + l);
+      double var = dt * (std::fabs(c[1]) + dt * (std::fabs(c[2]) + dt * std::fabs(c[3])));
+      lmax = std::max(lmax, c[0] + var);
+      lmin = std::min(lmin, c[0] - var);
+    }
+  }
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(d_storage, coef.data(), coef.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "lr_orbits_init copy");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "lr_orbits_init sync");
+
+  out->t0 = t0;
+  out->dt = dt;
+  out->n = n;
+  out->coef = d_storage;
+  out->L_min = lmin;
+  out->L_max = lmax;
+  out->R_max = rmax;
+  return LR_OK;
+}
+
+int lr_projection_padding(const lr_orbits* orb, int order, double dt, int64_t* front,
+                          int64_t* back) {
+  if (int st = check_orbits(orb)) return st;
+  if (!front || !back) return fail(LR_E_ARG, "null pointer");
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (!(dt > 0.0) || !is_finite(dt)) return fail(LR_E_ARG, "bad dt");
+  const int half = (order + 1) / 2;
+  const double rc = orb->R_max / lr::kC;
+  const double dmax = std::max(orb->L_max, 0.0) + rc;   // largest retarded delay
+  const double dmin = std::min(orb->L_min, 0.0) - rc;   // most negative one
+  *front = (int64_t)std::ceil(dmax / dt) + half + 1;
+  *back = (int64_t)std::ceil(-dmin / dt) + half + 1;
+  return LR_OK;
+}
+
+int lr_tdi_padding(const lr_orbits* orb, int order, int generation, double dt, int64_t* front,
+                   int64_t* back) {
+  if (int st = check_orbits(orb)) return st;
+  if (!front || !back) return fail(LR_E_ARG, "null pointer");
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (generation != 1 && generation != 2)
+    return fail(LR_E_UNSUPPORTED, "generation %d (1 or 2)", generation);
+  if (!(dt > 0.0) || !is_finite(dt)) return fail(LR_E_ARG, "bad dt");
+  const int half = (order + 1) / 2;
+  const int chain = generation == 1 ? 3 : 7;             // longest chain of link delays
+  const double dmax = chain * std::max(orb->L_max, 0.0);
+  const double dmin = chain * std::min(orb->L_min, 0.0);
+  *front = (int64_t)std::ceil(dmax / dt) + half + 1;
+  *back = (int64_t)std::ceil(-dmin / dt) + half + 1;
+  return LR_OK;
+}
+
+int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, const double* hp,
+                     const double* hc, double lam, double beta, int order, int64_t y_start,
+                     int64_t n_y, double* y, void* stream) {
+  if (int st = check_orbits(orb)) return st;
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (n_y < 0 || n_h < 0 || y_start < 0) return fail(LR_E_ARG, "negative size or start");
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_h) || !is_finite(lam) || !is_finite(beta))
+    return fail(LR_E_ARG, "non-finite time, dt or sky angle");
+  if (n_y == 0) return LR_OK;
+  if (!hp || !hc || !y) return fail(LR_E_ARG, "null pointer");
+  if (n_y > ((int64_t)1 << 40)) return fail(LR_E_ARG, "n_y too large");
+  if (overlap(y, 6 * n_y * sizeof(double), hp, n_h * sizeof(double)) ||
+      overlap(y, 6 * n_y * sizeof(double), hc, n_h * sizeof(double)))
+    return fail(LR_E_ARG, "y overlaps h+ or hx");
+  int64_t front, back;
+  if (int st = lr_projection_padding(orb, order, dt, &front, &back)) return st;
+  if (y_start - front < 0 || y_start + n_y - 1 + back > n_h - 1)
+    return fail(LR_E_RANGE, "h covers [0, %lld) but the link samples [%lld, %lld) need "
+                            "%lld before and %lld after", (long long)n_h, (long long)y_start,
+                (long long)(y_start + n_y), (long long)front, (long long)back);
+  const double t_off = t0_h - orb->t0;
+  if (int st = check_orbit_span(orb, t_off, dt, y_start, y_start + n_y - 1)) return st;
+
+  lr::ProjArgs a;
+  a.orb = view_of(orb);
+  a.hp = hp;
+  a.hc = hc;
+  a.n_h = n_h;
+  a.t_off = t_off;
+  a.dt = dt;
+  a.inv_dt = 1.0 / dt;
+  a.sky = lr::sky_basis(lam, beta);
+  a.y_start = y_start;
+  a.n_y = n_y;
+  a.y = y;
+  hipError_t e = lr::run_project_links(order, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lr_project_links launch");
+  return LR_OK;
+}
+
+int lr_tdi_combine(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, const double* y,
+                   int generation, int order, int channels, int64_t out_start, int64_t n_out,
+                   double* out, void* stream) {
+  if (int st = check_orbits(orb)) return st;
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (generation != 1 && generation != 2)
+    return fail(LR_E_UNSUPPORTED, "generation %d (1 or 2)", generation);
+  if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
+    return fail(LR_E_UNSUPPORTED, "channels %d (LR_XYZ, LR_AET or LR_XYZ_AET)", channels);
+  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
+  if (n_out < 0 || n_y < 0 || out_start < 0) return fail(LR_E_ARG, "negative size or start");
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_y)) return fail(LR_E_ARG, "non-finite t0 or dt");
+  if (n_out == 0) return LR_OK;
+  if (!y || !out) return fail(LR_E_ARG, "null pointer");
+  if (n_out > ((int64_t)1 << 40)) return fail(LR_E_ARG, "n_out too large");
+  if (overlap(out, rows * n_out * sizeof(double), y, 6 * n_y * sizeof(double)))
+    return fail(LR_E_ARG, "out overlaps y");
+  int64_t front, back;
+  if (int st = lr_tdi_padding(orb, order, generation, dt, &front, &back)) return st;
+  if (out_start - front < 0 || out_start + n_out - 1 + back > n_y - 1)
+    return fail(LR_E_RANGE, "y covers [0, %lld) but the outputs [%lld, %lld) need %lld "
+                            "before and %lld after", (long long)n_y, (long long)out_start,
+                (long long)(out_start + n_out), (long long)front, (long long)back);
+  const double t_off = t0_y - orb->t0;
+  if (int st = check_orbit_span(orb, t_off, dt, out_start, out_start + n_out - 1)) return st;
+
+  lr::TdiArgs a;
+  a.orb = view_of(orb);
+  a.y = y;
+  a.n_y = n_y;
+  a.t_off = t_off;
+  a.dt = dt;
+  a.inv_dt = 1.0 / dt;
+  a.out_start = out_start;
+  a.n_out = n_out;
+  a.channels = channels;
+  a.out = out;
+  hipError_t e = lr::run_tdi(order, generation, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lr_tdi_combine launch");
+  return LR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+"""Build the HIP library ``_lisaresp.so`` for gfx950 in the package directory.
+
+Run ``python -m paper_2204_06633_amd.csrc.build`` (or call ``build()``).  Every
+call recompiles.  Flags: -O3, C++17, no fast-math (IEEE division and square
+root), FMA contraction allowed, packed-FP32 instructions disabled.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.dirname(HERE)
+ROOT = os.path.dirname(PKG)
+TARGET = os.path.join(PKG, "_lisaresp.so")
+SOURCES = ["forward_a.hip", "forward_b.hip", "forward_c.hip", "forward_d.hip", "dispatch.cpp",
+           "api.cpp"]
+ARCH = os.environ.get("LR_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def flags():
+    return ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-munsafe-fp-atomics", "-fno-fast-math", "-Wall", "-Wno-unused-variable",
+            "-I" + os.path.join(ROOT, "include")]
+
+
+def build(verbose=True, jobs=None):
+    """Compile every source to an object in parallel, then link the library."""
+    out_dir = os.path.join(HERE, "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    cc = hipcc()
+    t0 = time.time()
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(out_dir, src.rsplit(".", 1)[0] + ".o")
+        objs.append(obj)
+        cmd = [cc, *flags(), "-c", os.path.join(HERE, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+    for src, p in procs:
+        if p.wait() != 0:
+            raise RuntimeError("compilation of %s failed" % src)
+    tmp = TARGET + ".tmp%d" % os.getpid()
+    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, TARGET)
+    if verbose:
+        print("built %s in %.1f s" % (TARGET, time.time() - t0), flush=True)
+    return TARGET
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)

@@ -1,0 +1,168 @@
+"""ctypes binding of the HIP library ``_lisaresp.so`` (C ABI in include/lisaresp.h).
+
+Argument marshalling only: every step of the response runs in the library's
+kernels.  Arrays are torch CUDA tensors (float64, contiguous); the stream is
+torch's current stream unless one is given.  A missing library raises: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lisaresp.so")
+
+LR_XYZ, LR_AET, LR_XYZ_AET = 0, 1, 2
+CHANNELS = {"XYZ": LR_XYZ, "AET": LR_AET, "XYZAET": LR_XYZ_AET}
+
+
+class LisaRespError(RuntimeError):
+    def __init__(self, status, where, message):
+        self.status = status
+        super().__init__("%s failed: %s (%s)" % (where, message, _status_name(status)))
+
+
+class lr_orbits(ctypes.Structure):
+    _fields_ = [("t0", ctypes.c_double), ("dt", ctypes.c_double), ("n", ctypes.c_int64),
+                ("coef", ctypes.c_void_p), ("L_min", ctypes.c_double),
+                ("L_max", ctypes.c_double), ("R_max", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _status_name(s):
+    try:
+        return lib().lr_status_str(int(s)).decode()
+    except Exception:  # noqa: BLE001 - only used to decorate an error message
+        return str(s)
+
+
+def lib():
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("HIP library %s is missing; build it with "
+                           "`python -m paper_2204_06633_amd.csrc.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    d, i32, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    P = ctypes.POINTER
+    po = P(lr_orbits)
+    L.lr_status_str.restype = ctypes.c_char_p
+    L.lr_status_str.argtypes = [i32]
+    L.lr_last_error.restype = ctypes.c_char_p
+    L.lr_abi_version.restype = i32
+    L.lr_orbits_bytes.restype = ctypes.c_size_t
+    L.lr_orbits_bytes.argtypes = [i64]
+    L.lr_orbits_init.argtypes = [d, d, i64, vp, vp, vp, ctypes.c_size_t, po, vp]
+    L.lr_projection_padding.argtypes = [po, i32, d, P(i64), P(i64)]
+    L.lr_tdi_padding.argtypes = [po, i32, i32, d, P(i64), P(i64)]
+    L.lr_project_links.argtypes = [po, d, d, i64, vp, vp, d, d, i32, i64, i64, vp, vp]
+    L.lr_tdi_combine.argtypes = [po, d, d, i64, vp, i32, i32, i32, i64, i64, vp, vp]
+    for name in ("lr_orbits_init", "lr_projection_padding", "lr_tdi_padding",
+                 "lr_project_links", "lr_tdi_combine"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status, where):
+    if status != 0:
+        raise LisaRespError(status, where, lib().lr_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Orbits
+# ---------------------------------------------------------------------------
+
+class Orbits:
+    """Orbit splines resident on the GPU (lr_orbits_init).
+
+    ``x`` [n][3][3] m and ``ltt`` [n][6] s are host arrays on the coarse grid
+    t0 + k*dt."""
+
+    def __init__(self, t0, dt, x, ltt, device="cuda", stream=None):
+        import numpy as np
+        import torch
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3, 3))
+        ltt = np.ascontiguousarray(np.asarray(ltt, dtype=np.float64).reshape(-1, 6))
+        n = x.shape[0]
+        if ltt.shape[0] != n:
+            raise ValueError("x and ltt have different lengths")
+        nbytes = lib().lr_orbits_bytes(n)
+        self.storage = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=device)
+        self.c = lr_orbits()
+        _check(lib().lr_orbits_init(float(t0), float(dt), n, x.ctypes.data, ltt.ctypes.data,
+                                    ctypes.c_void_p(self.storage.data_ptr()), nbytes,
+                                    ctypes.byref(self.c), _stream(stream)), "lr_orbits_init")
+
+    @classmethod
+    def from_samples(cls, s, **kw):
+        return cls(s.t0, s.dt, s.x, s.ltt, **kw)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+    def projection_padding(self, order, dt):
+        f, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lr_projection_padding(self.ref, int(order), float(dt), ctypes.byref(f),
+                                           ctypes.byref(b)), "lr_projection_padding")
+        return f.value, b.value
+
+    def tdi_padding(self, order, generation, dt):
+        f, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lr_tdi_padding(self.ref, int(order), int(generation), float(dt),
+                                    ctypes.byref(f), ctypes.byref(b)), "lr_tdi_padding")
+        return f.value, b.value
+
+
+# ---------------------------------------------------------------------------
+# Plain per-template calls
+# ---------------------------------------------------------------------------
+
+def project_links(orb: Orbits, t0_h, dt, hp, hc, lam, beta, order, y_start, n_y, y=None,
+                  stream=None):
+    """Link responses y[6][n_y] for the link samples at h-indices
+    y_start .. y_start + n_y - 1 (lr_project_links)."""
+    import torch
+    if y is None:
+        y = torch.empty((6, n_y), dtype=torch.float64, device=hp.device)
+    _check(lib().lr_project_links(orb.ref, float(t0_h), float(dt), hp.numel(), _dev(hp, "hp"),
+                                  _dev(hc, "hc"), float(lam), float(beta), int(order),
+                                  int(y_start), int(n_y), _dev(y, "y"), _stream(stream)),
+           "lr_project_links")
+    return y
+
+
+def tdi_combine(orb: Orbits, t0_y, dt, y, generation, order, channels, out_start, n_out,
+                out=None, stream=None):
+    """TDI channels out[3 or 6][n_out] at y-indices out_start .. out_start +
+    n_out - 1 (lr_tdi_combine).  ``channels`` is "XYZ", "AET" or "XYZAET"."""
+    import torch
+    if out is None:
+        rows = 6 if channels == "XYZAET" else 3
+        out = torch.empty((rows, n_out), dtype=torch.float64, device=y.device)
+    n_y = y.shape[-1]
+    _check(lib().lr_tdi_combine(orb.ref, float(t0_y), float(dt), n_y, _dev(y, "y"),
+                                int(generation), int(order), CHANNELS[channels], int(out_start),
+                                int(n_out), _dev(out, "out"), _stream(stream)), "lr_tdi_combine")
+    return out

@@ -1,0 +1,117 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+that include/*.h declares, and rejects bad arguments before any launch."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2204_06633_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(lr_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lr_orbits_init", "lr_project_links", "lr_tdi_combine"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(native.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    L = native.lib()
+    for s in range(6):
+        assert L.lr_status_str(s).startswith(b"LR_")
+    assert L.lr_abi_version() >= 1
+
+
+def _fake_orbits(n=20, dt=1e4, t0=0.0, lmin=8.0, lmax=8.7, rmax=1.6e11):
+    o = native.lr_orbits()
+    o.t0, o.dt, o.n = t0, dt, n
+    o.coef = ctypes.c_void_p(0x1000)          # never dereferenced on the host
+    o.L_min, o.L_max, o.R_max = lmin, lmax, rmax
+    return o
+
+
+def test_padding_rules():
+    L = native.lib()
+    o = _fake_orbits()
+    f, b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.lr_projection_padding(ctypes.byref(o), 25, 10.0, ctypes.byref(f), ctypes.byref(b)) == 0
+    rc = 1.6e11 / 299792458.0
+    assert f.value >= (8.7 + rc) / 10.0 + 12 and b.value >= rc / 10.0 + 13
+    assert L.lr_tdi_padding(ctypes.byref(o), 25, 2, 10.0, ctypes.byref(f), ctypes.byref(b)) == 0
+    assert f.value >= 7 * 8.7 / 10.0 + 12 and b.value >= 13
+    assert L.lr_tdi_padding(ctypes.byref(o), 25, 3, 10.0, ctypes.byref(f), ctypes.byref(b)) == 3
+    assert L.lr_tdi_padding(ctypes.byref(o), 24, 2, 10.0, ctypes.byref(f), ctypes.byref(b)) == 3
+
+
+@pytest.mark.parametrize("order,status", [(0, 3), (2, 3), (33, 3)])
+def test_bad_order_rejected_before_launch(order, status):
+    L = native.lib()
+    o = _fake_orbits()
+    p = ctypes.c_void_p(0x2000)
+    st = L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 1000, p, p, 0.1, 0.2, order, 100, 10,
+                            ctypes.c_void_p(0x9000000), None)
+    assert st == status
+    assert L.lr_last_error()
+
+
+def test_range_and_alias_rejected_before_launch():
+    L = native.lib()
+    o = _fake_orbits()
+    hp, hc = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
+    y = ctypes.c_void_p(0x300000)
+    # stencil would leave h at the front
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 3, 10, y,
+                              None) == 2
+    # output overlapping an input
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 10,
+                              hp, None) == 1
+    # orbit grid does not cover the sample times
+    assert L.lr_project_links(ctypes.byref(o), 1e7, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 10, y,
+                              None) == 2
+    # non-finite sky angle
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, float("nan"), 0.2, 25,
+                              200, 10, y, None) == 1
+    # TDI: unknown channels, generation; too little y before the outputs
+    assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 2, 25, 7, 100, 10, y, None) == 3
+    assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 3, 25, 0, 100, 10, y, None) == 3
+    assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 2, 25, 0, 5, 10, y, None) == 2
+    # empty requests are no-ops
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 0, y,
+                              None) == 0
+
+
+def test_orbits_init_rejects_bad_input_on_host():
+    import numpy as np
+    L = native.lib()
+    out = native.lr_orbits()
+    x = np.zeros((3, 3, 3))
+    lt = np.zeros((3, 6))
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.lr_orbits_init(0.0, 1e4, 3, x.ctypes.data, lt.ctypes.data, dummy, 10 ** 6,
+                            ctypes.byref(out), None) == 1
+    x = np.zeros((5, 3, 3))
+    lt = np.zeros((5, 6))
+    assert L.lr_orbits_init(0.0, 1e4, 5, x.ctypes.data, lt.ctypes.data, dummy, 8,
+                            ctypes.byref(out), None) == 4
+    x[2, 1, 1] = np.nan
+    assert L.lr_orbits_init(0.0, 1e4, 5, x.ctypes.data, lt.ctypes.data, dummy, 10 ** 6,
+                            ctypes.byref(out), None) == 1
