@@ -114,12 +114,12 @@ def main():
     y = torch.empty((6, g.n_y), dtype=torch.float64, device=dev)
     out = torch.empty((6, g.n_out), dtype=torch.float64, device=dev)
     t0_y = g.t0_h + g.y_start * g.dt
+    sky = torch.tensor([case.lam, case.beta], dtype=torch.float64, device=dev)
 
     def step(ev=None):
         if ev is not None:
             ev[0].record()
-        native.project_links(orb, g.t0_h, g.dt, hp, hc, case.lam, case.beta, case.order,
-                             g.y_start, g.n_y, y=y)
+        native.project_links(orb, g.t0_h, g.dt, hp, hc, sky, case.order, g.y_start, g.n_y, y=y)
         if ev is not None:
             ev[1].record()
         native.tdi_combine(orb, t0_y, g.dt, y, case.generation, case.order, case.channels,

@@ -111,13 +111,17 @@ int lr_tdi_padding(const lr_orbits *orb, int order, int generation, double dt, i
  * (lam, beta) (Sec. IV.A), n_ij = (x_i - x_j)/|x_i - x_j| and all orbit
  * quantities at the reception time t.
  *
- * hp, hc: [n_h] at t0_h + j*dt.  Writes y[l * n_y + i] for the link sample
- * at h-index y_start + i, i = 0..n_y-1.  Requires y_start - front >= 0 and
- * y_start + n_y - 1 + back <= n_h - 1 (lr_projection_padding), and the orbit
- * grid to cover the link sample times.  n_y = 0 is a no-op.
+ * hp, hc: [n_h] at t0_h + j*dt.  sky: device [2] = (lam, beta) in radians
+ * (device-resident so that a captured graph can be replayed with new
+ * angles).  Writes y[l * n_y + i] for the link sample at h-index
+ * y_start + i, i = 0..n_y-1.  Requires y_start - front >= 0 and
+ * y_start + n_y - 1 + back <= n_h - 1 (lr_projection_padding, valid for any
+ * sky position), and the orbit grid to cover the link sample times.
+ * n_y = 0 is a no-op.  Non-finite angles give non-finite y, never an
+ * out-of-bounds access.
  * ---------------------------------------------------------------------- */
 int lr_project_links(const lr_orbits *orb, double t0_h, double dt, int64_t n_h,
-                     const double *hp, const double *hc, double lam, double beta, int order,
+                     const double *hp, const double *hc, const double *sky, int order,
                      int64_t y_start, int64_t n_y, double *y, void *stream);
 
 /* ------------------------------------------------------------------------
@@ -136,6 +140,49 @@ int lr_project_links(const lr_orbits *orb, double t0_h, double dt, int64_t n_h,
 int lr_tdi_combine(const lr_orbits *orb, double t0_y, double dt, int64_t n_y, const double *y,
                    int generation, int order, int channels, int64_t out_start, int64_t n_out,
                    double *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoints.  Not in the paper; they are the exact transposes of the linear
+ * maps above (derived from Sec. IV.B-IV.C and the interpolation of
+ * Sec. IV.E), so that a likelihood gradient can flow from the TDI channels
+ * back to h+, hx and the sky angles.  Gradients are accumulated with FP64
+ * atomics: results are reproducible to rounding, not bit for bit.
+ * ---------------------------------------------------------------------- */
+
+/* g_y = T^T g_out: transpose of lr_tdi_combine with the same arguments.
+ * g_out: [3 or 6][n_out] laid out like `out`; g_y: [6][n_y], overwritten
+ * (entries no output depends on are zero). */
+int lr_tdi_adjoint(const lr_orbits *orb, double t0_y, double dt, int64_t n_y, int generation,
+                   int order, int channels, int64_t out_start, int64_t n_out,
+                   const double *g_out, double *g_y, void *stream);
+
+/* Bytes of device workspace lr_project_adjoint needs for the sky gradient. */
+size_t lr_project_adjoint_workspace(int64_t n_y);
+
+/* (g_hp, g_hc) = P^T g_y: transpose of lr_project_links with respect to h+
+ * and hx (same arguments), both [n_h] and overwritten.  If g_sky is not
+ * NULL it receives d<g_y, y>/d(lam, beta) (device [2]); that needs hp, hc
+ * and a device workspace of lr_project_adjoint_workspace(n_y) bytes (its
+ * partial sums are reduced in a fixed order).  hp and hc may be NULL when
+ * g_sky is NULL. */
+int lr_project_adjoint(const lr_orbits *orb, double t0_h, double dt, int64_t n_h,
+                       const double *hp, const double *hc, const double *sky, int order,
+                       int64_t y_start, int64_t n_y, const double *g_y, double *g_hp,
+                       double *g_hc, double *g_sky, void *work, size_t work_bytes,
+                       void *stream);
+
+/* ------------------------------------------------------------------------
+ * White-noise likelihood, Sec. II.A eq. (like) with the channel sum of
+ * Sec. IV.C, for noise of standard deviation sigma per sample and channel:
+ *   loglike = -1/2 sum_k (data_k - h_k)^2 / sigma^2,
+ *   g_h_k   = d loglike / d h_k = (data_k - h_k) / sigma^2.
+ * h, data, g_h: device [n] (any channel-major layout, e.g. [3][n_out]);
+ * loglike: device [1]; g_h may be NULL.  The sum runs over a fixed grid in a
+ * fixed order (deterministic).  work: lr_loglike_workspace() bytes.
+ * ---------------------------------------------------------------------- */
+size_t lr_loglike_workspace(void);
+int lr_loglike(const double *h, const double *data, int64_t n, double sigma, double *loglike,
+               double *g_h, void *work, size_t work_bytes, void *stream);
 
 #ifdef __cplusplus
 }

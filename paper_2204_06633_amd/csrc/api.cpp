@@ -115,6 +115,53 @@ int check_orbit_span(const lr_orbits* o, double t_off, double dt, int64_t j0, in
 
 }  // namespace
 
+extern "C" int lr_projection_padding(const lr_orbits*, int, double, int64_t*, int64_t*);
+extern "C" int lr_tdi_padding(const lr_orbits*, int, int, double, int64_t*, int64_t*);
+
+namespace {
+
+// Shared checks of the projection calls: sizes, padding and orbit coverage.
+int check_projection(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, int order,
+                     int64_t y_start, int64_t n_y) {
+  if (int st = check_orbits(orb)) return st;
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (n_y < 0 || n_h < 0 || y_start < 0) return fail(LR_E_ARG, "negative size or start");
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_h)) return fail(LR_E_ARG, "non-finite t0 or dt");
+  if (n_y == 0) return LR_OK;
+  if (n_y > ((int64_t)1 << 40) || n_h > ((int64_t)1 << 40)) return fail(LR_E_ARG, "size too large");
+  int64_t front, back;
+  if (int st = lr_projection_padding(orb, order, dt, &front, &back)) return st;
+  if (y_start - front < 0 || y_start + n_y - 1 + back > n_h - 1)
+    return fail(LR_E_RANGE, "h covers [0, %lld) but the link samples [%lld, %lld) need "
+                            "%lld before and %lld after", (long long)n_h, (long long)y_start,
+                (long long)(y_start + n_y), (long long)front, (long long)back);
+  return check_orbit_span(orb, t0_h - orb->t0, dt, y_start, y_start + n_y - 1);
+}
+
+// Shared checks of the TDI calls.
+int check_tdi(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, int generation,
+              int order, int channels, int64_t out_start, int64_t n_out) {
+  if (int st = check_orbits(orb)) return st;
+  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  if (generation != 1 && generation != 2)
+    return fail(LR_E_UNSUPPORTED, "generation %d (1 or 2)", generation);
+  if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
+    return fail(LR_E_UNSUPPORTED, "channels %d (LR_XYZ, LR_AET or LR_XYZ_AET)", channels);
+  if (n_out < 0 || n_y < 0 || out_start < 0) return fail(LR_E_ARG, "negative size or start");
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_y)) return fail(LR_E_ARG, "non-finite t0 or dt");
+  if (n_out == 0) return LR_OK;
+  if (n_out > ((int64_t)1 << 40) || n_y > ((int64_t)1 << 40)) return fail(LR_E_ARG, "size too large");
+  int64_t front, back;
+  if (int st = lr_tdi_padding(orb, order, generation, dt, &front, &back)) return st;
+  if (out_start - front < 0 || out_start + n_out - 1 + back > n_y - 1)
+    return fail(LR_E_RANGE, "y covers [0, %lld) but the outputs [%lld, %lld) need %lld "
+                            "before and %lld after", (long long)n_y, (long long)out_start,
+                (long long)(out_start + n_out), (long long)front, (long long)back);
+  return check_orbit_span(orb, t0_y - orb->t0, dt, out_start, out_start + n_out - 1);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lr_status_str(int s) {
@@ -226,27 +273,16 @@ int lr_tdi_padding(const lr_orbits* orb, int order, int generation, double dt, i
 }
 
 int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, const double* hp,
-                     const double* hc, double lam, double beta, int order, int64_t y_start,
+                     const double* hc, const double* sky, int order, int64_t y_start,
                      int64_t n_y, double* y, void* stream) {
-  if (int st = check_orbits(orb)) return st;
-  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
-  if (n_y < 0 || n_h < 0 || y_start < 0) return fail(LR_E_ARG, "negative size or start");
-  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_h) || !is_finite(lam) || !is_finite(beta))
-    return fail(LR_E_ARG, "non-finite time, dt or sky angle");
+  if (int st = check_projection(orb, t0_h, dt, n_h, order, y_start, n_y)) return st;
   if (n_y == 0) return LR_OK;
-  if (!hp || !hc || !y) return fail(LR_E_ARG, "null pointer");
-  if (n_y > ((int64_t)1 << 40)) return fail(LR_E_ARG, "n_y too large");
-  if (overlap(y, 6 * n_y * sizeof(double), hp, n_h * sizeof(double)) ||
-      overlap(y, 6 * n_y * sizeof(double), hc, n_h * sizeof(double)))
-    return fail(LR_E_ARG, "y overlaps h+ or hx");
-  int64_t front, back;
-  if (int st = lr_projection_padding(orb, order, dt, &front, &back)) return st;
-  if (y_start - front < 0 || y_start + n_y - 1 + back > n_h - 1)
-    return fail(LR_E_RANGE, "h covers [0, %lld) but the link samples [%lld, %lld) need "
-                            "%lld before and %lld after", (long long)n_h, (long long)y_start,
-                (long long)(y_start + n_y), (long long)front, (long long)back);
+  if (!hp || !hc || !y || !sky) return fail(LR_E_ARG, "null pointer");
+  const size_t ybytes = 6 * (size_t)n_y * sizeof(double), hbytes = (size_t)n_h * sizeof(double);
+  if (overlap(y, ybytes, hp, hbytes) || overlap(y, ybytes, hc, hbytes) ||
+      overlap(y, ybytes, sky, 2 * sizeof(double)))
+    return fail(LR_E_ARG, "y overlaps an input");
   const double t_off = t0_h - orb->t0;
-  if (int st = check_orbit_span(orb, t_off, dt, y_start, y_start + n_y - 1)) return st;
 
   lr::ProjArgs a;
   a.orb = view_of(orb);
@@ -256,7 +292,7 @@ int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, 
   a.t_off = t_off;
   a.dt = dt;
   a.inv_dt = 1.0 / dt;
-  a.sky = lr::sky_basis(lam, beta);
+  a.sky = sky;
   a.y_start = y_start;
   a.n_y = n_y;
   a.y = y;
@@ -268,28 +304,14 @@ int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, 
 int lr_tdi_combine(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, const double* y,
                    int generation, int order, int channels, int64_t out_start, int64_t n_out,
                    double* out, void* stream) {
-  if (int st = check_orbits(orb)) return st;
-  if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
-  if (generation != 1 && generation != 2)
-    return fail(LR_E_UNSUPPORTED, "generation %d (1 or 2)", generation);
-  if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
-    return fail(LR_E_UNSUPPORTED, "channels %d (LR_XYZ, LR_AET or LR_XYZ_AET)", channels);
-  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
-  if (n_out < 0 || n_y < 0 || out_start < 0) return fail(LR_E_ARG, "negative size or start");
-  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0_y)) return fail(LR_E_ARG, "non-finite t0 or dt");
+  if (int st = check_tdi(orb, t0_y, dt, n_y, generation, order, channels, out_start, n_out))
+    return st;
   if (n_out == 0) return LR_OK;
   if (!y || !out) return fail(LR_E_ARG, "null pointer");
-  if (n_out > ((int64_t)1 << 40)) return fail(LR_E_ARG, "n_out too large");
+  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
   if (overlap(out, rows * n_out * sizeof(double), y, 6 * n_y * sizeof(double)))
     return fail(LR_E_ARG, "out overlaps y");
-  int64_t front, back;
-  if (int st = lr_tdi_padding(orb, order, generation, dt, &front, &back)) return st;
-  if (out_start - front < 0 || out_start + n_out - 1 + back > n_y - 1)
-    return fail(LR_E_RANGE, "y covers [0, %lld) but the outputs [%lld, %lld) need %lld "
-                            "before and %lld after", (long long)n_y, (long long)out_start,
-                (long long)(out_start + n_out), (long long)front, (long long)back);
   const double t_off = t0_y - orb->t0;
-  if (int st = check_orbit_span(orb, t_off, dt, out_start, out_start + n_out - 1)) return st;
 
   lr::TdiArgs a;
   a.orb = view_of(orb);
@@ -304,6 +326,115 @@ int lr_tdi_combine(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, co
   a.out = out;
   hipError_t e = lr::run_tdi(order, generation, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "lr_tdi_combine launch");
+  return LR_OK;
+}
+
+int lr_tdi_adjoint(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, int generation,
+                   int order, int channels, int64_t out_start, int64_t n_out,
+                   const double* g_out, double* g_y, void* stream) {
+  if (int st = check_tdi(orb, t0_y, dt, n_y, generation, order, channels, out_start, n_out))
+    return st;
+  if (n_y == 0) return LR_OK;
+  if (!g_y || (n_out > 0 && !g_out)) return fail(LR_E_ARG, "null pointer");
+  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
+  if (overlap(g_y, 6 * n_y * sizeof(double), g_out, rows * n_out * sizeof(double)))
+    return fail(LR_E_ARG, "g_y overlaps g_out");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_fill_zero(g_y, 6 * n_y, s);
+  if (e != hipSuccess) return hip_fail(e, "lr_tdi_adjoint fill");
+  if (n_out == 0) return LR_OK;
+  lr::TdiAdjArgs a;
+  a.orb = view_of(orb);
+  a.g_out = g_out;
+  a.channels = channels;
+  a.n_y = n_y;
+  a.t_off = t0_y - orb->t0;
+  a.dt = dt;
+  a.inv_dt = 1.0 / dt;
+  a.out_start = out_start;
+  a.n_out = n_out;
+  a.g_y = g_y;
+  e = lr::run_tdi_adjoint(order, generation, a, s);
+  if (e != hipSuccess) return hip_fail(e, "lr_tdi_adjoint launch");
+  return LR_OK;
+}
+
+size_t lr_project_adjoint_workspace(int64_t n_y) {
+  if (n_y <= 0) return 0;
+  return (size_t)((n_y + lr::kTile - 1) / lr::kTile) * 2 * sizeof(double);
+}
+
+int lr_project_adjoint(const lr_orbits* orb, double t0_h, double dt, int64_t n_h,
+                       const double* hp, const double* hc, const double* sky, int order,
+                       int64_t y_start, int64_t n_y, const double* g_y, double* g_hp,
+                       double* g_hc, double* g_sky, void* work, size_t work_bytes,
+                       void* stream) {
+  if (int st = check_projection(orb, t0_h, dt, n_h, order, y_start, n_y)) return st;
+  if (!g_hp || !g_hc || !sky || (n_y > 0 && !g_y)) return fail(LR_E_ARG, "null pointer");
+  if (g_sky && (!hp || !hc)) return fail(LR_E_ARG, "the sky gradient needs h+ and hx");
+  const size_t hbytes = (size_t)n_h * sizeof(double), ybytes = 6 * (size_t)n_y * sizeof(double);
+  if (overlap(g_hp, hbytes, g_hc, hbytes) || overlap(g_hp, hbytes, g_y, ybytes) ||
+      overlap(g_hc, hbytes, g_y, ybytes) || overlap(g_hp, hbytes, hp, hbytes) ||
+      overlap(g_hp, hbytes, hc, hbytes) || overlap(g_hc, hbytes, hp, hbytes) ||
+      overlap(g_hc, hbytes, hc, hbytes))
+    return fail(LR_E_ARG, "an output overlaps an input or the other output");
+  if (g_sky) {
+    if (work_bytes < lr_project_adjoint_workspace(n_y) || (n_y > 0 && !work))
+      return fail(LR_E_WORKSPACE, "workspace %zu bytes < %zu", work_bytes,
+                  lr_project_adjoint_workspace(n_y));
+    if (overlap(g_sky, 2 * sizeof(double), work, work_bytes) ||
+        overlap(g_sky, 2 * sizeof(double), g_hp, hbytes) ||
+        overlap(g_sky, 2 * sizeof(double), g_hc, hbytes))
+      return fail(LR_E_ARG, "g_sky overlaps the workspace or g_h");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_fill_zero(g_hp, n_h, s);
+  if (e == hipSuccess) e = lr::run_fill_zero(g_hc, n_h, s);
+  if (e == hipSuccess && g_sky && n_y == 0) e = lr::run_fill_zero(g_sky, 2, s);
+  if (e != hipSuccess) return hip_fail(e, "lr_project_adjoint fill");
+  if (n_y == 0) return LR_OK;
+  lr::ProjAdjArgs a;
+  a.orb = view_of(orb);
+  a.hp = hp;
+  a.hc = hc;
+  a.n_h = n_h;
+  a.t_off = t0_h - orb->t0;
+  a.dt = dt;
+  a.inv_dt = 1.0 / dt;
+  a.sky = sky;
+  a.y_start = y_start;
+  a.n_y = n_y;
+  a.g_y = g_y;
+  a.g_hp = g_hp;
+  a.g_hc = g_hc;
+  a.sky_part = g_sky ? static_cast<double*>(work) : nullptr;
+  e = lr::run_project_adjoint(order, a, s);
+  if (e == hipSuccess && g_sky)
+    e = lr::run_sky_finalize(a.sky_part, (n_y + lr::kTile - 1) / lr::kTile, g_sky, s);
+  if (e != hipSuccess) return hip_fail(e, "lr_project_adjoint launch");
+  return LR_OK;
+}
+
+size_t lr_loglike_workspace(void) { return lr::loglike_workspace_bytes(); }
+
+int lr_loglike(const double* h, const double* data, int64_t n, double sigma, double* loglike,
+               double* g_h, void* work, size_t work_bytes, void* stream) {
+  if (n < 0) return fail(LR_E_ARG, "negative size");
+  if (!(sigma > 0.0) || !is_finite(sigma)) return fail(LR_E_ARG, "sigma must be positive");
+  if (!loglike || !work || (n > 0 && (!h || !data))) return fail(LR_E_ARG, "null pointer");
+  if (work_bytes < lr::loglike_workspace_bytes())
+    return fail(LR_E_WORKSPACE, "workspace %zu bytes < %zu", work_bytes,
+                lr::loglike_workspace_bytes());
+  const size_t nb = (size_t)n * sizeof(double);
+  if (g_h && (overlap(g_h, nb, h, nb) || overlap(g_h, nb, data, nb) ||
+              overlap(g_h, nb, work, work_bytes) || overlap(g_h, nb, loglike, sizeof(double))))
+    return fail(LR_E_ARG, "g_h overlaps an input, the workspace or loglike");
+  if (overlap(loglike, sizeof(double), work, work_bytes))
+    return fail(LR_E_ARG, "loglike overlaps the workspace");
+  hipError_t e = lr::run_loglike(h, data, n, 1.0 / (sigma * sigma), g_h,
+                                 static_cast<double*>(work), loglike,
+                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lr_loglike launch");
   return LR_OK;
 }
 

@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 TARGET = os.path.join(PKG, "_lisaresp.so")
-SOURCES = ["forward_a.hip", "forward_b.hip", "forward_c.hip", "forward_d.hip", "dispatch.cpp",
-           "api.cpp"]
+SOURCES = ["forward_%s.hip" % k for k in "abcd"] + ["adjoint_%s.hip" % k for k in "abcd"] + \
+    ["util.hip", "dispatch.cpp", "api.cpp"]
 ARCH = os.environ.get("LR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -46,14 +46,85 @@ struct Sky {
   double k[3], u[3], v[3];
 };
 
-// k = -e_r, u = -e_phi, v = -e_theta for ecliptic longitude lam, latitude beta.
-__host__ __device__ inline Sky sky_basis(double lam, double beta) {
-  double cb = cos(beta), sb = sin(beta), cl = cos(lam), sl = sin(lam);
+// k = -e_r, u = -e_phi, v = -e_theta for ecliptic longitude lam, latitude beta
+// (Sec. IV.A), from sl = sin(lam), cl = cos(lam), sb = sin(beta), cb = cos(beta).
+__host__ __device__ inline Sky sky_from_trig(double sl, double cl, double sb, double cb) {
   Sky s;
   s.k[0] = -cb * cl; s.k[1] = -cb * sl; s.k[2] = -sb;
   s.u[0] = sl;       s.u[1] = -cl;      s.u[2] = 0.0;
   s.v[0] = -sb * cl; s.v[1] = -sb * sl; s.v[2] = cb;
   return s;
+}
+
+__host__ __device__ inline Sky sky_basis(double lam, double beta) {
+  return sky_from_trig(sin(lam), cos(lam), sin(beta), cos(beta));
+}
+
+// Derivatives of (k, u, v) with respect to lam and beta.
+struct SkyDeriv {
+  double dk[2][3], du[2][3], dv[2][3];   // [lam, beta][xyz]
+};
+
+__host__ __device__ inline SkyDeriv sky_derivatives(double sl, double cl, double sb, double cb) {
+  SkyDeriv d;
+  d.dk[0][0] = cb * sl;  d.dk[0][1] = -cb * cl; d.dk[0][2] = 0.0;
+  d.dk[1][0] = sb * cl;  d.dk[1][1] = sb * sl;  d.dk[1][2] = -cb;
+  d.du[0][0] = cl;       d.du[0][1] = sl;       d.du[0][2] = 0.0;
+  d.du[1][0] = 0.0;      d.du[1][1] = 0.0;      d.du[1][2] = 0.0;
+  d.dv[0][0] = sb * sl;  d.dv[0][1] = -sb * cl; d.dv[0][2] = 0.0;
+  d.dv[1][0] = -cb * cl; d.dv[1][1] = -cb * sl; d.dv[1][2] = -sb;
+  return d;
+}
+
+// Per-sample constellation geometry at a reception time (Sec. IV.B):
+// light times, k.x/c per spacecraft, antenna patterns and k.n per arm.
+// Arms 0, 1, 2 are n12, n23, n31; link l uses arm kArm[l] with direction
+// kDir[l] (n_ji = -n_ij, so xi is shared and k.n flips sign).
+constexpr int kArm[6] = {0, 1, 2, 2, 1, 0};
+constexpr double kDir[6] = {1.0, 1.0, 1.0, -1.0, -1.0, -1.0};
+
+struct LinkGeom {
+  double x[3][3];       // spacecraft positions (m)
+  double L[6];          // light times (s)
+  double kx[3];         // k.x_s / c (s)
+  double n[3][3];       // unit arm vectors n12, n23, n31
+  double un[3], vn[3];  // u.n, v.n per arm
+  double xip[3], xic[3], kn[3];
+};
+
+__device__ __forceinline__ void link_geometry(const double* seg, double u, const Sky& sk,
+                                              LinkGeom& g) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g.x[s][c] = spline_at(seg, 3 * s + c, u);
+#pragma unroll
+  for (int l = 0; l < 6; ++l) g.L[l] = spline_at(seg, 9 + l, u);
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    g.kx[s] = (sk.k[0] * g.x[s][0] + sk.k[1] * g.x[s][1] + sk.k[2] * g.x[s][2]) / kC;
+#pragma unroll
+  for (int arm = 0; arm < 3; ++arm) {
+    const int r = arm, e = (arm + 1) % 3;
+    double d0 = g.x[r][0] - g.x[e][0], d1 = g.x[r][1] - g.x[e][1], d2 = g.x[r][2] - g.x[e][2];
+    double nrm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    d0 /= nrm; d1 /= nrm; d2 /= nrm;
+    g.n[arm][0] = d0; g.n[arm][1] = d1; g.n[arm][2] = d2;
+    double un = sk.u[0] * d0 + sk.u[1] * d1 + sk.u[2] * d2;
+    double vn = sk.v[0] * d0 + sk.v[1] * d1 + sk.v[2] * d2;
+    g.un[arm] = un;
+    g.vn[arm] = vn;
+    g.xip[arm] = un * un - vn * vn;
+    g.xic[arm] = 2.0 * un * vn;
+    g.kn[arm] = sk.k[0] * d0 + sk.k[1] * d1 + sk.k[2] * d2;
+  }
+}
+
+// Retarded delays (s) of the nine interpolation positions of one link
+// sample: 0..2 reception at spacecraft 1..3 (shared by the two links received
+// there), 3..8 emission of links 0..5.
+__device__ __forceinline__ double position_delay(const LinkGeom& g, int p) {
+  return p < 3 ? g.kx[p] : g.L[p - 3] + g.kx[kLinkEmit[p - 3] - 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -99,13 +170,40 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N]) {
 
 // Split the retarded position q - d/dt into an integer shift (so that
 // j0 = q + shift) and eps in [0, 1), with d a delay in seconds.  The shift is
-// clamped to +-2^30 so that non-finite delays stay in integer range.
+// clamped to +-2^24 so that non-finite delays keep every index computation in
+// int32 range (such samples then take the clamped global-memory path).
 __device__ __forceinline__ int split_delay(double d, double inv_dt, double& eps) {
   double a = -d * inv_dt;
   double f = floor(a);
-  f = fmin(fmax(f, -1073741824.0), 1073741824.0);
+  f = fmin(fmax(f, -16777216.0), 16777216.0);
   eps = a - f;
   return (int)f;
+}
+
+// Derivative weights dw_m/deps of the same Lagrange basis (product rule on
+// the prefix and suffix products).
+template <int N>
+__device__ __forceinline__ void lagrange_weights_d(double eps, double (&w)[N], double (&dw)[N]) {
+  constexpr LagrangeDenoms<N> C = make_denoms<N>();
+  constexpr int H = N / 2;
+  double pre = 1.0, dpre = 0.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    w[m] = pre;
+    dw[m] = dpre;
+    const double d = eps - (double)(m - (H - 1));
+    dpre = fma(dpre, d, pre);
+    pre *= d;
+  }
+  double suf = 1.0, dsuf = 0.0;
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    dw[m] = C.c[m] * fma(dw[m], suf, w[m] * dsuf);
+    w[m] *= suf * C.c[m];
+    const double d = eps - (double)(m - (H - 1));
+    dsuf = fma(dsuf, d, suf);
+    suf *= d;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -25,4 +25,22 @@ hipError_t run_tdi(int order, int gen, const TdiArgs& a, hipStream_t s) {
   }
 }
 
+hipError_t run_tdi_adjoint(int order, int gen, const TdiAdjArgs& a, hipStream_t s) {
+  switch (order) {
+#define X(ORD, NT) case ORD: return launch_tdi_adjoint<NT>(a, gen, s);
+    LR_ORDER_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s) {
+  switch (order) {
+#define X(ORD, NT) case ORD: return launch_project_adjoint<NT>(a, s);
+    LR_ORDER_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace lr

@@ -18,8 +18,45 @@
 
 namespace lr {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kTile;   // output samples per workgroup
 constexpr int kSlack = 64;   // window samples beyond kBlock + taps
+
+// ---------------------------------------------------------------------------
+// Shared tile machinery
+// ---------------------------------------------------------------------------
+
+// Sky basis from the device angles [lam, beta]: two lanes evaluate the
+// trigonometric functions, the workgroup shares them through LDS.
+struct SkyTrig {
+  double sl, cl, sb, cb;
+};
+
+__device__ __forceinline__ SkyTrig load_sky(const double* sky, double (&s_trig)[2][2]) {
+  const int tid = threadIdx.x;
+  if (tid < 2) {
+    double sn, cs;
+    sincos(sky[tid], &sn, &cs);
+    s_trig[tid][0] = sn;
+    s_trig[tid][1] = cs;
+  }
+  __syncthreads();
+  return SkyTrig{s_trig[0][0], s_trig[0][1], s_trig[1][0], s_trig[1][1]};
+}
+
+// Workgroup-wide [min(lo), max(hi)] of per-lane int ranges.
+template <int BLOCK>
+__device__ __forceinline__ void block_range(int lo, int hi, int (&red)[2][BLOCK / 64], int& wlo,
+                                            int& whi) {
+  const int tid = threadIdx.x;
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((tid & 63) == 0) { red[0][tid >> 6] = lo; red[1][tid >> 6] = hi; }
+  __syncthreads();
+  wlo = red[0][0];
+  whi = red[1][0];
+#pragma unroll
+  for (int w = 1; w < BLOCK / 64; ++w) { wlo = min(wlo, red[0][w]); whi = max(whi, red[1][w]); }
+}
 
 // ---------------------------------------------------------------------------
 // Projection
@@ -30,6 +67,7 @@ __global__ __launch_bounds__(kBlock) void project_links_kernel(ProjArgs a) {
   constexpr int CAP = kBlock + N + kSlack;
   __shared__ double2 win[CAP];
   __shared__ int red[2][kBlock / 64];
+  __shared__ double s_trig[2][2];
 
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * kBlock;
@@ -38,63 +76,28 @@ __global__ __launch_bounds__(kBlock) void project_links_kernel(ProjArgs a) {
   const int rel = active ? tid : (int)(a.n_y - 1 - i0);   // idle lanes mirror the last sample
   const int64_t q = a.y_start + i0 + rel;
 
-  // Orbit state at the reception time t_q.
+  const SkyTrig tr = load_sky(a.sky, s_trig);
+  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
   double u;
   const double* seg = orbit_segment(a.orb, a.t_off + (double)q * a.dt, u);
-  double x[3][3], L[6];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[s][c] = spline_at(seg, 3 * s + c, u);
-#pragma unroll
-  for (int l = 0; l < 6; ++l) L[l] = spline_at(seg, 9 + l, u);
+  LinkGeom g;
+  link_geometry(seg, u, sk, g);
 
-  const Sky& sk = a.sky;
-  double kx[3];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-    kx[s] = (sk.k[0] * x[s][0] + sk.k[1] * x[s][1] + sk.k[2] * x[s][2]) / kC;
-
-  // Arms 0,1,2 = n12, n23, n31; n_ji = -n_ij so xi is shared, k.n flips sign.
-  double xip[3], xic[3], kn[3];
-#pragma unroll
-  for (int arm = 0; arm < 3; ++arm) {
-    const int r = arm, e = (arm + 1) % 3;
-    double d0 = x[r][0] - x[e][0], d1 = x[r][1] - x[e][1], d2 = x[r][2] - x[e][2];
-    double nrm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    d0 /= nrm; d1 /= nrm; d2 /= nrm;
-    double un = sk.u[0] * d0 + sk.u[1] * d1 + sk.u[2] * d2;
-    double vn = sk.v[0] * d0 + sk.v[1] * d1 + sk.v[2] * d2;
-    xip[arm] = un * un - vn * vn;
-    xic[arm] = 2.0 * un * vn;
-    kn[arm] = sk.k[0] * d0 + sk.k[1] * d1 + sk.k[2] * d2;
-  }
-
-  // Nine retarded positions: 0..2 reception at spacecraft 1..3 (shared by
-  // the two links received there), 3..8 emission of links 0..5.
   int sh[9];
   double ep[9];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) sh[s] = split_delay(kx[s], a.inv_dt, ep[s]);
-#pragma unroll
-  for (int l = 0; l < 6; ++l) sh[3 + l] = split_delay(L[l] + kx[kLinkEmit[l] - 1], a.inv_dt, ep[3 + l]);
-
+  for (int p = 0; p < 9; ++p) sh[p] = split_delay(position_delay(g, p), a.inv_dt, ep[p]);
   int lo = sh[0], hi = sh[0];
 #pragma unroll
   for (int p = 1; p < 9; ++p) { lo = min(lo, sh[p]); hi = max(hi, sh[p]); }
-  lo = wave_min(rel + lo - (H - 1));
-  hi = wave_max(rel + hi + H);
-  if ((tid & 63) == 0) { red[0][tid >> 6] = lo; red[1][tid >> 6] = hi; }
-  __syncthreads();
-  int wlo = red[0][0], whi = red[1][0];
-#pragma unroll
-  for (int w = 1; w < kBlock / 64; ++w) { wlo = min(wlo, red[0][w]); whi = max(whi, red[1][w]); }
+  int wlo, whi;
+  block_range<kBlock>(rel + lo - (H - 1), rel + hi + H, red, wlo, whi);
   const int count = whi - wlo + 1;
   const int64_t base = a.y_start + i0 + wlo;     // h-index of win[0]
   const int64_t hmax = a.n_h - 1;
 
   double hv[2][9];
-  if (count <= CAP) {
+  if (count > 0 && count <= CAP) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > hmax ? hmax : j);
@@ -138,14 +141,12 @@ __global__ __launch_bounds__(kBlock) void project_links_kernel(ProjArgs a) {
   }
 
   if (!active) return;
-  constexpr int kArm[6] = {0, 1, 2, 2, 1, 0};
-  constexpr double kDir[6] = {1.0, 1.0, 1.0, -1.0, -1.0, -1.0};
 #pragma unroll
   for (int l = 0; l < 6; ++l) {
     const int arm = kArm[l];
     const int pr = kLinkRecv[l] - 1, pe = 3 + l;
-    double num = xip[arm] * (hv[0][pe] - hv[0][pr]) + xic[arm] * (hv[1][pe] - hv[1][pr]);
-    a.y[(int64_t)l * a.n_y + i] = num / (2.0 * (1.0 - kDir[l] * kn[arm]));
+    double num = g.xip[arm] * (hv[0][pe] - hv[0][pr]) + g.xic[arm] * (hv[1][pe] - hv[1][pr]);
+    a.y[(int64_t)l * a.n_y + i] = num / (2.0 * (1.0 - kDir[l] * g.kn[arm]));
   }
 }
 
@@ -265,20 +266,15 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
   double e_unused;
   int lo = min(0, split_delay(dmax, a.inv_dt, e_unused) - (H - 1));
   int hi = max(0, split_delay(dmin, a.inv_dt, e_unused) + H);
-  lo = wave_min(rel + lo);
-  hi = wave_max(rel + hi);
-  if ((tid & 63) == 0) { red[0][tid >> 6] = lo; red[1][tid >> 6] = hi; }
-  __syncthreads();
-  int wlo = red[0][0], whi = red[1][0];
-#pragma unroll
-  for (int w = 1; w < kBlock / 64; ++w) { wlo = min(wlo, red[0][w]); whi = max(whi, red[1][w]); }
+  int wlo, whi;
+  block_range<kBlock>(rel + lo, rel + hi, red, wlo, whi);
   const int count = whi - wlo + 1;
   const int64_t base = a.out_start + i0 + wlo;
   const int64_t ymax = a.n_y - 1;
   const int c0 = rel - wlo;
 
   double acc[3] = {0.0, 0.0, 0.0};
-  if (count <= CAP) {
+  if (count > 0 && count <= CAP) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > ymax ? ymax : j);

@@ -15,7 +15,7 @@ struct ProjArgs {
   int64_t n_h;
   double t_off;      // t0_h - (time of coarse orbit sample 0)
   double dt, inv_dt;
-  Sky sky;
+  const double* sky; // device [lam, beta]
   int64_t y_start, n_y;
   double* y;         // [6][n_y]
 };
@@ -31,11 +31,53 @@ struct TdiArgs {
   double* out;       // [3 or 6][n_out]
 };
 
+struct TdiAdjArgs {
+  OrbitView orb;
+  const double* g_out;  // [3 or 6][n_out]
+  int channels;
+  int64_t n_y;
+  double t_off;         // t0_y - (time of coarse orbit sample 0)
+  double dt, inv_dt;
+  int64_t out_start, n_out;
+  double* g_y;          // [6][n_y], zero-filled before the launch
+};
+
+struct ProjAdjArgs {
+  OrbitView orb;
+  const double* hp;     // needed for the sky gradient only
+  const double* hc;
+  int64_t n_h;
+  double t_off;
+  double dt, inv_dt;
+  const double* sky;    // device [lam, beta]
+  int64_t y_start, n_y;
+  const double* g_y;    // [6][n_y]
+  double* g_hp;         // [n_h], zero-filled before the launch
+  double* g_hc;
+  double* sky_part;     // [blocks][2] partial sky gradients, or null
+};
+
 // Per-tap-count launchers (N = order + 1), instantiated in forward_*.hip.
 template <int N>
 hipError_t launch_project(const ProjArgs& a, hipStream_t s);
 template <int N>
 hipError_t launch_tdi(const TdiArgs& a, int gen, hipStream_t s);
+
+template <int N>
+hipError_t launch_tdi_adjoint(const TdiAdjArgs& a, int gen, hipStream_t s);
+template <int N>
+hipError_t launch_project_adjoint(const ProjAdjArgs& a, hipStream_t s);
+
+// Workgroup size of the tiled kernels (output samples per workgroup).
+constexpr int kTile = 256;
+
+hipError_t run_fill_zero(double* p, int64_t n, hipStream_t s);
+hipError_t run_sky_finalize(const double* part, int64_t nblocks, double* g_sky, hipStream_t s);
+size_t loglike_workspace_bytes();
+hipError_t run_loglike(const double* h, const double* d, int64_t n, double inv_var, double* g,
+                       double* part, double* out, hipStream_t s);
+hipError_t run_tdi_adjoint(int order, int gen, const TdiAdjArgs& a, hipStream_t s);
+hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s);
 
 // Runtime dispatch on the interpolation order (odd 1..31).
 hipError_t run_project_links(int order, const ProjArgs& a, hipStream_t s);

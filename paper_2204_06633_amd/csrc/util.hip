@@ -1,0 +1,93 @@
+// Small helper kernels: zero fill (graph-safe replacement of memset nodes)
+// and the fixed-order reduction of per-workgroup sky-gradient partials.
+#include "internal.hpp"
+
+namespace lr {
+
+__global__ void fill_zero_kernel(double* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = 0.0;
+}
+
+// Sum the per-workgroup sky partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(256) void sky_finalize_kernel(const double* part, int64_t nblocks,
+                                                           double* g_sky) {
+  __shared__ double s[2][256];
+  const int tid = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t b = tid; b < nblocks; b += 256) { a0 += part[2 * b]; a1 += part[2 * b + 1]; }
+  s[0][tid] = a0;
+  s[1][tid] = a1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) { s[0][tid] += s[0][tid + w]; s[1][tid] += s[1][tid + w]; }
+    __syncthreads();
+  }
+  if (tid == 0) { g_sky[0] = s[0][0]; g_sky[1] = s[1][0]; }
+}
+
+// White-noise Gaussian log-likelihood pieces (Sec. II.A, eq. like, summed over
+// channels as in Sec. IV.C): per-workgroup partial sums of (d - h)^2 and,
+// optionally, the gradient (d - h)/sigma^2 with respect to h.  A fixed grid
+// and a fixed per-lane order keep the sum deterministic.
+constexpr int kLikeBlocks = 1024;
+
+__global__ __launch_bounds__(256) void loglike_kernel(const double* h, const double* d, int64_t n,
+                                                      double inv_var, double* g, double* part) {
+  __shared__ double s[256];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + tid; k < n; k += stride) {
+    const double r = d[k] - h[k];
+    acc = fma(r, r, acc);
+    if (g) g[k] = r * inv_var;
+  }
+  s[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) s[tid] += s[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void loglike_finalize_kernel(const double* part, int nblocks,
+                                                               double inv_var, double* out) {
+  __shared__ double s[256];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int b = tid; b < nblocks; b += 256) acc += part[b];
+  s[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) s[tid] += s[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = -0.5 * inv_var * s[0];
+}
+
+size_t loglike_workspace_bytes() { return kLikeBlocks * sizeof(double); }
+
+hipError_t run_loglike(const double* h, const double* d, int64_t n, double inv_var, double* g,
+                       double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(loglike_kernel, dim3(kLikeBlocks), dim3(256), 0, s, h, d, n, inv_var, g, part);
+  hipLaunchKernelGGL(loglike_finalize_kernel, dim3(1), dim3(256), 0, s, part, kLikeBlocks, inv_var,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t run_sky_finalize(const double* part, int64_t nblocks, double* g_sky, hipStream_t s) {
+  hipLaunchKernelGGL(sky_finalize_kernel, dim3(1), dim3(256), 0, s, part, nblocks, g_sky);
+  return hipGetLastError();
+}
+
+}  // namespace lr

@@ -60,10 +60,18 @@ def lib():
     L.lr_orbits_init.argtypes = [d, d, i64, vp, vp, vp, ctypes.c_size_t, po, vp]
     L.lr_projection_padding.argtypes = [po, i32, d, P(i64), P(i64)]
     L.lr_tdi_padding.argtypes = [po, i32, i32, d, P(i64), P(i64)]
-    L.lr_project_links.argtypes = [po, d, d, i64, vp, vp, d, d, i32, i64, i64, vp, vp]
+    L.lr_project_links.argtypes = [po, d, d, i64, vp, vp, vp, i32, i64, i64, vp, vp]
     L.lr_tdi_combine.argtypes = [po, d, d, i64, vp, i32, i32, i32, i64, i64, vp, vp]
+    L.lr_tdi_adjoint.argtypes = [po, d, d, i64, i32, i32, i32, i64, i64, vp, vp, vp]
+    L.lr_project_adjoint_workspace.restype = ctypes.c_size_t
+    L.lr_project_adjoint_workspace.argtypes = [i64]
+    L.lr_project_adjoint.argtypes = [po, d, d, i64, vp, vp, vp, i32, i64, i64, vp, vp, vp, vp,
+                                     vp, ctypes.c_size_t, vp]
+    L.lr_loglike_workspace.restype = ctypes.c_size_t
+    L.lr_loglike.argtypes = [vp, vp, i64, d, vp, vp, vp, ctypes.c_size_t, vp]
     for name in ("lr_orbits_init", "lr_projection_padding", "lr_tdi_padding",
-                 "lr_project_links", "lr_tdi_combine"):
+                 "lr_project_links", "lr_tdi_combine", "lr_tdi_adjoint", "lr_project_adjoint",
+                 "lr_loglike"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -139,17 +147,21 @@ class Orbits:
 # Plain per-template calls
 # ---------------------------------------------------------------------------
 
-def project_links(orb: Orbits, t0_h, dt, hp, hc, lam, beta, order, y_start, n_y, y=None,
+def _opt(t, name):
+    return ctypes.c_void_p(0) if t is None else _dev(t, name)
+
+
+def project_links(orb: Orbits, t0_h, dt, hp, hc, sky, order, y_start, n_y, y=None,
                   stream=None):
     """Link responses y[6][n_y] for the link samples at h-indices
-    y_start .. y_start + n_y - 1 (lr_project_links)."""
+    y_start .. y_start + n_y - 1 (lr_project_links).  ``sky`` is a device
+    tensor [lam, beta]."""
     import torch
     if y is None:
         y = torch.empty((6, n_y), dtype=torch.float64, device=hp.device)
     _check(lib().lr_project_links(orb.ref, float(t0_h), float(dt), hp.numel(), _dev(hp, "hp"),
-                                  _dev(hc, "hc"), float(lam), float(beta), int(order),
-                                  int(y_start), int(n_y), _dev(y, "y"), _stream(stream)),
-           "lr_project_links")
+                                  _dev(hc, "hc"), _dev(sky, "sky"), int(order), int(y_start),
+                                  int(n_y), _dev(y, "y"), _stream(stream)), "lr_project_links")
     return y
 
 
@@ -166,3 +178,68 @@ def tdi_combine(orb: Orbits, t0_y, dt, y, generation, order, channels, out_start
                                 int(generation), int(order), CHANNELS[channels], int(out_start),
                                 int(n_out), _dev(out, "out"), _stream(stream)), "lr_tdi_combine")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Adjoints and likelihood
+# ---------------------------------------------------------------------------
+
+def tdi_adjoint(orb: Orbits, t0_y, dt, n_y, generation, order, channels, out_start, g_out,
+                g_y=None, stream=None):
+    """g_y[6][n_y] = transpose of tdi_combine applied to g_out (lr_tdi_adjoint)."""
+    import torch
+    if g_y is None:
+        g_y = torch.empty((6, n_y), dtype=torch.float64, device=g_out.device)
+    n_out = g_out.shape[-1]
+    _check(lib().lr_tdi_adjoint(orb.ref, float(t0_y), float(dt), int(n_y), int(generation),
+                                int(order), CHANNELS[channels], int(out_start), int(n_out),
+                                _dev(g_out, "g_out"), _dev(g_y, "g_y"), _stream(stream)),
+           "lr_tdi_adjoint")
+    return g_y
+
+
+def project_adjoint(orb: Orbits, t0_h, dt, n_h, hp, hc, sky, order, y_start, g_y, want_sky=True,
+                    g_hp=None, g_hc=None, g_sky=None, work=None, stream=None):
+    """(g_hp, g_hc, g_sky) = transpose of project_links applied to g_y
+    (lr_project_adjoint); g_sky is None unless ``want_sky``."""
+    import torch
+    dev = g_y.device
+    n_y = g_y.shape[-1]
+    if g_hp is None:
+        g_hp = torch.empty(n_h, dtype=torch.float64, device=dev)
+    if g_hc is None:
+        g_hc = torch.empty(n_h, dtype=torch.float64, device=dev)
+    nbytes = 0
+    if want_sky:
+        if g_sky is None:
+            g_sky = torch.empty(2, dtype=torch.float64, device=dev)
+        nbytes = lib().lr_project_adjoint_workspace(n_y)
+        if work is None:
+            work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
+    else:
+        g_sky = None
+    _check(lib().lr_project_adjoint(orb.ref, float(t0_h), float(dt), int(n_h), _opt(hp, "hp"),
+                                    _opt(hc, "hc"), _dev(sky, "sky"), int(order), int(y_start),
+                                    int(n_y), _dev(g_y, "g_y"), _dev(g_hp, "g_hp"),
+                                    _dev(g_hc, "g_hc"), _opt(g_sky, "g_sky"),
+                                    _opt(work if want_sky else None, "work"),
+                                    work.numel() * 8 if want_sky else 0, _stream(stream)),
+           "lr_project_adjoint")
+    return g_hp, g_hc, g_sky
+
+
+def loglike(h, data, sigma, want_grad=True, out=None, g_h=None, work=None, stream=None):
+    """(loglike[1], g_h) of the white-noise likelihood (lr_loglike)."""
+    import torch
+    dev = h.device
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    if want_grad and g_h is None:
+        g_h = torch.empty_like(h)
+    nbytes = lib().lr_loglike_workspace()
+    if work is None:
+        work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    _check(lib().lr_loglike(_dev(h, "h"), _dev(data, "data"), h.numel(), float(sigma),
+                            _dev(out, "loglike"), _opt(g_h if want_grad else None, "g_h"),
+                            _dev(work, "work"), work.numel() * 8, _stream(stream)), "lr_loglike")
+    return out, (g_h if want_grad else None)

@@ -1,21 +1,93 @@
-"""Per-template forward response on the GPU: projection then TDI.
+"""Per-template response on the GPU and its autograd wrappers.
 
-Thin glue over the two C-ABI calls (lr_project_links, lr_tdi_combine); all
-arithmetic runs in the HIP kernels.  The index bookkeeping follows
-``inputs.TemplateGrid``: h on [0, n_h), links on [y_start, y_start + n_y),
-output on [out_start, out_start + n_out) of the same uniform grid.
+Thin glue over the C-ABI calls: lr_project_links then lr_tdi_combine forward,
+lr_tdi_adjoint then lr_project_adjoint backward, lr_loglike for the
+white-noise likelihood.  All arithmetic runs in the HIP kernels.  The index
+bookkeeping follows ``inputs.TemplateGrid``: h on [0, n_h), links on
+[y_start, y_start + n_y), output on [out_start, out_start + n_out) of the same
+uniform grid.
 """
 from __future__ import annotations
+
+import dataclasses
+
+import torch
 
 from . import native
 
 
-def plain_forward(orb_proj: native.Orbits, orb_tdi: native.Orbits, grid, hp, hc, lam, beta,
-                  order, generation, channels="XYZ", y=None, out=None, stream=None):
-    """Returns (out[3][n_out], y[6][n_y]) for one template."""
-    y = native.project_links(orb_proj, grid.t0_h, grid.dt, hp, hc, lam, beta, order,
-                             grid.y_start, grid.n_y, y=y, stream=stream)
-    t0_y = grid.t0_h + grid.y_start * grid.dt
-    out = native.tdi_combine(orb_tdi, t0_y, grid.dt, y, generation, order, channels,
-                             grid.front_tdi, grid.n_out, out=out, stream=stream)
+@dataclasses.dataclass
+class Template:
+    """Everything a response call needs besides h+, hx and the sky angles."""
+    orb_proj: native.Orbits
+    orb_tdi: native.Orbits
+    grid: object                 # inputs.TemplateGrid
+    order: int = 25
+    generation: int = 2
+    channels: str = "XYZ"
+
+    @property
+    def t0_y(self):
+        return self.grid.t0_h + self.grid.y_start * self.grid.dt
+
+
+def plain_forward(tpl: Template, hp, hc, sky, y=None, out=None, stream=None):
+    """Returns (out[3 or 6][n_out], y[6][n_y]) for one template."""
+    g = tpl.grid
+    y = native.project_links(tpl.orb_proj, g.t0_h, g.dt, hp, hc, sky, tpl.order, g.y_start,
+                             g.n_y, y=y, stream=stream)
+    out = native.tdi_combine(tpl.orb_tdi, tpl.t0_y, g.dt, y, tpl.generation, tpl.order,
+                             tpl.channels, g.front_tdi, g.n_out, out=out, stream=stream)
     return out, y
+
+
+def plain_adjoint(tpl: Template, hp, hc, sky, g_out, want_sky=True, stream=None):
+    """Transpose of ``plain_forward``: (g_hp, g_hc, g_sky)."""
+    g = tpl.grid
+    g_y = native.tdi_adjoint(tpl.orb_tdi, tpl.t0_y, g.dt, g.n_y, tpl.generation, tpl.order,
+                             tpl.channels, g.front_tdi, g_out, stream=stream)
+    return native.project_adjoint(tpl.orb_proj, g.t0_h, g.dt, g.n_h, hp, hc, sky, tpl.order,
+                                  g.y_start, g_y, want_sky=want_sky, stream=stream)
+
+
+class ResponseFn(torch.autograd.Function):
+    """out = R(h+, hx; lam, beta) with the hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, hp, hc, sky, tpl):
+        hp, hc, sky = hp.contiguous(), hc.contiguous(), sky.contiguous()
+        out, _ = plain_forward(tpl, hp, hc, sky)
+        ctx.save_for_backward(hp, hc, sky)
+        ctx.tpl = tpl
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out):
+        hp, hc, sky = ctx.saved_tensors
+        g_hp, g_hc, g_sky = plain_adjoint(ctx.tpl, hp, hc, sky, g_out.contiguous(),
+                                          want_sky=ctx.needs_input_grad[2])
+        return g_hp, g_hc, g_sky, None
+
+
+class LoglikeFn(torch.autograd.Function):
+    """-1/2 sum (data - h)^2 / sigma^2 with gradient (data - h)/sigma^2."""
+
+    @staticmethod
+    def forward(ctx, h, data, sigma):
+        ll, g = native.loglike(h.contiguous(), data.contiguous(), sigma,
+                               want_grad=ctx.needs_input_grad[0])
+        ctx.save_for_backward(g if g is not None else torch.empty(0, device=h.device))
+        return ll[0]
+
+    @staticmethod
+    def backward(ctx, g_ll):
+        (g,) = ctx.saved_tensors
+        return g * g_ll, None, None
+
+
+def response(tpl: Template, hp, hc, sky):
+    return ResponseFn.apply(hp, hc, sky, tpl)
+
+
+def loglike(h, data, sigma):
+    return LoglikeFn.apply(h, data, sigma)

@@ -67,7 +67,8 @@ def test_bad_order_rejected_before_launch(order, status):
     L = native.lib()
     o = _fake_orbits()
     p = ctypes.c_void_p(0x2000)
-    st = L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 1000, p, p, 0.1, 0.2, order, 100, 10,
+    sky = ctypes.c_void_p(0x3000)
+    st = L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 1000, p, p, sky, order, 100, 10,
                             ctypes.c_void_p(0x9000000), None)
     assert st == status
     assert L.lr_last_error()
@@ -78,25 +79,52 @@ def test_range_and_alias_rejected_before_launch():
     o = _fake_orbits()
     hp, hc = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000)
     y = ctypes.c_void_p(0x300000)
+    sky = ctypes.c_void_p(0x50000000)
     # stencil would leave h at the front
-    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 3, 10, y,
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, sky, 25, 3, 10, y,
                               None) == 2
     # output overlapping an input
-    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 10,
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, sky, 25, 200, 10,
                               hp, None) == 1
     # orbit grid does not cover the sample times
-    assert L.lr_project_links(ctypes.byref(o), 1e7, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 10, y,
+    assert L.lr_project_links(ctypes.byref(o), 1e7, 10.0, 5000, hp, hc, sky, 25, 200, 10, y,
                               None) == 2
-    # non-finite sky angle
-    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, float("nan"), 0.2, 25,
+    # non-finite dt, null sky
+    assert L.lr_project_links(ctypes.byref(o), 0.0, float("nan"), 5000, hp, hc, sky, 25,
                               200, 10, y, None) == 1
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, None, 25, 200, 10, y,
+                              None) == 1
     # TDI: unknown channels, generation; too little y before the outputs
     assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 2, 25, 7, 100, 10, y, None) == 3
     assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 3, 25, 0, 100, 10, y, None) == 3
     assert L.lr_tdi_combine(ctypes.byref(o), 0.0, 10.0, 500, hp, 2, 25, 0, 5, 10, y, None) == 2
     # empty requests are no-ops
-    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, 0.1, 0.2, 25, 200, 0, y,
+    assert L.lr_project_links(ctypes.byref(o), 0.0, 10.0, 5000, hp, hc, sky, 25, 200, 0, y,
                               None) == 0
+
+
+def test_adjoint_and_likelihood_checks_before_launch():
+    L = native.lib()
+    o = _fake_orbits()
+    a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    sky = ctypes.c_void_p(0x50000000)
+    # TDI adjoint: too little y before the outputs; bad generation
+    assert L.lr_tdi_adjoint(ctypes.byref(o), 0.0, 10.0, 500, 2, 25, 0, 5, 10, a, b, None) == 2
+    assert L.lr_tdi_adjoint(ctypes.byref(o), 0.0, 10.0, 500, 5, 25, 0, 100, 10, a, b, None) == 3
+    # projection adjoint: sky gradient without h or without workspace
+    assert L.lr_project_adjoint(ctypes.byref(o), 0.0, 10.0, 5000, None, None, sky, 25, 200, 10,
+                                a, b, c, ctypes.c_void_p(0x70000000), None, 0, None) == 1
+    assert L.lr_project_adjoint(ctypes.byref(o), 0.0, 10.0, 5000, a, b, sky, 25, 200, 10,
+                                c, ctypes.c_void_p(0x400000), ctypes.c_void_p(0x500000),
+                                ctypes.c_void_p(0x70000000), None, 0, None) == 4
+    # g_hp aliasing g_hc
+    assert L.lr_project_adjoint(ctypes.byref(o), 0.0, 10.0, 5000, None, None, sky, 25, 200, 10,
+                                c, a, a, None, None, 0, None) == 1
+    assert L.lr_project_adjoint_workspace(1000) >= 2 * 8 * 4
+    # likelihood: bad sigma, small workspace
+    nb = L.lr_loglike_workspace()
+    assert L.lr_loglike(a, b, 10, 0.0, c, None, ctypes.c_void_p(0x600000), nb, None) == 1
+    assert L.lr_loglike(a, b, 10, 1.0, c, None, ctypes.c_void_p(0x600000), 8, None) == 4
 
 
 def test_orbits_init_rejects_bad_input_on_host():

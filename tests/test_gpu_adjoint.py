@@ -1,0 +1,281 @@
+"""GPU adjoint, sky gradient and likelihood gradient against the CPU oracle.
+
+Bars: adjoint vs oracle transpose 1e-10 (relative L2); gradients vs central
+finite differences (Richardson-extrapolated) 1e-6 per parameter.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_06633_amd import inputs
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+TOL_ADJ = 1e-10
+TOL_FD = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _t(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _template(case):
+    from paper_2204_06633_amd import native, response
+    gp = native.Orbits.from_samples(case.orbits_proj)
+    gt = gp if case.orbits_tdi is case.orbits_proj else native.Orbits.from_samples(case.orbits_tdi)
+    return response.Template(gp, gt, case.grid, case.order, case.generation, case.channels)
+
+
+@pytest.mark.parametrize("gen,channels,order", [(1, "XYZ", 25), (2, "AET", 25), (2, "XYZAET", 7),
+                                                (2, "XYZ", 31)])
+def test_tdi_adjoint_matches_oracle(torch_cuda, gen, channels, order):
+    from paper_2204_06633_amd import native
+    torch = torch_cuda
+    rng = np.random.default_rng(31 + gen + order)
+    s = inputs.make_orbit_samples("keplerian", 3e6, 3e6 + 2e4)
+    gorb = native.Orbits.from_samples(s)
+    dt = 10.0
+    ft, bt = gorb.tdi_padding(order, gen, dt)
+    n_out = 913
+    n_y = ft + n_out + bt + 3
+    rows = 6 if channels == "XYZAET" else 3
+    g_out = rng.standard_normal((rows, n_out))
+    t0_y = 3e6 + 500.0
+    got = native.tdi_adjoint(gorb, t0_y, dt, n_y, gen, order, channels, ft + 1, _t(torch, g_out))
+    torch.cuda.synchronize()
+    g = g_out
+    if channels == "AET":
+        g = oracle.aet_transpose(g_out)
+    elif channels == "XYZAET":
+        g = g_out[:3] + oracle.aet_transpose(g_out[3:])
+    ref = oracle.tdi_adjoint(oracle.Orbits.from_samples(s), t0_y, dt, n_y, gen, order,
+                             np.arange(ft + 1, ft + 1 + n_out), g)
+    assert cases.rel_err(got.cpu().numpy(), ref) <= TOL_ADJ
+
+
+@pytest.mark.parametrize("order", [1, 9, 25])
+def test_project_adjoint_matches_oracle(torch_cuda, order):
+    from paper_2204_06633_amd import native
+    torch = torch_cuda
+    case = cases.make_case("padj", "keplerian", 1500, 10.0, order, 2, "XYZ", seed=40 + order)
+    g = case.grid
+    tpl = _template(case)
+    rng = np.random.default_rng(order)
+    g_y = rng.standard_normal((6, g.n_y))
+    sky = _t(torch, [case.lam, case.beta])
+    ghp, ghc, _ = native.project_adjoint(tpl.orb_proj, g.t0_h, g.dt, g.n_h, None, None, sky,
+                                         order, g.y_start, _t(torch, g_y), want_sky=False)
+    torch.cuda.synchronize()
+    rhp, rhc = oracle.project_adjoint(oracle.Orbits.from_samples(case.orbits_proj), g.t0_h, g.dt,
+                                      g.n_h, case.lam, case.beta, order,
+                                      np.arange(g.y_start, g.y_start + g.n_y), g_y)
+    assert cases.rel_err(np.stack([ghp.cpu().numpy(), ghc.cpu().numpy()]),
+                         np.stack([rhp, rhc])) <= TOL_ADJ
+
+
+def test_adjoint_brute_force_transpose(torch_cuda):
+    """Tiny grid: R built column by column from unit impulses (oracle), then
+    R^T g against the GPU adjoint."""
+    from paper_2204_06633_amd import response
+    torch = torch_cuda
+    case = cases.make_case("tiny", "keplerian", 12, 10.0, 5, 2, "XYZ", seed=3)
+    g = case.grid
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    cols = []
+    for pol in range(2):
+        for j in range(g.n_h):
+            e = np.zeros(g.n_h)
+            e[j] = 1.0
+            z = np.zeros(g.n_h)
+            args = (e, z) if pol == 0 else (z, e)
+            cols.append(oracle.response(orb, orb, g, *args, case.lam, case.beta, 5, 2).ravel())
+    R = np.stack(cols, axis=1)
+    gout = np.random.default_rng(2).standard_normal((3, g.n_out))
+    expect = R.T @ gout.ravel()
+    tpl = _template(case)
+    ghp, ghc, _ = response.plain_adjoint(tpl, None, None, _t(torch, [case.lam, case.beta]),
+                                         _t(torch, gout), want_sky=False)
+    got = np.concatenate([ghp.cpu().numpy(), ghc.cpu().numpy()])
+    assert np.linalg.norm(got - expect) <= TOL_ADJ * np.linalg.norm(expect)
+
+
+def test_dot_product_full_year(torch_cuda):
+    """<R h, g> = <h, R^T g> at the full 1-yr size (any-size property)."""
+    from paper_2204_06633_amd import response
+    torch = torch_cuda
+    case = cases.config_c2("XYZAET")
+    tpl = _template(case)
+    hp, hc = _t(torch, case.hp), _t(torch, case.hc)
+    sky = _t(torch, [case.lam, case.beta])
+    out, _ = response.plain_forward(tpl, hp, hc, sky)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    g = torch.randn(out.shape, dtype=torch.float64, device="cuda", generator=gen)
+    ghp, ghc, _ = response.plain_adjoint(tpl, hp, hc, sky, g, want_sky=False)
+    lhs = float(torch.sum(out * g))
+    rhs = float(torch.sum(ghp * hp) + torch.sum(ghc * hc))
+    scale = float(torch.linalg.norm(out) * torch.linalg.norm(g))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+def _fd_richardson(f, x0, step):
+    d1 = (f(x0 + step) - f(x0 - step)) / (2 * step)
+    d2 = (f(x0 + step / 2) - f(x0 - step / 2)) / step
+    return (4 * d2 - d1) / 3
+
+
+def test_sky_gradient_vs_oracle_finite_differences(torch_cuda):
+    from paper_2204_06633_amd import response
+    torch = torch_cuda
+    case = cases.make_case("skyfd", "keplerian", 3000, 10.0, 25, 2, "AET", seed=12)
+    g = case.grid
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    gout = np.random.default_rng(9).standard_normal((3, g.n_out))
+    tpl = _template(case)
+    _, _, gsky = response.plain_adjoint(tpl, _t(torch, case.hp), _t(torch, case.hc),
+                                        _t(torch, [case.lam, case.beta]), _t(torch, gout))
+    gsky = gsky.cpu().numpy()
+
+    def J(lam, beta):
+        out = oracle.response(orb, orb, g, case.hp, case.hc, lam, beta, 25, 2, "AET")
+        return math.fsum((out * gout).ravel().tolist())
+
+    fd_lam = _fd_richardson(lambda x: J(x, case.beta), case.lam, 1e-4)
+    fd_beta = _fd_richardson(lambda x: J(case.lam, x), case.beta, 1e-4)
+    assert abs(gsky[0] - fd_lam) <= TOL_FD * abs(fd_lam)
+    assert abs(gsky[1] - fd_beta) <= TOL_FD * abs(fd_beta)
+
+
+# ---------------------------------------------------------------------------
+# Likelihood gradient to the eight source parameters (Sec. II.A, Sec. III)
+# ---------------------------------------------------------------------------
+
+SIGMA = 1e-21
+
+
+def _likelihood_case(n_out, dt=10.0):
+    params = np.array(inputs.PAPER_FIG3_BINARY, dtype=np.float64)
+    case = cases.make_case("c4", "keplerian", n_out, dt, 25, 2, "AET", seed=4, params=params)
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    inj = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta, 25, 2, "AET")
+    noise = np.random.default_rng(40).standard_normal(inj.shape) * SIGMA
+    return case, orb, inj + noise
+
+
+def _fd_steps(T):
+    return np.array([1e-4 * 1e-22, 1e-3 / (2 * math.pi * T), 1e-3 / (math.pi * T * T), 1e-4,
+                     1e-4, 1e-4, 1e-5, 1e-5])
+
+
+def _gpu_loglike_grad(torch, case, data, theta):
+    from paper_2204_06633_amd import response, waveform
+    tpl = _template(case)
+    p = _t(torch, theta).requires_grad_(True)
+    t = _t(torch, case.grid.waveform_times())
+    hp, hc = waveform.gb_polarizations(p, t)
+    out = response.response(tpl, hp, hc, p[6:8])
+    ll = response.loglike(out, _t(torch, data), SIGMA)
+    ll.backward()
+    return float(ll.detach()), p.grad.cpu().numpy()
+
+
+def test_loglike_matches_oracle(torch_cuda):
+    from paper_2204_06633_amd import native, response
+    torch = torch_cuda
+    case, orb, data = _likelihood_case(4000)
+    theta = np.array(case.params)
+    theta[1] *= 1 + 1e-7
+    hp, hc = inputs.gb_polarizations(theta, case.grid.waveform_times())
+    h = oracle.response(orb, orb, case.grid, hp, hc, theta[6], theta[7], 25, 2, "AET")
+    ll, g = native.loglike(_t(torch, h), _t(torch, data), SIGMA)
+    ref = oracle.loglike(h, data, SIGMA)
+    assert abs(float(ll[0]) - ref) <= 1e-13 * abs(ref)
+    assert np.allclose(g.cpu().numpy(), (data - h) / SIGMA ** 2, rtol=1e-15, atol=0)
+
+
+def test_loglike_gradient_vs_oracle_finite_differences(torch_cuda):
+    """One day at 10 s: autograd through the torch waveform and the
+    hand-written adjoint, against central differences of the oracle's
+    log-likelihood (difference form, exactly rounded sums)."""
+    torch = torch_cuda
+    n_out = 8640
+    case, orb, data = _likelihood_case(n_out)
+    theta = np.array(case.params)
+    theta[0] *= 1.3
+    theta[1] *= 1 + 2e-7
+    theta[6] += 1e-3
+    theta[7] -= 1e-3
+    _, grad = _gpu_loglike_grad(torch, case, data, theta)
+    g = case.grid
+
+    def h_of(th):
+        hp, hc = inputs.gb_polarizations(th, g.waveform_times())
+        return oracle.response(orb, orb, g, hp, hc, th[6], th[7], 25, 2, "AET")
+
+    h0 = h_of(theta)
+    steps = _fd_steps(n_out * g.dt)
+    for k in range(8):
+        def f(x, k=k):
+            th = theta.copy()
+            th[k] = x
+            return oracle.loglike_difference(h_of(th), h0, data, SIGMA)
+        fd = _fd_richardson(f, theta[k], steps[k])
+        assert abs(grad[k] - fd) <= TOL_FD * abs(fd), (inputs.PARAM_NAMES[k], grad[k], fd)
+
+
+def test_loglike_gradient_full_year_self_consistent(torch_cuda):
+    """One year at 10 s (the full-size differentiation workload): the
+    autograd gradient against central differences of the GPU log-likelihood
+    (forward parity with the oracle is covered separately)."""
+    from paper_2204_06633_amd import response, waveform
+    torch = torch_cuda
+    n_out = int(round(inputs.YEAR / 10.0))
+    params = np.array(inputs.PAPER_FIG3_BINARY, dtype=np.float64)
+    case = cases.make_case("c4_year", "keplerian", n_out, 10.0, 25, 2, "AET", seed=4,
+                           params=params)
+    tpl = _template(case)
+    t = _t(torch, case.grid.waveform_times())
+
+    def out_of(th):
+        p = _t(torch, th)
+        hp, hc = waveform.gb_polarizations(p, t)
+        return response.plain_forward(tpl, hp.contiguous(), hc.contiguous(), p[6:8])[0].clone()
+
+    inj = out_of(params)
+    gen = torch.Generator(device="cuda").manual_seed(40)
+    data = inj + SIGMA * torch.randn(inj.shape, dtype=torch.float64, device="cuda", generator=gen)
+    # Evaluate away from the injection in every parameter, so that each
+    # gradient component is dominated by the signal: at the injection the
+    # phase-like components are pure noise sums, and at 1 yr the waveform's
+    # own phase rounding (ulp(2e6 rad) ~ 5e-10) then limits any central
+    # difference to ~1e-4 relative.
+    theta = params.copy()
+    theta[0] *= 1.3
+    theta[1] *= 1 + 1e-9
+    theta[3] += 0.3
+    theta[4] += 0.05
+    theta[5] += 0.05
+    theta[6] += 1e-3
+    theta[7] -= 1e-3
+    _, grad = _gpu_loglike_grad(torch, case, data.cpu().numpy(), theta)
+    h0 = out_of(theta)
+    steps = _fd_steps(n_out * 10.0)
+
+    def diff(h1):
+        return float(-0.5 * torch.sum((h0 - h1) * (2 * data - h1 - h0)) / SIGMA ** 2)
+
+    for k in range(8):
+        def f(x, k=k):
+            th = theta.copy()
+            th[k] = x
+            return diff(out_of(th))
+        fd = _fd_richardson(f, theta[k], steps[k])
+        assert abs(grad[k] - fd) <= TOL_FD * abs(fd), (inputs.PARAM_NAMES[k], grad[k], fd)

@@ -51,7 +51,7 @@ def test_project_links_parity(torch_cuda, order, n_out):
     gorb = _gpu_orbits(case.orbits_proj)
     _padding_ok(case, gorb, gorb)
     y = native.project_links(gorb, g.t0_h, g.dt, _t(torch, case.hp), _t(torch, case.hc),
-                             case.lam, case.beta, order, g.y_start, g.n_y)
+                             _t(torch, [case.lam, case.beta]), order, g.y_start, g.n_y)
     torch.cuda.synchronize()
     orb = oracle.Orbits.from_samples(case.orbits_proj)
     ref = oracle.project_links(orb, g.t0_h, g.dt, case.hp, case.hc, case.lam, case.beta, order,
@@ -87,9 +87,9 @@ def _gpu_response(torch, case):
     gp = _gpu_orbits(case.orbits_proj)
     gt = gp if case.orbits_tdi is case.orbits_proj else _gpu_orbits(case.orbits_tdi)
     _padding_ok(case, gp, gt)
-    out, _ = response.plain_forward(gp, gt, case.grid, _t(torch, case.hp), _t(torch, case.hc),
-                                    case.lam, case.beta, case.order, case.generation,
-                                    case.channels)
+    tpl = response.Template(gp, gt, case.grid, case.order, case.generation, case.channels)
+    out, _ = response.plain_forward(tpl, _t(torch, case.hp), _t(torch, case.hc),
+                                    _t(torch, [case.lam, case.beta]))
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -146,15 +146,29 @@ def test_empty_and_range_errors(torch_cuda):
     g = case.grid
     gorb = _gpu_orbits(case.orbits_proj)
     hp, hc = _t(torch, case.hp), _t(torch, case.hc)
-    y = native.project_links(gorb, g.t0_h, g.dt, hp, hc, 0.1, 0.2, 25, g.y_start, 0)
+    sky = _t(torch, [0.1, 0.2])
+    y = native.project_links(gorb, g.t0_h, g.dt, hp, hc, sky, 25, g.y_start, 0)
     assert y.shape == (6, 0)
     fp, _ = gorb.projection_padding(25, g.dt)
     with pytest.raises(native.LisaRespError) as e:
-        native.project_links(gorb, g.t0_h, g.dt, hp, hc, 0.1, 0.2, 25, fp - 1, 10)
+        native.project_links(gorb, g.t0_h, g.dt, hp, hc, sky, 25, fp - 1, 10)
     assert e.value.status == 2
     with pytest.raises(native.LisaRespError) as e:
-        native.project_links(gorb, g.t0_h, g.dt, hp, hc, 0.1, 0.2, 24, g.y_start, 10)
+        native.project_links(gorb, g.t0_h, g.dt, hp, hc, sky, 24, g.y_start, 10)
     assert e.value.status == 3
     with pytest.raises(native.LisaRespError) as e:     # orbit grid does not cover the times
-        native.project_links(gorb, g.t0_h + 1e6, g.dt, hp, hc, 0.1, 0.2, 25, g.y_start, 10)
+        native.project_links(gorb, g.t0_h + 1e6, g.dt, hp, hc, sky, 25, g.y_start, 10)
     assert e.value.status == 2
+
+
+def test_non_finite_sky_stays_in_bounds(torch_cuda):
+    """NaN angles must give NaN link responses, never a stray access."""
+    from paper_2204_06633_amd import native
+    torch = torch_cuda
+    case = cases.make_case("nan", "keplerian", 600, 10.0, 25, 2, "XYZ", seed=8)
+    g = case.grid
+    gorb = _gpu_orbits(case.orbits_proj)
+    y = native.project_links(gorb, g.t0_h, g.dt, _t(torch, case.hp), _t(torch, case.hc),
+                             _t(torch, [float("nan"), 0.3]), 25, g.y_start, g.n_y)
+    torch.cuda.synchronize()
+    assert torch.isnan(y).all()
