@@ -184,6 +184,76 @@ size_t lr_loglike_workspace(void);
 int lr_loglike(const double *h, const double *data, int64_t n, double sigma, double *loglike,
                double *g_h, void *work, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many templates (sources, or MCMC walkers of one source; the
+ * paper's sampler runs 4 temperatures x 50 walkers, Sec. II.B) whose outputs
+ * share one time grid t0 + i*dt, evaluated by one persistent fused kernel:
+ * projection and TDI in one pass with the link series kept on chip, and the
+ * TDI interpolation coefficients (which depend on the orbits only) shared by
+ * `group` templates at a time.  Durations may differ between templates.
+ * Projection and TDI may use different orbits (the paper's hybrid
+ * templates, Sec. V).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t h_offset;    /* index of the template's h[0] in the batch h+ / hx arrays */
+    int64_t n_h;         /* its h samples */
+    int64_t out_start;   /* its h-index of output sample 0 (time t0) */
+    int64_t n_out;       /* its output samples (>= 0) */
+    int64_t out_offset;  /* index of its output block in the batch output array; the block
+                            is rows x n_out, channel-major (rows 3, or 6 for LR_XYZ_AET) */
+} lr_template;
+
+/* Filled by lr_batch_prepare; treat as opaque.  Holds copies of the orbit
+ * handles and offsets into the caller's device workspace. */
+typedef struct {
+    lr_orbits proj, tdi;
+    double t0, dt;
+    int order, generation, channels, group;
+    int front, tile_out, blocks, adjoint;
+    int64_t n_templates, n_items, n_tdi_items, n_proj_items, n_like_items;
+    int64_t gy_doubles, h_extent, out_extent;
+    void *ws;
+    size_t off[12];
+} lr_batch;
+
+/* Device workspace bytes for a batch.  With adjoint != 0 it includes the
+ * link-gradient scratch of lr_response_adjoint (6 values per link sample of
+ * every template). */
+size_t lr_batch_workspace(const lr_template *t, int64_t n, const lr_orbits *tdi, double dt,
+                          int order, int generation, int channels, int group, int adjoint);
+
+/* Validate a batch (per-template padding from lr_projection_padding /
+ * lr_tdi_padding, orbit coverage, output blocks), build the work lists and
+ * copy them into ws (synchronises `stream` once; call it outside graph
+ * capture).  t: [host][n]; group = templates per work item (1, 2 or 4);
+ * t0: absolute time of output sample 0.  Errors: LR_E_ARG, LR_E_RANGE,
+ * LR_E_UNSUPPORTED (dt so small that the TDI stencil does not fit a tile),
+ * LR_E_WORKSPACE, LR_E_HIP. */
+int lr_batch_prepare(const lr_template *t, int64_t n, const lr_orbits *proj,
+                     const lr_orbits *tdi, double t0, double dt, int order, int generation,
+                     int channels, int group, int adjoint, void *ws, size_t ws_bytes,
+                     lr_batch *out, void *stream);
+
+/* Forward response of every template (Sec. IV.B-IV.C): hp, hc hold the
+ * templates' h arrays at their offsets, sky is device [n][2] (lam, beta),
+ * out receives each template's block.  Graph-capturable. */
+int lr_response(const lr_batch *b, const double *hp, const double *hc, const double *sky,
+                double *out, void *stream);
+
+/* Transpose of lr_response (needs a batch prepared with adjoint != 0):
+ * g_out laid out like out; g_hp, g_hc like hp, hc over [0, h_extent),
+ * overwritten; g_sky device [n][2] (d/d lam, d/d beta) or NULL.
+ * Graph-capturable. */
+int lr_response_adjoint(const lr_batch *b, const double *hp, const double *hc,
+                        const double *sky, const double *g_out, double *g_hp, double *g_hc,
+                        double *g_sky, void *stream);
+
+/* Per-template white-noise log-likelihood (as lr_loglike) of a batch
+ * output: loglike device [n]; g_out (like out, or NULL) receives
+ * (data - out)/sigma^2.  Graph-capturable. */
+int lr_batch_loglike(const lr_batch *b, const double *out, const double *data, double sigma,
+                     double *loglike, double *g_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

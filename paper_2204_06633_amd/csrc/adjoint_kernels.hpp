@@ -81,28 +81,28 @@ __device__ __forceinline__ void scatter_groups(const double (&L)[6], double inv_
   (scatter_group<N, GEN, G, LDS>(L, inv_dt, lds, lds_stride, c0, gy, n_y, p, gch), ...);
 }
 
+constexpr int kAdjTdiCap(int N) { return kBlock + N + kSlack; }
+
+// One output tile (kBlock samples) of the TDI adjoint; `acc` and `red` are
+// the workgroup's LDS scratch.
 template <int N, int GEN>
-__global__ __launch_bounds__(kBlock) void tdi_adjoint_kernel(TdiAdjArgs a) {
+__device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t tile, double* acc,
+                                                 int (&red)[2][kBlock / 64]) {
   constexpr int H = N / 2;
-  constexpr int CAP = kBlock + N + kSlack;
+  constexpr int CAP = kAdjTdiCap(N);
   constexpr int NG = TdiTab<GEN>::v.ngroup;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
   using Groups = std::make_integer_sequence<int, NG>;
-  __shared__ double acc[6 * CAP];
-  __shared__ int red[2][kBlock / 64];
 
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t i0 = tile * kBlock;
   const int64_t i = i0 + tid;
   const bool active = i < a.n_out;
   const int rel = active ? tid : (int)(a.n_out - 1 - i0);
   const int64_t p = a.out_start + i0 + rel;
 
-  double u;
-  const double* seg = orbit_segment(a.orb, a.t_off + (double)p * a.dt, u);
   double L[6];
-#pragma unroll
-  for (int l = 0; l < 6; ++l) L[l] = spline_at(seg, 9 + l, u);
+  light_times(a.orb, a.t_off + (double)p * a.dt, L);
   double dmin, dmax;
   delay_range<GEN>(L, dmin, dmax, Groups{});
   double e_unused;
@@ -143,21 +143,39 @@ __global__ __launch_bounds__(kBlock) void tdi_adjoint_kernel(TdiAdjArgs a) {
   }
 }
 
+template <int N, int GEN>
+__global__ __launch_bounds__(kBlock) void tdi_adjoint_kernel(TdiAdjArgs a) {
+  __shared__ double acc[6 * kAdjTdiCap(N)];
+  __shared__ int red[2][kBlock / 64];
+  tdi_adjoint_tile<N, GEN>(a, blockIdx.x, acc, red);
+}
+
 // ---------------------------------------------------------------------------
 // Projection adjoint
 // ---------------------------------------------------------------------------
+constexpr int kAdjProjCap(int N) { return kBlock + N + kSlack; }
+
+struct ProjAdjShared {
+  int red[2][kBlock / 64];
+  double s_trig[2][2];
+  double s_part[2][kBlock / 64];
+};
+
+// One link-sample tile (kBlock samples) of the projection adjoint; its sky
+// partial pair goes to part[0..1] (if SKY).  acc: 2 * CAP doubles of LDS,
+// win: CAP double2 (SKY only).
 template <int N, bool SKY>
-__global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) {
+__device__ __forceinline__ void project_adjoint_tile(const ProjAdjArgs& a, int64_t tile,
+                                                     double* acc, double2* win,
+                                                     ProjAdjShared& sh_, double* part_out) {
   constexpr int H = N / 2;
-  constexpr int CAP = kBlock + N + kSlack;
-  __shared__ double acc[2 * CAP];                 // g_h+ then g_hx over the footprint
-  __shared__ double2 win[SKY ? CAP : 1];          // h+/hx window (sky gradient only)
-  __shared__ int red[2][kBlock / 64];
-  __shared__ double s_trig[2][2];
-  __shared__ double s_part[2][kBlock / 64];
+  constexpr int CAP = kAdjProjCap(N);
+  auto& red = sh_.red;
+  auto& s_trig = sh_.s_trig;
+  auto& s_part = sh_.s_part;
 
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t i0 = tile * kBlock;
   const int64_t i = i0 + tid;
   const bool active = i < a.n_y;
   const int rel = active ? tid : (int)(a.n_y - 1 - i0);
@@ -165,10 +183,8 @@ __global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) 
 
   const SkyTrig tr = load_sky(a.sky, s_trig);
   const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
-  double u;
-  const double* seg = orbit_segment(a.orb, a.t_off + (double)q * a.dt, u);
   LinkGeom g;
-  link_geometry(seg, u, sk, g);
+  link_geometry(a.orb, a.t_off + (double)q * a.dt, sk, g);
 
   int sh[9];
   double ep[9];
@@ -310,10 +326,19 @@ __global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) 
       double s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int w = 0; w < kBlock / 64; ++w) { s0 += s_part[0][w]; s1 += s_part[1][w]; }
-      a.sky_part[2 * blockIdx.x] = s0;
-      a.sky_part[2 * blockIdx.x + 1] = s1;
+      part_out[0] = s0;
+      part_out[1] = s1;
     }
   }
+}
+
+template <int N, bool SKY>
+__global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) {
+  __shared__ double acc[2 * kAdjProjCap(N)];
+  __shared__ double2 win[SKY ? kAdjProjCap(N) : 1];
+  __shared__ ProjAdjShared sh_;
+  project_adjoint_tile<N, SKY>(a, blockIdx.x, acc, win, sh_,
+                               SKY ? a.sky_part + 2 * blockIdx.x : nullptr);
 }
 
 template <int N>

@@ -14,10 +14,11 @@
 #include "internal.hpp"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int status, const char* fmt, ...) {
+namespace lr {
+int set_error(int status, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -26,6 +27,11 @@ int fail(int status, const char* fmt, ...) {
   g_err = buf;
   return status;
 }
+}  // namespace lr
+
+namespace {
+
+#define fail lr::set_error
 
 int hip_fail(hipError_t e, const char* where) {
   return fail(LR_E_HIP, "%s: %s", where, hipGetErrorString(e));

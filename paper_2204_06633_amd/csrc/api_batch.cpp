@@ -1,0 +1,371 @@
+// C-ABI host layer of the batched calls: validation, work lists, workspace
+// layout and launches.  See include/lisaresp.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/lisaresp.h"
+#include "batch_types.hpp"
+#include "internal.hpp"
+
+namespace {
+
+using lr::set_error;
+
+constexpr int kYTile = 512;           // link samples per fused work item (2 per lane)
+constexpr int64_t kAdjTile = 256;     // samples per adjoint work item
+constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
+
+enum Region {
+  R_TPL, R_ITEMS, R_COUNTER, R_ADJ_TPL, R_TDI_ITEMS, R_PROJ_ITEMS, R_SKY_PART, R_SKY_SPAN,
+  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_GY, R_COUNT
+};
+
+struct Plan {
+  int F = 0, B = 0, T_out = 0;
+  std::vector<lr::BatchTemplate> tpl;
+  std::vector<int> items;
+  std::vector<lr::BatchAdjTemplate> adj;
+  std::vector<int64_t> tdi_items, proj_items, sky_span, like_items, like_span;
+  int64_t gy_doubles = 0, h_extent = 0, out_extent = 0, max_n_out = 0;
+  size_t bytes[R_COUNT] = {};
+  size_t off[R_COUNT] = {};
+  size_t total = 0;
+};
+
+bool valid_order(int order) { return order >= 1 && order <= 31 && (order % 2) == 1; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, int order,
+              int generation, int channels, int group, int adjoint, Plan& P) {
+  if (n < 0 || (n > 0 && !t)) return set_error(LR_E_ARG, "bad template list");
+  if (group != 1 && group != 2 && group != 4)
+    return set_error(LR_E_UNSUPPORTED, "group %d (1, 2 or 4 templates per work item)", group);
+  if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
+    return set_error(LR_E_UNSUPPORTED, "channels %d", channels);
+  if (!valid_order(order)) return set_error(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
+  int64_t F, B;
+  if (int st = lr_tdi_padding(tdi, order, generation, dt, &F, &B)) return st;
+  P.F = (int)F;
+  P.B = (int)B;
+  P.T_out = (kYTile - P.F - P.B) & ~1;
+  if (P.T_out < 2)
+    return set_error(LR_E_UNSUPPORTED, "dt = %g s is too small for the fused kernel (the TDI "
+                                       "stencil needs %lld + %lld of %d link samples)",
+                     dt, (long long)F, (long long)B, kYTile);
+  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
+
+  // grouped forward work list: longest templates first
+  std::vector<int64_t> order_idx(n);
+  std::iota(order_idx.begin(), order_idx.end(), 0);
+  std::stable_sort(order_idx.begin(), order_idx.end(),
+                   [&](int64_t a, int64_t b) { return t[a].n_out > t[b].n_out; });
+  const int64_t n_groups = (n + group - 1) / group;
+  P.tpl.assign(n_groups * group, lr::BatchTemplate{0, 0, 0, 0, 0, -1});
+  for (int64_t g = 0; g < n_groups; ++g) {
+    int64_t gmax = 0;
+    for (int k = 0; k < group; ++k) {
+      const int64_t s = g * group + k;
+      if (s >= n) break;
+      const lr_template& T = t[order_idx[s]];
+      P.tpl[s] = lr::BatchTemplate{T.h_offset, T.n_h, T.out_start, T.n_out, T.out_offset,
+                                   order_idx[s]};
+      gmax = std::max(gmax, T.n_out);
+    }
+    const int64_t tiles = (gmax + P.T_out - 1) / P.T_out;
+    for (int64_t tl = 0; tl < tiles; ++tl) {
+      P.items.push_back((int)g);
+      P.items.push_back((int)tl);
+    }
+  }
+  if ((int64_t)P.items.size() / 2 > (int64_t)0x7fffffff)
+    return set_error(LR_E_ARG, "too many work items");
+
+  // adjoint and likelihood lists, caller's order
+  P.adj.resize(n);
+  for (int64_t b = 0; b < n; ++b) {
+    const lr_template& T = t[b];
+    lr::BatchAdjTemplate A;
+    A.h_off = T.h_offset;
+    A.n_h = T.n_h;
+    A.y_start = T.out_start - P.F;
+    A.n_y = T.n_out > 0 ? T.n_out + P.F + P.B : 0;
+    A.gy_off = P.gy_doubles;
+    A.out_off = T.out_offset;
+    A.n_out = T.n_out;
+    A.index = b;
+    A.t_off_h = 0.0;                      // set by prepare (needs the orbit and t0)
+    P.adj[b] = A;
+    P.gy_doubles += 6 * A.n_y;
+    for (int64_t tl = 0; tl < (T.n_out + kAdjTile - 1) / kAdjTile; ++tl) {
+      P.tdi_items.push_back(b);
+      P.tdi_items.push_back(tl);
+    }
+    const int64_t first = (int64_t)P.proj_items.size() / 2;
+    for (int64_t tl = 0; tl < (A.n_y + kAdjTile - 1) / kAdjTile; ++tl) {
+      P.proj_items.push_back(b);
+      P.proj_items.push_back(tl);
+    }
+    P.sky_span.push_back(first);
+    P.sky_span.push_back((int64_t)P.proj_items.size() / 2 - first);
+    P.sky_span.push_back(b);
+    const int64_t lfirst = (int64_t)P.like_items.size() / 2;
+    const int64_t len = rows * T.n_out;
+    for (int64_t c = 0; c < len; c += kLikeChunk) {
+      P.like_items.push_back(T.out_offset + c);
+      P.like_items.push_back(T.out_offset + std::min(len, c + kLikeChunk));
+    }
+    P.like_span.push_back(lfirst);
+    P.like_span.push_back((int64_t)P.like_items.size() / 2 - lfirst);
+    P.like_span.push_back(b);
+    P.h_extent = std::max(P.h_extent, T.h_offset + T.n_h);
+    P.out_extent = std::max(P.out_extent, T.out_offset + len);
+    P.max_n_out = std::max(P.max_n_out, T.n_out);
+  }
+
+  P.bytes[R_TPL] = P.tpl.size() * sizeof(lr::BatchTemplate);
+  P.bytes[R_ITEMS] = P.items.size() * sizeof(int);
+  P.bytes[R_COUNTER] = sizeof(int);
+  P.bytes[R_ADJ_TPL] = P.adj.size() * sizeof(lr::BatchAdjTemplate);
+  P.bytes[R_TDI_ITEMS] = adjoint ? P.tdi_items.size() * sizeof(int64_t) : 0;
+  P.bytes[R_PROJ_ITEMS] = adjoint ? P.proj_items.size() * sizeof(int64_t) : 0;
+  P.bytes[R_SKY_PART] = adjoint ? P.proj_items.size() * sizeof(double) : 0;   // 2 per item
+  P.bytes[R_SKY_SPAN] = adjoint ? P.sky_span.size() * sizeof(int64_t) : 0;
+  P.bytes[R_LIKE_ITEMS] = P.like_items.size() * sizeof(int64_t);
+  P.bytes[R_LIKE_PART] = P.like_items.size() / 2 * sizeof(double);
+  P.bytes[R_LIKE_SPAN] = P.like_span.size() * sizeof(int64_t);
+  P.bytes[R_GY] = adjoint ? (size_t)P.gy_doubles * sizeof(double) : 0;
+  size_t o = 0;
+  for (int r = 0; r < R_COUNT; ++r) {
+    P.off[r] = o;
+    o = align256(o + P.bytes[r]);
+  }
+  P.total = std::max<size_t>(o, 256);
+  return LR_OK;
+}
+
+bool disjoint(std::vector<std::pair<int64_t, int64_t>> iv) {
+  std::sort(iv.begin(), iv.end());
+  for (size_t i = 1; i < iv.size(); ++i)
+    if (iv[i].first < iv[i - 1].second) return false;
+  return true;
+}
+
+template <typename T>
+T* at(const lr_batch* b, Region r) {
+  return reinterpret_cast<T*>(static_cast<char*>(b->ws) + b->off[r]);
+}
+
+lr::OrbitView view(const lr_orbits& o) {
+  lr::OrbitView v;
+  v.coef = static_cast<const double*>(o.coef);
+  v.dt = o.dt;
+  v.inv_dt = 1.0 / o.dt;
+  v.nseg = o.n - 1;
+  return v;
+}
+
+int check_batch(const lr_batch* b) {
+  if (!b || !b->ws || !b->proj.coef || !b->tdi.coef) return set_error(LR_E_ARG, "batch not prepared");
+  return LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lr_batch_workspace(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt,
+                          int order, int generation, int channels, int group, int adjoint) {
+  Plan P;
+  if (make_plan(t, n, tdi, dt, order, generation, channels, group, adjoint, P)) return 0;
+  return P.total;
+}
+
+int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
+                     const lr_orbits* tdi, double t0, double dt, int order, int generation,
+                     int channels, int group, int adjoint, void* ws, size_t ws_bytes,
+                     lr_batch* out, void* stream) {
+  if (!out || !proj || !tdi) return set_error(LR_E_ARG, "null pointer");
+  if (!std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt)) return set_error(LR_E_ARG, "bad t0 or dt");
+  Plan P;
+  if (int st = make_plan(t, n, tdi, dt, order, generation, channels, group, adjoint, P)) return st;
+  if (!ws || ws_bytes < P.total)
+    return set_error(LR_E_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, P.total);
+  int64_t fp, bp;
+  if (int st = lr_projection_padding(proj, order, dt, &fp, &bp)) return st;
+  const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
+  std::vector<std::pair<int64_t, int64_t>> hiv, oiv;
+  for (int64_t b = 0; b < n; ++b) {
+    const lr_template& T = t[b];
+    if (T.n_out < 0 || T.n_h < 0 || T.h_offset < 0 || T.out_offset < 0)
+      return set_error(LR_E_ARG, "template %lld: negative size or offset", (long long)b);
+    if (T.n_out == 0) continue;
+    const int64_t y0 = T.out_start - P.F, y1 = T.out_start + T.n_out + P.B - 1;
+    if (y0 - fp < 0 || y1 + bp > T.n_h - 1)
+      return set_error(LR_E_RANGE, "template %lld: h covers [0, %lld) but its link samples "
+                                   "[%lld, %lld] need %lld before and %lld after",
+                       (long long)b, (long long)T.n_h, (long long)y0, (long long)y1,
+                       (long long)fp, (long long)bp);
+    hiv.push_back({T.h_offset, T.h_offset + T.n_h});
+    oiv.push_back({T.out_offset, T.out_offset + rows * T.n_out});
+  }
+  if (!disjoint(oiv)) return set_error(LR_E_ARG, "output blocks overlap");
+  if (adjoint && !disjoint(hiv)) return set_error(LR_E_ARG, "h ranges overlap (adjoint batch)");
+  const double t_off_p = t0 - proj->t0, t_off_t = t0 - tdi->t0;
+  const double span_p = (double)(proj->n - 1) * proj->dt, span_t = (double)(tdi->n - 1) * tdi->dt;
+  if (n > 0 && P.max_n_out > 0) {
+    const double a0 = t_off_p - P.F * dt, a1 = t_off_p + (double)(P.max_n_out + P.B) * dt;
+    const double b0 = t_off_t, b1 = t_off_t + (double)P.max_n_out * dt;
+    if (!(a0 >= 0.0) || !(a1 <= span_p) || !(b0 >= 0.0) || !(b1 <= span_t))
+      return set_error(LR_E_RANGE, "the orbit grids do not cover the batch's sample times");
+  }
+  for (auto& A : P.adj) A.t_off_h = t_off_p - (double)t[A.index].out_start * dt;
+
+  // host image of the workspace, one copy
+  std::vector<char> img(P.total, 0);
+  auto put = [&](Region r, const void* src) {
+    if (P.bytes[r]) std::memcpy(img.data() + P.off[r], src, P.bytes[r]);
+  };
+  put(R_TPL, P.tpl.data());
+  put(R_ITEMS, P.items.data());
+  put(R_ADJ_TPL, P.adj.data());
+  put(R_TDI_ITEMS, P.tdi_items.data());
+  put(R_PROJ_ITEMS, P.proj_items.data());
+  put(R_SKY_SPAN, P.sky_span.data());
+  put(R_LIKE_ITEMS, P.like_items.data());
+  put(R_LIKE_SPAN, P.like_span.data());
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(ws, img.data(), P.off[R_GY], hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(LR_E_HIP, "lr_batch_prepare copy: %s", hipGetErrorString(e));
+
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  const int64_t n_items = (int64_t)P.items.size() / 2;
+  const int64_t per_cu = lr::fused_blocks_per_cu(order, generation, group);
+
+  out->proj = *proj;
+  out->tdi = *tdi;
+  out->t0 = t0;
+  out->dt = dt;
+  out->order = order;
+  out->generation = generation;
+  out->channels = channels;
+  out->group = group;
+  out->front = P.F;
+  out->tile_out = P.T_out;
+  out->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)cus * per_cu));
+  out->adjoint = adjoint ? 1 : 0;
+  out->n_templates = n;
+  out->n_items = n_items;
+  out->n_tdi_items = (int64_t)P.tdi_items.size() / 2;
+  out->n_proj_items = (int64_t)P.proj_items.size() / 2;
+  out->n_like_items = (int64_t)P.like_items.size() / 2;
+  out->gy_doubles = adjoint ? P.gy_doubles : 0;
+  out->h_extent = P.h_extent;
+  out->out_extent = P.out_extent;
+  out->ws = ws;
+  for (int r = 0; r < R_COUNT; ++r) out->off[r] = P.off[r];
+  return LR_OK;
+}
+
+int lr_response(const lr_batch* b, const double* hp, const double* hc, const double* sky,
+                double* out, void* stream) {
+  if (int st = check_batch(b)) return st;
+  if (b->n_items == 0) return LR_OK;
+  if (!hp || !hc || !sky || !out) return set_error(LR_E_ARG, "null pointer");
+  lr::BatchFwdArgs a;
+  a.orb_p = view(b->proj);
+  a.orb_t = view(b->tdi);
+  a.tpl = at<const lr::BatchTemplate>(b, R_TPL);
+  a.items = at<const int>(b, R_ITEMS);
+  a.n_items = (int)b->n_items;
+  a.counter = at<int>(b, R_COUNTER);
+  a.t_off_p = b->t0 - b->proj.t0;
+  a.t_off_t = b->t0 - b->tdi.t0;
+  a.dt = b->dt;
+  a.inv_dt = 1.0 / b->dt;
+  a.F = b->front;
+  a.T_out = b->tile_out;
+  a.hp = hp;
+  a.hc = hc;
+  a.sky = sky;
+  a.channels = b->channels;
+  a.out = out;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_reset_counter(a.counter, s);
+  if (e == hipSuccess)
+    e = lr::run_fused_forward(b->order, b->generation, b->group, a, b->blocks, s);
+  if (e != hipSuccess) return set_error(LR_E_HIP, "lr_response launch: %s", hipGetErrorString(e));
+  return LR_OK;
+}
+
+int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
+                        const double* sky, const double* g_out, double* g_hp, double* g_hc,
+                        double* g_sky, void* stream) {
+  if (int st = check_batch(b)) return st;
+  if (!b->adjoint) return set_error(LR_E_WORKSPACE, "batch prepared without adjoint workspace");
+  if (!g_hp || !g_hc || !sky || (b->n_tdi_items > 0 && !g_out))
+    return set_error(LR_E_ARG, "null pointer");
+  if (g_sky && (!hp || !hc)) return set_error(LR_E_ARG, "the sky gradient needs h+ and hx");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_fill_zero(g_hp, b->h_extent, s);
+  if (e == hipSuccess) e = lr::run_fill_zero(g_hc, b->h_extent, s);
+  if (e == hipSuccess) e = lr::run_fill_zero(at<double>(b, R_GY), b->gy_doubles, s);
+  if (e == hipSuccess && g_sky) e = lr::run_fill_zero(g_sky, 2 * b->n_templates, s);
+  lr::BatchAdjArgs a;
+  a.orb_p = view(b->proj);
+  a.orb_t = view(b->tdi);
+  a.tpl = at<const lr::BatchAdjTemplate>(b, R_ADJ_TPL);
+  a.t_off_y = (b->t0 - b->tdi.t0) - b->front * b->dt;
+  a.dt = b->dt;
+  a.inv_dt = 1.0 / b->dt;
+  a.F = b->front;
+  a.channels = b->channels;
+  a.hp = hp;
+  a.hc = hc;
+  a.sky = sky;
+  a.g_out = g_out;
+  a.g_y = at<double>(b, R_GY);
+  a.g_hp = g_hp;
+  a.g_hc = g_hc;
+  a.sky_part = g_sky ? at<double>(b, R_SKY_PART) : nullptr;
+  if (e == hipSuccess && b->n_tdi_items > 0) {
+    a.items = at<const int64_t>(b, R_TDI_ITEMS);
+    e = lr::run_batch_tdi_adjoint(b->order, b->generation, a, b->n_tdi_items, s);
+  }
+  if (e == hipSuccess && b->n_proj_items > 0) {
+    a.items = at<const int64_t>(b, R_PROJ_ITEMS);
+    e = lr::run_batch_project_adjoint(b->order, a, b->n_proj_items, s);
+  }
+  if (e == hipSuccess && g_sky && b->n_proj_items > 0)
+    e = lr::run_batch_sky_finalize(a.sky_part, at<const int64_t>(b, R_SKY_SPAN), b->n_templates,
+                                   g_sky, s);
+  if (e != hipSuccess)
+    return set_error(LR_E_HIP, "lr_response_adjoint launch: %s", hipGetErrorString(e));
+  return LR_OK;
+}
+
+int lr_batch_loglike(const lr_batch* b, const double* out, const double* data, double sigma,
+                     double* loglike, double* g_out, void* stream) {
+  if (int st = check_batch(b)) return st;
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return set_error(LR_E_ARG, "sigma must be positive");
+  if (!loglike || (b->n_like_items > 0 && (!out || !data))) return set_error(LR_E_ARG, "null pointer");
+  if (b->n_templates == 0) return LR_OK;
+  hipError_t e = lr::run_batch_loglike(out, data, at<const int64_t>(b, R_LIKE_ITEMS),
+                                       b->n_like_items, 1.0 / (sigma * sigma), g_out,
+                                       at<double>(b, R_LIKE_PART),
+                                       at<const int64_t>(b, R_LIKE_SPAN), b->n_templates,
+                                       loglike, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return set_error(LR_E_HIP, "lr_batch_loglike launch: %s", hipGetErrorString(e));
+  return LR_OK;
+}
+
+}  // extern "C"

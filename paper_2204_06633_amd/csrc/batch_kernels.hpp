@@ -1,0 +1,293 @@
+// Batched response kernels for gfx950 (FP64): many templates (sources or
+// MCMC walkers) sharing one output time grid, one launch.
+//
+// fused_forward_kernel<N, GEN, M> is persistent: each workgroup takes work
+// items (a group of M templates, a tile of output samples) from an atomic
+// counter until the list is exhausted.  For one item it
+//   1. computes, template by template, the link series of the tile plus the
+//      TDI halo directly into LDS (projection, Sec. IV.B) -- the link series
+//      never reaches HBM;
+//   2. evaluates TDI (Sec. IV.C) for all M templates at once: the delays
+//      depend on the orbits only, so each Lagrange coefficient sequence is
+//      generated once per sample and applied to the M templates' series;
+//   3. stores X/Y/Z and/or A/E/T of each template.
+#pragma once
+
+#include "adjoint_kernels.hpp"
+#include "batch_types.hpp"
+
+namespace lr {
+
+// TDI of the lane's two outputs for M templates from their LDS link windows.
+template <int N, int GEN, int M>
+__device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* ylds,
+                                          const double (&La)[6], const double (&Lb)[6], int c0,
+                                          const bool (&live)[M], double (&acc)[M][2][3]) {
+  constexpr int H = N / 2;
+  constexpr int YT = kFwdTile;
+  constexpr int ND = TdiTab<GEN>::v.ndirect;
+  const GroupTable<GEN>& GT = group_table<GEN>();
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[k][s][c] = 0.0;
+
+#pragma unroll
+  for (int t = 0; t < ND; ++t) {
+    const Direct dr = TdiTab<GEN>::v.direct[t];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const double* w = ylds + (k * 6 + dr.link) * YT;
+      acc[k][0][dr.chan] += (double)dr.sign * w[par<YT>(c0)];
+      acc[k][1][dr.chan] += (double)dr.sign * w[par<YT>(c0 + 1)];
+    }
+  }
+#pragma unroll 1
+  for (int g = 0; g < GT.n; ++g) {
+    const GroupRow& G = GT.row[g];
+    double ea, eb;
+    const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
+    const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
+    const bool same = __all(sa == sb);
+    // The padding bound keeps every stored output's stencil inside the tile;
+    // the clamp only guards the idle lanes past a template's end.
+    const int top = YT - 1 - N;
+    const ParStream<YT> pa_(min(max(c0 + sa - (H - 1), 0), top)),
+        pb_(min(max(c0 + 1 + sb - (H - 1), 0), top));
+#pragma unroll 1
+    for (int u = 0; u < G.nuse; ++u) {
+      const int link = G.link[u];
+      double xa[M], xb[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) { xa[k] = 0.0; xb[k] = 0.0; }
+      LagrangeStream<N> A(ea), B(eb);
+      if (same) {
+#pragma unroll
+        for (int m = 0; m <= N; ++m) {
+          double v[M];
+#pragma unroll
+          for (int k = 0; k < M; ++k) v[k] = ylds[(k * 6 + link) * YT + pa_.at(m)];
+          if (m < N) {
+            const double c = A.coef(m);
+#pragma unroll
+            for (int k = 0; k < M; ++k) xa[k] = fma(c, v[k], xa[k] * A.d);
+            A.next();
+          }
+          if (m > 0) {
+            const double c = B.coef(m - 1);
+#pragma unroll
+            for (int k = 0; k < M; ++k) xb[k] = fma(c, v[k], xb[k] * B.d);
+            B.next();
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+          const double c = A.coef(m), e = B.coef(m);
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            xa[k] = fma(c, ylds[(k * 6 + link) * YT + pa_.at(m)], xa[k] * A.d);
+            xb[k] = fma(e, ylds[(k * 6 + link) * YT + pb_.at(m)], xb[k] * B.d);
+          }
+          A.next();
+          B.next();
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc[k][0][c] = fma(G.sgn[u][c], xa[k], acc[k][0][c]);
+          acc[k][1][c] = fma(G.sgn[u][c], xb[k], acc[k][1][c]);
+        }
+    }
+  }
+  (void)live;
+}
+
+template <int N, int GEN, int M>
+__global__ __launch_bounds__(kBlock) void fused_forward_kernel(BatchFwdArgs a) {
+  constexpr int YT = kFwdTile;
+  constexpr int CAPH = kFwdTile + N + kSlack;
+  __shared__ double ylds[M * 6 * YT];
+  __shared__ double2 hwin[CAPH];
+  __shared__ int red[2][kBlock / 64];
+  __shared__ double s_trig[2][2];
+  __shared__ int s_item;
+
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= a.n_items) break;                     // uniform: every lane read s_item
+    const int grp = a.items[2 * item], tile = a.items[2 * item + 1];
+    const int64_t o0 = (int64_t)tile * a.T_out;       // output index of the tile's first output
+    const int64_t i_base = o0 - a.F;                  // output index of tile element 0
+
+    // 1. link series of each template of the group into LDS
+    bool live[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const BatchTemplate T = a.tpl[grp * M + k];
+      live[k] = T.index >= 0 && o0 < T.n_out;
+      if (!live[k]) continue;                         // uniform
+      const int64_t n_valid = min((int64_t)a.T_out, T.n_out - o0);
+      const int r_end = (int)min((int64_t)YT, a.F + n_valid + (YT - a.F - a.T_out));
+      const int last = r_end - 1;
+      const bool act_a = 2 * tid <= last, act_b = 2 * tid + 1 <= last;
+      const int ra = act_a ? 2 * tid : (last & ~1);
+      __syncthreads();                                // s_trig and hwin free
+      if (tid < 2) {
+        double sn, cs;
+        sincos(a.sky[2 * T.index + tid], &sn, &cs);
+        s_trig[tid][0] = sn;
+        s_trig[tid][1] = cs;
+      }
+      __syncthreads();
+      const Sky sk = sky_from_trig(s_trig[0][0], s_trig[0][1], s_trig[1][0], s_trig[1][1]);
+      double ya[6], yb[6];
+      project_pair<N>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, a.hp + T.h_off,
+                      a.hc + T.h_off, T.n_h, T.out_start + i_base, sk, ra, hwin, red, ya, yb);
+#pragma unroll
+      for (int l = 0; l < 6; ++l) {
+        double* row = ylds + (k * 6 + l) * YT;
+        if (act_a) row[par<YT>(ra)] = ya[l];
+        if (act_b) row[par<YT>(ra + 1)] = yb[l];
+      }
+    }
+    __syncthreads();
+
+    // 2. TDI of the tile's outputs for all live templates
+    const int oa = 2 * tid;                           // tile-relative output of sample a
+    const bool out_a = oa < a.T_out;
+    const int ob = out_a ? oa : a.T_out - 2;          // idle lanes mirror the last pair
+    double La[6], Lb[6];
+    light_times(a.orb_t, a.t_off_t + (double)(o0 + ob) * a.dt, La);
+    light_times(a.orb_t, a.t_off_t + (double)(o0 + ob + 1) * a.dt, Lb);
+    double acc[M][2][3];
+    fused_tdi<N, GEN, M>(a, ylds, La, Lb, a.F + ob, live, acc);
+
+    // 3. store
+    if (out_a) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        if (!live[k]) continue;
+        const BatchTemplate T = a.tpl[grp * M + k];
+        const int64_t i = o0 + oa;
+        if (i < T.n_out) store_channels(acc[k][0], a.channels, a.out + T.out_off, T.n_out, i);
+        if (i + 1 < T.n_out)
+          store_channels(acc[k][1], a.channels, a.out + T.out_off, T.n_out, i + 1);
+      }
+    }
+    __syncthreads();                                  // LDS free for the next item
+  }
+}
+
+template <int N, int GEN, int M>
+hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((fused_forward_kernel<N, GEN, M>), dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of the fused kernel (sizes the persistent grid).
+template <int N, int GEN, int M>
+int fused_occupancy() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_forward_kernel<N, GEN, M>, kBlock,
+                                                   0) != hipSuccess)
+    nb = 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace lr
+
+namespace lr {
+
+// ---------------------------------------------------------------------------
+// Batched adjoints: one work item = (template, tile); the per-tile bodies are
+// the single-template ones.
+// ---------------------------------------------------------------------------
+template <int N, int GEN>
+__global__ __launch_bounds__(kBlock) void batch_tdi_adjoint_kernel(BatchAdjArgs a) {
+  __shared__ double acc[6 * kAdjTdiCap(N)];
+  __shared__ int red[2][kBlock / 64];
+  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  const BatchAdjTemplate T = a.tpl[b];
+  TdiAdjArgs x;
+  x.orb = a.orb_t;
+  x.g_out = a.g_out + T.out_off;
+  x.channels = a.channels;
+  x.n_y = T.n_y;
+  x.t_off = a.t_off_y;
+  x.dt = a.dt;
+  x.inv_dt = a.inv_dt;
+  x.out_start = a.F;
+  x.n_out = T.n_out;
+  x.g_y = a.g_y + T.gy_off;
+  tdi_adjoint_tile<N, GEN>(x, tile, acc, red);
+}
+
+template <int N, bool SKY>
+__global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjArgs a) {
+  __shared__ double acc[2 * kAdjProjCap(N)];
+  __shared__ double2 win[SKY ? kAdjProjCap(N) : 1];
+  __shared__ ProjAdjShared sh_;
+  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  const BatchAdjTemplate T = a.tpl[b];
+  ProjAdjArgs x;
+  x.orb = a.orb_p;
+  x.hp = a.hp + T.h_off;
+  x.hc = a.hc + T.h_off;
+  x.n_h = T.n_h;
+  x.t_off = T.t_off_h;
+  x.dt = a.dt;
+  x.inv_dt = a.inv_dt;
+  x.sky = a.sky + 2 * T.index;
+  x.y_start = T.y_start;
+  x.n_y = T.n_y;
+  x.g_y = a.g_y + T.gy_off;
+  x.g_hp = a.g_hp + T.h_off;
+  x.g_hc = a.g_hc + T.h_off;
+  x.sky_part = nullptr;
+  project_adjoint_tile<N, SKY>(x, tile, acc, win, sh_,
+                               SKY ? a.sky_part + 2 * blockIdx.x : nullptr);
+}
+
+template <int N, int GEN>
+hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s) {
+  hipLaunchKernelGGL((batch_tdi_adjoint_kernel<N, GEN>), dim3((unsigned)n_items), dim3(kBlock), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s) {
+  if (a.sky_part)
+    hipLaunchKernelGGL((batch_project_adjoint_kernel<N, true>), dim3((unsigned)n_items),
+                       dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((batch_project_adjoint_kernel<N, false>), dim3((unsigned)n_items),
+                       dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+#define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M)                                                 \
+  template hipError_t launch_fused_forward<NT, GEN, M>(const BatchFwdArgs&, int, hipStream_t); \
+  template int fused_occupancy<NT, GEN, M>();
+
+#define LR_INSTANTIATE_BATCH_FWD(NT, GEN)   \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1)    \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2)    \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4)
+
+#define LR_INSTANTIATE_BATCH_ADJ(NT)                                                           \
+  template hipError_t launch_batch_tdi_adjoint<NT, 1>(const BatchAdjArgs&, int64_t,             \
+                                                      hipStream_t);                            \
+  template hipError_t launch_batch_tdi_adjoint<NT, 2>(const BatchAdjArgs&, int64_t,             \
+                                                      hipStream_t);                            \
+  template hipError_t launch_batch_project_adjoint<NT>(const BatchAdjArgs&, int64_t, hipStream_t);
+
+}  // namespace lr

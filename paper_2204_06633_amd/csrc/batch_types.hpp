@@ -1,0 +1,82 @@
+// Descriptors and arguments of the batched kernels (shared by the kernels
+// and the host layer).
+#pragma once
+
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace lr {
+
+struct BatchTemplate {
+  int64_t h_off;       // offset of h[0] in the batch h+ / hx arrays
+  int64_t n_h;
+  int64_t out_start;   // h-index of output sample 0
+  int64_t n_out;
+  int64_t out_off;     // offset of the output block (rows x n_out, channel-major)
+  int64_t index;       // position in the caller's template list (sky row); < 0: empty slot
+};
+
+struct BatchFwdArgs {
+  OrbitView orb_p, orb_t;
+  const BatchTemplate* tpl;  // [n_groups * M], grouped
+  const int* items;          // [n_items][2]: group, tile
+  int n_items;
+  int* counter;              // work-item counter, zero before the launch
+  double t_off_p, t_off_t;   // time of output sample 0 minus each orbit grid's first sample
+  double dt, inv_dt;
+  int F;                     // link samples before the first output of a tile
+  int T_out;                 // outputs per tile (even)
+  const double* hp;
+  const double* hc;
+  const double* sky;         // [n_templates][2] (lam, beta) in the caller's order
+  int channels;
+  double* out;
+};
+
+struct BatchAdjTemplate {
+  int64_t h_off, n_h;
+  int64_t y_start, n_y;     // link series: h-indices [y_start, y_start + n_y)
+  int64_t gy_off;           // offset of its [6][n_y] block in the link-gradient workspace
+  int64_t out_off, n_out;
+  int64_t index;            // caller's position (sky row, g_sky row, loglike entry)
+  double t_off_h;           // time of h[0] minus the projection orbit grid's first sample
+};
+
+struct BatchAdjArgs {
+  OrbitView orb_p, orb_t;
+  const BatchAdjTemplate* tpl;  // [n_templates], caller's order
+  const int64_t* items;         // [n_items][2]: template, tile
+  double t_off_y;               // time of link sample 0 (= output index -F) minus the TDI grid's
+  double dt, inv_dt;
+  int F;                        // link samples before output 0
+  int channels;
+  const double* hp;
+  const double* hc;
+  const double* sky;
+  const double* g_out;
+  double* g_y;
+  double* g_hp;
+  double* g_hc;
+  double* sky_part;             // [n_proj_items][2] or null
+};
+
+// Launchers (instantiated per tap count in batch_*.hip).
+template <int N, int GEN, int M>
+hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s);
+template <int N, int GEN, int M>
+int fused_occupancy();
+template <int N, int GEN>
+hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
+template <int N>
+hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
+
+hipError_t run_fused_forward(int order, int gen, int group, const BatchFwdArgs& a, int blocks,
+                             hipStream_t s);
+int fused_blocks_per_cu(int order, int gen, int group);
+hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int64_t n_items,
+                                 hipStream_t s);
+hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,
+                                     hipStream_t s);
+
+}  // namespace lr

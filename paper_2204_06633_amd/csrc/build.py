@@ -16,8 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 TARGET = os.path.join(PKG, "_lisaresp.so")
-SOURCES = ["forward_%s.hip" % k for k in "abcd"] + ["adjoint_%s.hip" % k for k in "abcd"] + \
-    ["util.hip", "dispatch.cpp", "api.cpp"]
+SOURCES = (["forward_%s.hip" % k for k in "abcd"] + ["adjoint_%s.hip" % k for k in "abcd"] +
+           ["batchfwd%d_%s.hip" % (g, k) for g in (1, 2) for k in "abcd"] +
+           ["batchadj_%s.hip" % k for k in "abcd"] +
+           ["util.hip", "dispatch.cpp", "api.cpp", "api_batch.cpp"])
 ARCH = os.environ.get("LR_OFFLOAD_ARCH", "gfx950")
 
 
@@ -41,17 +43,21 @@ def build(verbose=True, jobs=None):
     os.makedirs(out_dir, exist_ok=True)
     cc = hipcc()
     t0 = time.time()
-    procs = []
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(out_dir, src.rsplit(".", 1)[0] + ".o")
-        objs.append(obj)
-        cmd = [cc, *flags(), "-c", os.path.join(HERE, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd)))
-    for src, p in procs:
+    jobs = jobs or min(os.cpu_count() or 4, int(os.environ.get("MAX_JOBS", "8")), 16)
+    objs = [os.path.join(out_dir, src.rsplit(".", 1)[0] + ".o") for src in SOURCES]
+    pending = list(zip(SOURCES, objs))
+    running = []
+    while pending or running:
+        while pending and len(running) < jobs:
+            src, obj = pending.pop(0)
+            cmd = [cc, *flags(), "-c", os.path.join(HERE, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((src, subprocess.Popen(cmd)))
+        src, p = running.pop(0)
         if p.wait() != 0:
+            for _, q in running:
+                q.wait()
             raise RuntimeError("compilation of %s failed" % src)
     tmp = TARGET + ".tmp%d" % os.getpid()
     cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]

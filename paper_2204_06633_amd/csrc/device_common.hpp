@@ -42,6 +42,28 @@ __device__ __forceinline__ double spline_at(const double* seg, int series, doubl
   return fma(fma(fma(c[3], u, c[2]), u, c[1]), u, c[0]);
 }
 
+// Spline series FIRST .. FIRST + COUNT - 1 at time tau.  When the whole wave
+// sits in one coarse segment (the usual case: a segment spans thousands of
+// samples) the coefficients are read once per wave with scalar loads instead
+// of once per lane.
+template <int FIRST, int COUNT>
+__device__ __forceinline__ void orbit_series(const OrbitView& o, double tau, double (&v)[COUNT]) {
+  double s = floor(tau * o.inv_dt);
+  s = fmin(fmax(s, 0.0), (double)(o.nseg - 1));
+  const double u = tau - s * o.dt;
+  const int si = (int)s;
+  const int su = __builtin_amdgcn_readfirstlane(si);
+  if (__all(si == su)) {
+    const double* seg = o.coef + (int64_t)su * kSegStride;
+#pragma unroll
+    for (int k = 0; k < COUNT; ++k) v[k] = spline_at(seg, FIRST + k, u);
+  } else {
+    const double* seg = o.coef + (int64_t)si * kSegStride;
+#pragma unroll
+    for (int k = 0; k < COUNT; ++k) v[k] = spline_at(seg, FIRST + k, u);
+  }
+}
+
 struct Sky {
   double k[3], u[3], v[3];
 };
@@ -92,23 +114,26 @@ struct LinkGeom {
   double xip[3], xic[3], kn[3];
 };
 
-__device__ __forceinline__ void link_geometry(const double* seg, double u, const Sky& sk,
+__device__ __forceinline__ void link_geometry(const OrbitView& o, double tau, const Sky& sk,
                                               LinkGeom& g) {
+  double v[15];
+  orbit_series<0, 15>(o, tau, v);
 #pragma unroll
   for (int s = 0; s < 3; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g.x[s][c] = spline_at(seg, 3 * s + c, u);
+    for (int c = 0; c < 3; ++c) g.x[s][c] = v[3 * s + c];
 #pragma unroll
-  for (int l = 0; l < 6; ++l) g.L[l] = spline_at(seg, 9 + l, u);
+  for (int l = 0; l < 6; ++l) g.L[l] = v[9 + l];
+  constexpr double inv_c = 1.0 / kC;
 #pragma unroll
   for (int s = 0; s < 3; ++s)
-    g.kx[s] = (sk.k[0] * g.x[s][0] + sk.k[1] * g.x[s][1] + sk.k[2] * g.x[s][2]) / kC;
+    g.kx[s] = (sk.k[0] * g.x[s][0] + sk.k[1] * g.x[s][1] + sk.k[2] * g.x[s][2]) * inv_c;
 #pragma unroll
   for (int arm = 0; arm < 3; ++arm) {
     const int r = arm, e = (arm + 1) % 3;
     double d0 = g.x[r][0] - g.x[e][0], d1 = g.x[r][1] - g.x[e][1], d2 = g.x[r][2] - g.x[e][2];
-    double nrm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    d0 /= nrm; d1 /= nrm; d2 /= nrm;
+    const double inrm = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    d0 *= inrm; d1 *= inrm; d2 *= inrm;
     g.n[arm][0] = d0; g.n[arm][1] = d1; g.n[arm][2] = d2;
     double un = sk.u[0] * d0 + sk.u[1] * d1 + sk.u[2] * d2;
     double vn = sk.v[0] * d0 + sk.v[1] * d1 + sk.v[2] * d2;
@@ -165,6 +190,53 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N]) {
   for (int m = N - 1; m >= 0; --m) {
     w[m] *= suf * C.c[m];
     suf *= eps - (double)(m - (H - 1));
+  }
+}
+
+// Streaming Lagrange interpolation, without materialising the weights:
+//   I = sum_m c_m P_m S_m f_m,  P_m = prod_{j<m}(eps - x_j), S_m = prod_{j>m}(eps - x_j),
+// evaluated by the recurrence T_k = T_{k-1} (eps - x_k) + c_k P_k f_k (so that
+// T_{N-1} = I) with P_{k+1} = P_k (eps - x_k).  Per tap: 3 FP64 ops shared by
+// all series on the stencil plus 2 per series, and O(1) registers.
+template <int N>
+struct LagrangeStream {
+  double d, P;
+  __device__ __forceinline__ explicit LagrangeStream(double eps)
+      : d(eps + (double)(N / 2 - 1)), P(1.0) {}
+  // coefficient c_k P_k of tap k; advance to tap k+1 afterwards with next()
+  __device__ __forceinline__ double coef(int k) const {
+    constexpr LagrangeDenoms<N> C = make_denoms<N>();
+    return C.c[k] * P;
+  }
+  __device__ __forceinline__ void next() {
+    P *= d;
+    d -= 1.0;
+  }
+};
+
+// Two weight sets at once (two independent product chains).
+template <int N>
+__device__ __forceinline__ void lagrange_weights2(double ea, double eb, double (&wa)[N],
+                                                  double (&wb)[N]) {
+  constexpr LagrangeDenoms<N> C = make_denoms<N>();
+  constexpr int H = N / 2;
+  double pa = 1.0, pb = 1.0;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    wa[m] = pa;
+    wb[m] = pb;
+    const double x = (double)(m - (H - 1));
+    pa *= ea - x;
+    pb *= eb - x;
+  }
+  double sa = 1.0, sb = 1.0;
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    wa[m] *= sa * C.c[m];
+    wb[m] *= sb * C.c[m];
+    const double x = (double)(m - (H - 1));
+    sa *= ea - x;
+    sb *= eb - x;
   }
 }
 

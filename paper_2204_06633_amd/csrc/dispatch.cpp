@@ -1,4 +1,5 @@
 // Runtime dispatch from the interpolation order to the compiled tap counts.
+#include "batch_types.hpp"
 #include "internal.hpp"
 
 namespace lr {
@@ -37,6 +38,68 @@ hipError_t run_tdi_adjoint(int order, int gen, const TdiAdjArgs& a, hipStream_t 
 hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s) {
   switch (order) {
 #define X(ORD, NT) case ORD: return launch_project_adjoint<NT>(a, s);
+    LR_ORDER_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define LR_GROUP_CASES(NT, GEN)                                                   \
+  switch (group) {                                                                \
+    case 1: return launch_fused_forward<NT, GEN, 1>(a, blocks, s);                 \
+    case 2: return launch_fused_forward<NT, GEN, 2>(a, blocks, s);                 \
+    case 4: return launch_fused_forward<NT, GEN, 4>(a, blocks, s);                 \
+    default: return hipErrorInvalidValue;                                         \
+  }
+
+hipError_t run_fused_forward(int order, int gen, int group, const BatchFwdArgs& a, int blocks,
+                             hipStream_t s) {
+  switch (order) {
+#define X(ORD, NT) \
+  case ORD:        \
+    if (gen == 1) { LR_GROUP_CASES(NT, 1) } else { LR_GROUP_CASES(NT, 2) }
+    LR_ORDER_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define LR_OCC_CASES(NT, GEN)                           \
+  switch (group) {                                      \
+    case 1: return fused_occupancy<NT, GEN, 1>();        \
+    case 2: return fused_occupancy<NT, GEN, 2>();        \
+    case 4: return fused_occupancy<NT, GEN, 4>();        \
+    default: return 1;                                  \
+  }
+
+int fused_blocks_per_cu(int order, int gen, int group) {
+  switch (order) {
+#define X(ORD, NT) \
+  case ORD:        \
+    if (gen == 1) { LR_OCC_CASES(NT, 1) } else { LR_OCC_CASES(NT, 2) }
+    LR_ORDER_CASES(X)
+#undef X
+    default: return 1;
+  }
+}
+
+hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int64_t n_items,
+                                 hipStream_t s) {
+  switch (order) {
+#define X(ORD, NT) \
+  case ORD:        \
+    return gen == 1 ? launch_batch_tdi_adjoint<NT, 1>(a, n_items, s) \
+                    : launch_batch_tdi_adjoint<NT, 2>(a, n_items, s);
+    LR_ORDER_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,
+                                     hipStream_t s) {
+  switch (order) {
+#define X(ORD, NT) case ORD: return launch_batch_project_adjoint<NT>(a, n_items, s);
     LR_ORDER_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

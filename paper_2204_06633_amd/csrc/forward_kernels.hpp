@@ -2,13 +2,21 @@
 //   project_links_kernel  -- link responses y_ij, Sec. IV.B
 //   tdi_kernel            -- Michelson TDI-1 / TDI-2 and A, E, T, Sec. IV.C
 //
-// Both kernels are time-tiled: a workgroup owns kBlock consecutive output
+// Both kernels are time-tiled: a workgroup owns kFwdTile consecutive output
 // samples, computes every retarded position of its samples first, reduces the
 // extent of all their interpolation stencils, stages exactly that window of
 // the input series in LDS with coalesced loads, and then evaluates the
 // Lagrange sums from LDS (the paper's shared-memory sub-arrays, Sec. IV.E,
-// re-designed around a per-tile stencil window).  One lane owns one output
-// sample; stores are link- / channel-major and coalesced.
+// re-designed around a per-tile stencil window).
+//
+// Each lane owns two consecutive output samples.  Their retarded positions
+// drift by far less than a sample, so for every position the two stencils
+// are the same window shifted by one: the lane streams N + 1 values from LDS
+// and feeds both Lagrange sums (half the LDS traffic of one sample per lane),
+// and the two weight sets are independent product chains (twice the
+// instruction-level parallelism).  A wave whose two stencils do not line up
+// for some position (an integer crossing) takes a separate-window branch for
+// that position.  Stores are link- / channel-major and coalesced.
 #pragma once
 
 #include <utility>
@@ -18,8 +26,10 @@
 
 namespace lr {
 
-constexpr int kBlock = kTile;   // output samples per workgroup
-constexpr int kSlack = 64;   // window samples beyond kBlock + taps
+constexpr int kBlock = kTile;          // lanes per workgroup
+constexpr int kSlack = 64;             // window samples beyond the tile + taps
+constexpr int kPerLane = 2;            // forward kernels: consecutive samples per lane
+constexpr int kFwdTile = kBlock * kPerLane;
 
 // ---------------------------------------------------------------------------
 // Shared tile machinery
@@ -58,95 +68,210 @@ __device__ __forceinline__ void block_range(int lo, int hi, int (&red)[2][BLOCK 
   for (int w = 1; w < BLOCK / 64; ++w) { wlo = min(wlo, red[0][w]); whi = max(whi, red[1][w]); }
 }
 
+// LDS windows of the two-samples-per-lane kernels are stored split by
+// parity: element j of a window of capacity CAP sits at par(j) = (j odd ?
+// half : 0) + j/2.  A lane streams from element ra + c (ra = 2*lane, c shared
+// by the wave), so for every tap the wave reads 64 consecutive addresses
+// instead of every other one (no bank conflicts).
+template <int CAP>
+__device__ __forceinline__ int par(int j) {
+  return (j & 1) * ((CAP + 1) / 2) + (j >> 1);
+}
+
+// Addresses of elements j0 and j0 + 1 of a parity-split window: element
+// j0 + k is at first + k/2 for even k and at second + (k-1)/2 for odd k.
+template <int CAP>
+struct ParStream {
+  int first, second;
+  __device__ __forceinline__ explicit ParStream(int j0) : first(par<CAP>(j0)), second(par<CAP>(j0 + 1)) {}
+  __device__ __forceinline__ int at(int k) const { return (k & 1) ? second + (k >> 1) : first + (k >> 1); }
+};
+
 // ---------------------------------------------------------------------------
 // Projection
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(kBlock) void project_links_kernel(ProjArgs a) {
-  constexpr int H = N / 2;
-  constexpr int CAP = kBlock + N + kSlack;
-  __shared__ double2 win[CAP];
-  __shared__ int red[2][kBlock / 64];
-  __shared__ double s_trig[2][2];
 
-  const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
-  const int64_t i = i0 + tid;
-  const bool active = i < a.n_y;
-  const int rel = active ? tid : (int)(a.n_y - 1 - i0);   // idle lanes mirror the last sample
-  const int64_t q = a.y_start + i0 + rel;
+// Positions p = 0..2 (reception at spacecraft p+1) enter the links received
+// there with a minus sign; p = 3..8 (emission of link p-3) enter that link
+// with a plus sign.  Adds xi+ h+ + xix hx of position p to the numerators.
+__device__ __forceinline__ void add_position(int p, const double (&xip)[3],
+                                             const double (&xic)[3], double hp, double hc,
+                                             double (&num)[6]) {
+  if (p >= 3) {
+    const int l = p - 3, arm = kArm[l];
+    num[l] += xip[arm] * hp + xic[arm] * hc;
+  } else {
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+      if (kLinkRecv[l] - 1 == p) num[l] -= xip[kArm[l]] * hp + xic[kArm[l]] * hc;
+  }
+}
 
-  const SkyTrig tr = load_sky(a.sky, s_trig);
-  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
-  double u;
-  const double* seg = orbit_segment(a.orb, a.t_off + (double)q * a.dt, u);
-  LinkGeom g;
-  link_geometry(seg, u, sk, g);
-
+// Per-sample state of the projection: what the link assembly needs.
+struct ProjSample {
   int sh[9];
   double ep[9];
-#pragma unroll
-  for (int p = 0; p < 9; ++p) sh[p] = split_delay(position_delay(g, p), a.inv_dt, ep[p]);
-  int lo = sh[0], hi = sh[0];
-#pragma unroll
-  for (int p = 1; p < 9; ++p) { lo = min(lo, sh[p]); hi = max(hi, sh[p]); }
-  int wlo, whi;
-  block_range<kBlock>(rel + lo - (H - 1), rel + hi + H, red, wlo, whi);
-  const int count = whi - wlo + 1;
-  const int64_t base = a.y_start + i0 + wlo;     // h-index of win[0]
-  const int64_t hmax = a.n_h - 1;
+  double xip[3], xic[3], kn[3];
+};
 
-  double hv[2][9];
+__device__ __forceinline__ void proj_sample(const OrbitView& orb, double tau, double inv_dt,
+                                            const Sky& sk, ProjSample& s) {
+  LinkGeom g;
+  link_geometry(orb, tau, sk, g);
+#pragma unroll
+  for (int p = 0; p < 9; ++p) s.sh[p] = split_delay(position_delay(g, p), inv_dt, s.ep[p]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { s.xip[k] = g.xip[k]; s.xic[k] = g.xic[k]; s.kn[k] = g.kn[k]; }
+}
+
+// Link responses of one template at the lane's two tile samples ra and ra+1
+// (ra even).  Tile element r has h-index hq0 + r and orbit time
+// t_off + (ti0 + r) * dt.  Uses the workgroup's LDS window and reduction
+// scratch; contains barriers, so every lane of the workgroup must call it.
+template <int N>
+__device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off, int64_t ti0,
+                                             double dt, double inv_dt, const double* hp,
+                                             const double* hc, int64_t n_h, int64_t hq0,
+                                             const Sky& sk, int ra, double2* win,
+                                             int (&red)[2][kBlock / 64], double (&ya)[6],
+                                             double (&yb)[6]) {
+  constexpr int H = N / 2;
+  constexpr int CAP = kFwdTile + N + kSlack;
+  const int tid = threadIdx.x;
+  ProjSample A, B;
+  proj_sample(orb, t_off + (double)(ti0 + ra) * dt, inv_dt, sk, A);
+  __builtin_amdgcn_sched_barrier(0);     // one sample's geometry live at a time
+  proj_sample(orb, t_off + (double)(ti0 + ra + 1) * dt, inv_dt, sk, B);
+  __builtin_amdgcn_sched_barrier(0);
+
+  int lo = min(A.sh[0], B.sh[0] + 1), hi = max(A.sh[0], B.sh[0] + 1);
+#pragma unroll
+  for (int p = 1; p < 9; ++p) {
+    lo = min(lo, min(A.sh[p], B.sh[p] + 1));
+    hi = max(hi, max(A.sh[p], B.sh[p] + 1));
+  }
+  int wlo, whi;
+  block_range<kBlock>(ra + lo - (H - 1), ra + hi + H, red, wlo, whi);
+  const int count = whi - wlo + 1;
+  const int64_t base = hq0 + wlo;                // h-index of window element 0
+  const int64_t hmax = n_h - 1;
+  const int64_t qa = hq0 + ra;
+
+  double na[6] = {0, 0, 0, 0, 0, 0}, nb[6] = {0, 0, 0, 0, 0, 0};
   if (count > 0 && count <= CAP) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > hmax ? hmax : j);
-      win[k] = make_double2(a.hp[j], a.hc[j]);
+      win[par<CAP>(k)] = make_double2(hp[j], hc[j]);
     }
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
-      double w[N];
-      lagrange_weights<N>(ep[p], w);
-      const double2* src = win + (rel + sh[p] - (H - 1) - wlo);
-      double sp = 0.0, sc = 0.0;
+      LagrangeStream<N> sa(A.ep[p]), sb(B.ep[p]);
+      const ParStream<CAP> src(ra + A.sh[p] - (H - 1) - wlo);
+      double pa = 0.0, ca = 0.0, pb = 0.0, cb = 0.0;
+      if (__all(A.sh[p] == B.sh[p])) {
+        // sample b's stencil is sample a's shifted by one: N + 1 loads feed both
 #pragma unroll
-      for (int m = 0; m < N; ++m) {
-        double2 v = src[m];
-        sp = fma(w[m], v.x, sp);
-        sc = fma(w[m], v.y, sc);
+        for (int k = 0; k <= N; ++k) {
+          const double2 v = win[src.at(k)];
+          if (k < N) {
+            const double c = sa.coef(k);
+            pa = fma(c, v.x, pa * sa.d);
+            ca = fma(c, v.y, ca * sa.d);
+            sa.next();
+          }
+          if (k > 0) {
+            const double c = sb.coef(k - 1);
+            pb = fma(c, v.x, pb * sb.d);
+            cb = fma(c, v.y, cb * sb.d);
+            sb.next();
+          }
+        }
+      } else {
+        const ParStream<CAP> srb(ra + 1 + B.sh[p] - (H - 1) - wlo);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double2 v = win[src.at(k)], w = win[srb.at(k)];
+          const double c = sa.coef(k), e = sb.coef(k);
+          pa = fma(c, v.x, pa * sa.d);
+          ca = fma(c, v.y, ca * sa.d);
+          pb = fma(e, w.x, pb * sb.d);
+          cb = fma(e, w.y, cb * sb.d);
+          sa.next();
+          sb.next();
+        }
       }
-      hv[0][p] = sp;
-      hv[1][p] = sc;
+      add_position(p, A.xip, A.xic, pa, ca, na);
+      add_position(p, B.xip, B.xic, pb, cb, nb);
+      __builtin_amdgcn_sched_barrier(0);   // keep one position's streams live at a time
     }
   } else {
     // Window larger than the LDS tile (very small dt or extreme orbits):
     // read the stencils from global memory, indices clamped.
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
-      double w[N];
-      lagrange_weights<N>(ep[p], w);
-      const int64_t j0 = q + sh[p] - (H - 1);
-      double sp = 0.0, sc = 0.0;
-#pragma unroll
+      LagrangeStream<N> sa(A.ep[p]), sb(B.ep[p]);
+      const int64_t ja = qa + A.sh[p] - (H - 1), jb = qa + 1 + B.sh[p] - (H - 1);
+      double pa = 0.0, ca = 0.0, pb = 0.0, cb = 0.0;
+#pragma unroll 1
       for (int m = 0; m < N; ++m) {
-        int64_t j = j0 + m;
+        int64_t j = ja + m;
         j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        sp = fma(w[m], a.hp[j], sp);
-        sc = fma(w[m], a.hc[j], sc);
+        const double c = sa.coef(m);
+        pa = fma(c, hp[j], pa * sa.d);
+        ca = fma(c, hc[j], ca * sa.d);
+        sa.next();
+        j = jb + m;
+        j = j < 0 ? 0 : (j > hmax ? hmax : j);
+        const double e = sb.coef(m);
+        pb = fma(e, hp[j], pb * sb.d);
+        cb = fma(e, hc[j], cb * sb.d);
+        sb.next();
       }
-      hv[0][p] = sp;
-      hv[1][p] = sc;
+      add_position(p, A.xip, A.xic, pa, ca, na);
+      add_position(p, B.xip, B.xic, pb, cb, nb);
     }
   }
-
-  if (!active) return;
 #pragma unroll
   for (int l = 0; l < 6; ++l) {
     const int arm = kArm[l];
-    const int pr = kLinkRecv[l] - 1, pe = 3 + l;
-    double num = g.xip[arm] * (hv[0][pe] - hv[0][pr]) + g.xic[arm] * (hv[1][pe] - hv[1][pr]);
-    a.y[(int64_t)l * a.n_y + i] = num / (2.0 * (1.0 - kDir[l] * g.kn[arm]));
+    ya[l] = na[l] / (2.0 * (1.0 - kDir[l] * A.kn[arm]));
+    yb[l] = nb[l] / (2.0 * (1.0 - kDir[l] * B.kn[arm]));
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock)
+void project_links_kernel(ProjArgs a) {
+  constexpr int CAP = kFwdTile + N + kSlack;
+  __shared__ double2 win[CAP];
+  __shared__ int red[2][kBlock / 64];
+  __shared__ double s_trig[2][2];
+
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * kFwdTile;
+  const int last = (int)min((int64_t)(kFwdTile - 1), a.n_y - 1 - i0);
+  const bool act_a = kPerLane * tid <= last, act_b = kPerLane * tid + 1 <= last;
+  const int ra = act_a ? kPerLane * tid : last;          // idle lanes mirror the last sample
+
+  const SkyTrig tr = load_sky(a.sky, s_trig);
+  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
+  double ya[6], yb[6];
+  project_pair<N>(a.orb, a.t_off, a.y_start + i0, a.dt, a.inv_dt, a.hp, a.hc, a.n_h,
+                  a.y_start + i0, sk, ra, win, red, ya, yb);
+
+  if (!act_a) return;
+  const int64_t i = i0 + ra;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    double* dst = a.y + (int64_t)l * a.n_y + i;
+    if (act_b && ((reinterpret_cast<uintptr_t>(dst) & 15) == 0)) {
+      *reinterpret_cast<double2*>(dst) = make_double2(ya[l], yb[l]);
+    } else {
+      dst[0] = ya[l];
+      if (act_b) dst[1] = yb[l];
+    }
   }
 }
 
@@ -198,107 +323,264 @@ __device__ __forceinline__ void delay_range(const double (&L)[6], double& dmin, 
   ((dmin = fmin(dmin, delay_of<GEN, G>(L)), dmax = fmax(dmax, delay_of<GEN, G>(L))), ...);
 }
 
-// Interpolate every series that group G delays and add it to its channel.
-template <int N, int GEN, int G, bool LDS>
-__device__ __forceinline__ void apply_group(const double (&L)[6], double inv_dt, const double* lds,
-                                            int lds_stride, int c0, const double* y, int64_t n_y,
-                                            int64_t p, double (&acc)[3]) {
-  constexpr int H = N / 2;
-  constexpr DelayGroup grp = TdiTab<GEN>::v.group[G];
-  double eps;
-  const int sh = split_delay(delay_of<GEN, G>(L), inv_dt, eps);
-  double w[N];
-  lagrange_weights<N>(eps, w);
-#pragma unroll
-  for (int k = 0; k < grp.nuse; ++k) {
-    double s = 0.0;
-    if constexpr (LDS) {
-      const double* src = lds + grp.use[k].link * lds_stride + (c0 + sh - (H - 1));
-#pragma unroll
-      for (int m = 0; m < N; ++m) s = fma(w[m], src[m], s);
-    } else {
-      const int64_t j0 = p + sh - (H - 1);
-      const double* ys = y + (int64_t)grp.use[k].link * n_y;
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        int64_t j = j0 + m;
-        j = j < 0 ? 0 : (j > n_y - 1 ? n_y - 1 : j);
-        s = fma(w[m], ys[j], s);
-      }
+// Delay groups as a run-time table in constant memory: the kernels loop over
+// groups without unrolling, so only one group's state is live at a time.
+struct GroupRow {
+  double cnt[6];       // light-time multiplicities of the group's delay
+  int nuse;            // 1 or 2 delayed terms share the delay
+  int link[2];         // measured link of each use
+  double sgn[2][3];    // signed X, Y, Z selector of each use
+};
+
+template <int GEN>
+struct GroupTable {
+  GroupRow row[3 * TdiTable<GEN>::kTermsPerChan];
+  int n;
+  int chain;           // longest chain of link delays (3 or 7)
+};
+
+template <int GEN>
+constexpr GroupTable<GEN> make_group_table() {
+  constexpr TdiTable<GEN> t = make_tdi_table<GEN>();
+  GroupTable<GEN> r{};
+  r.n = t.ngroup;
+  r.chain = GEN == 1 ? 3 : 7;
+  for (int g = 0; g < t.ngroup; ++g) {
+    for (int l = 0; l < 6; ++l) r.row[g].cnt[l] = (double)t.group[g].cnt[l];
+    r.row[g].nuse = t.group[g].nuse;
+    for (int k = 0; k < t.group[g].nuse; ++k) {
+      r.row[g].link[k] = t.group[g].use[k].link;
+      for (int c = 0; c < 3; ++c)
+        r.row[g].sgn[k][c] = t.group[g].use[k].chan == c ? (double)t.group[g].use[k].sign : 0.0;
     }
-    acc[grp.use[k].chan] += (double)grp.use[k].sign * s;
+  }
+  return r;
+}
+
+static __constant__ GroupTable<1> kGroups1 = make_group_table<1>();
+static __constant__ GroupTable<2> kGroups2 = make_group_table<2>();
+
+template <int GEN>
+__device__ __forceinline__ const GroupTable<GEN>& group_table();
+template <>
+__device__ __forceinline__ const GroupTable<1>& group_table<1>() { return kGroups1; }
+template <>
+__device__ __forceinline__ const GroupTable<2>& group_table<2>() { return kGroups2; }
+
+__device__ __forceinline__ double row_delay(const GroupRow& g, const double (&L)[6]) {
+  double d = 0.0;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) d = fma(g.cnt[l], L[l], d);
+  return d;
+}
+
+// Safe bounds of every group delay from the light times: a delay is a sum of
+// 1..chain link light times.
+__device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int chain, double& dlo,
+                                                   double& dhi) {
+  double lmin = L[0], lmax = L[0];
+#pragma unroll
+  for (int l = 1; l < 6; ++l) { lmin = fmin(lmin, L[l]); lmax = fmax(lmax, L[l]); }
+  dlo = fmin(lmin, chain * lmin);
+  dhi = fmax(lmax, chain * lmax);
+}
+
+// One use (measured link) of a delay group for both samples of a lane, from
+// the parity-split LDS window w: sa_ starts sample a's stencil; if `same`,
+// sample b's stencil is the next window position, otherwise it starts at sb_.
+template <int N, int CAP>
+__device__ __forceinline__ void stream_pair(double ea, double eb, bool same, const double* w,
+                                            const ParStream<CAP>& sa_, const ParStream<CAP>& sb_,
+                                            double& xa, double& xb) {
+  LagrangeStream<N> A(ea), B(eb);
+  xa = 0.0;
+  xb = 0.0;
+  if (same) {
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      const double v = w[sa_.at(k)];
+      if (k < N) { xa = fma(A.coef(k), v, xa * A.d); A.next(); }
+      if (k > 0) { xb = fma(B.coef(k - 1), v, xb * B.d); B.next(); }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      xa = fma(A.coef(k), w[sa_.at(k)], xa * A.d);
+      xb = fma(B.coef(k), w[sb_.at(k)], xb * B.d);
+      A.next();
+      B.next();
+    }
   }
 }
 
-template <int N, int GEN, bool LDS, int... G>
-__device__ __forceinline__ void apply_groups(const double (&L)[6], double inv_dt, const double* lds,
-                                             int lds_stride, int c0, const double* y, int64_t n_y,
-                                             int64_t p, double (&acc)[3],
-                                             std::integer_sequence<int, G...>) {
-  (apply_group<N, GEN, G, LDS>(L, inv_dt, lds, lds_stride, c0, y, n_y, p, acc), ...);
+// Two uses sharing one delay (one product chain per sample, two series).
+template <int N, int CAP>
+__device__ __forceinline__ void stream_pair2(double ea, double eb, bool same, const double* w0,
+                                             const double* w1, const ParStream<CAP>& sa_,
+                                             const ParStream<CAP>& sb_, double (&xa)[2],
+                                             double (&xb)[2]) {
+  LagrangeStream<N> A(ea), B(eb);
+  xa[0] = xa[1] = xb[0] = xb[1] = 0.0;
+  if (same) {
+#pragma unroll
+    for (int k = 0; k <= N; ++k) {
+      const double v0 = w0[sa_.at(k)], v1 = w1[sa_.at(k)];
+      if (k < N) {
+        const double c = A.coef(k);
+        xa[0] = fma(c, v0, xa[0] * A.d);
+        xa[1] = fma(c, v1, xa[1] * A.d);
+        A.next();
+      }
+      if (k > 0) {
+        const double c = B.coef(k - 1);
+        xb[0] = fma(c, v0, xb[0] * B.d);
+        xb[1] = fma(c, v1, xb[1] * B.d);
+        B.next();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double c = A.coef(k), e = B.coef(k);
+      xa[0] = fma(c, w0[sa_.at(k)], xa[0] * A.d);
+      xa[1] = fma(c, w1[sa_.at(k)], xa[1] * A.d);
+      xb[0] = fma(e, w0[sb_.at(k)], xb[0] * B.d);
+      xb[1] = fma(e, w1[sb_.at(k)], xb[1] * B.d);
+      A.next();
+      B.next();
+    }
+  }
+}
+
+// Global-memory version for one sample (clamped indices).
+template <int N>
+__device__ __forceinline__ double stream_global(double eps, const double* ys, int64_t j0,
+                                                int64_t n) {
+  LagrangeStream<N> A(eps);
+  double x = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < N; ++k) {
+    int64_t j = j0 + k;
+    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    x = fma(A.coef(k), ys[j], x * A.d);
+    A.next();
+  }
+  return x;
+}
+
+__device__ __forceinline__ void light_times(const OrbitView& o, double tau, double (&L)[6]) {
+  orbit_series<9, 6>(o, tau, L);
 }
 
 template <int N, int GEN>
 __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
   constexpr int H = N / 2;
-  constexpr int CAP = kBlock + N + kSlack;
-  constexpr int NG = TdiTab<GEN>::v.ngroup;
+  constexpr int CAP = kFwdTile + N + kSlack;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
-  using Groups = std::make_integer_sequence<int, NG>;
+  const GroupTable<GEN>& GT = group_table<GEN>();
   __shared__ double win[6 * CAP];
   __shared__ int red[2][kBlock / 64];
 
   const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
-  const int64_t i = i0 + tid;
-  const bool active = i < a.n_out;
-  const int rel = active ? tid : (int)(a.n_out - 1 - i0);
-  const int64_t p = a.out_start + i0 + rel;          // y-index of the output sample
+  const int64_t i0 = (int64_t)blockIdx.x * kFwdTile;
+  const int last = (int)min((int64_t)(kFwdTile - 1), a.n_out - 1 - i0);
+  const bool act_a = kPerLane * tid <= last, act_b = kPerLane * tid + 1 <= last;
+  const int ra = act_a ? kPerLane * tid : last;
+  const int64_t pa = a.out_start + i0 + ra;          // y-index of sample a; b is pa + 1
 
-  double u;
-  const double* seg = orbit_segment(a.orb, a.t_off + (double)p * a.dt, u);
-  double L[6];
-#pragma unroll
-  for (int l = 0; l < 6; ++l) L[l] = spline_at(seg, 9 + l, u);
+  double La[6], Lb[6];
+  light_times(a.orb, a.t_off + (double)pa * a.dt, La);
+  light_times(a.orb, a.t_off + (double)(pa + 1) * a.dt, Lb);
 
-  double dmin, dmax;
-  delay_range<GEN>(L, dmin, dmax, Groups{});
+  double dlo_a, dhi_a, dlo_b, dhi_b;
+  group_delay_bounds(La, GT.chain, dlo_a, dhi_a);
+  group_delay_bounds(Lb, GT.chain, dlo_b, dhi_b);
   double e_unused;
-  int lo = min(0, split_delay(dmax, a.inv_dt, e_unused) - (H - 1));
-  int hi = max(0, split_delay(dmin, a.inv_dt, e_unused) + H);
+  const int lo = min(0, min(split_delay(dhi_a, a.inv_dt, e_unused),
+                            split_delay(dhi_b, a.inv_dt, e_unused) + 1) - (H - 1));
+  const int hi = max(1, max(split_delay(dlo_a, a.inv_dt, e_unused),
+                            split_delay(dlo_b, a.inv_dt, e_unused) + 1) + H);
   int wlo, whi;
-  block_range<kBlock>(rel + lo, rel + hi, red, wlo, whi);
+  block_range<kBlock>(ra + lo, ra + hi, red, wlo, whi);
   const int count = whi - wlo + 1;
   const int64_t base = a.out_start + i0 + wlo;
   const int64_t ymax = a.n_y - 1;
-  const int c0 = rel - wlo;
+  const int c0 = ra - wlo;
 
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc_a[3] = {0.0, 0.0, 0.0}, acc_b[3] = {0.0, 0.0, 0.0};
   if (count > 0 && count <= CAP) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > ymax ? ymax : j);
 #pragma unroll
-      for (int l = 0; l < 6; ++l) win[l * CAP + k] = a.y[(int64_t)l * a.n_y + j];
+      for (int l = 0; l < 6; ++l) win[l * CAP + par<CAP>(k)] = a.y[(int64_t)l * a.n_y + j];
     }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
       const Direct dr = TdiTab<GEN>::v.direct[t];
-      acc[dr.chan] += (double)dr.sign * win[dr.link * CAP + c0];
+      acc_a[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0)];
+      acc_b[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0 + 1)];
     }
-    apply_groups<N, GEN, true>(L, a.inv_dt, win, CAP, c0, a.y, a.n_y, p, acc, Groups{});
+#pragma unroll 1
+    for (int g = 0; g < GT.n; ++g) {
+      const GroupRow& G = GT.row[g];
+      double ea, eb;
+      const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
+      const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
+      const bool same = __all(sa == sb);
+      const ParStream<CAP> pa_(c0 + sa - (H - 1)), pb_(c0 + 1 + sb - (H - 1));
+      if (G.nuse == 1) {
+        double xa, xb;
+        stream_pair<N, CAP>(ea, eb, same, win + G.link[0] * CAP, pa_, pb_, xa, xb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc_a[c] = fma(G.sgn[0][c], xa, acc_a[c]);
+          acc_b[c] = fma(G.sgn[0][c], xb, acc_b[c]);
+        }
+      } else {
+        double xa[2], xb[2];
+        stream_pair2<N, CAP>(ea, eb, same, win + G.link[0] * CAP, win + G.link[1] * CAP, pa_,
+                             pb_, xa, xb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc_a[c] = fma(G.sgn[0][c], xa[0], fma(G.sgn[1][c], xa[1], acc_a[c]));
+          acc_b[c] = fma(G.sgn[0][c], xb[0], fma(G.sgn[1][c], xb[1], acc_b[c]));
+        }
+      }
+    }
   } else {
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
       const Direct dr = TdiTab<GEN>::v.direct[t];
-      acc[dr.chan] += (double)dr.sign * a.y[(int64_t)dr.link * a.n_y + p];
+      const double* ys = a.y + (int64_t)dr.link * a.n_y;
+      acc_a[dr.chan] += (double)dr.sign * ys[pa];
+      acc_b[dr.chan] += (double)dr.sign * ys[min(pa + 1, ymax)];
     }
-    apply_groups<N, GEN, false>(L, a.inv_dt, win, CAP, c0, a.y, a.n_y, p, acc, Groups{});
+#pragma unroll 1
+    for (int g = 0; g < GT.n; ++g) {
+      const GroupRow& G = GT.row[g];
+      double ea, eb;
+      const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
+      const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
+#pragma unroll 1
+      for (int k = 0; k < G.nuse; ++k) {
+        const double* ys = a.y + (int64_t)G.link[k] * a.n_y;
+        const double xa = stream_global<N>(ea, ys, pa + sa - (H - 1), a.n_y);
+        const double xb = stream_global<N>(eb, ys, pa + 1 + sb - (H - 1), a.n_y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc_a[c] = fma(G.sgn[k][c], xa, acc_a[c]);
+          acc_b[c] = fma(G.sgn[k][c], xb, acc_b[c]);
+        }
+      }
+    }
   }
 
-  if (!active) return;
-  store_channels(acc, a.channels, a.out, a.n_out, i);
+  if (!act_a) return;
+  const int64_t i = i0 + ra;
+  store_channels(acc_a, a.channels, a.out, a.n_out, i);
+  if (act_b) store_channels(acc_b, a.channels, a.out, a.n_out, i + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,14 +588,14 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
 // ---------------------------------------------------------------------------
 template <int N>
 hipError_t launch_project(const ProjArgs& a, hipStream_t s) {
-  const int64_t blocks = (a.n_y + kBlock - 1) / kBlock;
+  const int64_t blocks = (a.n_y + kFwdTile - 1) / kFwdTile;
   hipLaunchKernelGGL(project_links_kernel<N>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t launch_tdi(const TdiArgs& a, int gen, hipStream_t s) {
-  const int64_t blocks = (a.n_out + kBlock - 1) / kBlock;
+  const int64_t blocks = (a.n_out + kFwdTile - 1) / kFwdTile;
   if (gen == 1)
     hipLaunchKernelGGL((tdi_kernel<N, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
   else

@@ -68,6 +68,9 @@ hipError_t launch_tdi_adjoint(const TdiAdjArgs& a, int gen, hipStream_t s);
 template <int N>
 hipError_t launch_project_adjoint(const ProjAdjArgs& a, hipStream_t s);
 
+// Records a formatted message for lr_last_error() and returns `status`.
+int set_error(int status, const char* fmt, ...);
+
 // Workgroup size of the tiled kernels (output samples per workgroup).
 constexpr int kTile = 256;
 
@@ -77,6 +80,13 @@ size_t loglike_workspace_bytes();
 hipError_t run_loglike(const double* h, const double* d, int64_t n, double inv_var, double* g,
                        double* part, double* out, hipStream_t s);
 hipError_t run_tdi_adjoint(int order, int gen, const TdiAdjArgs& a, hipStream_t s);
+hipError_t run_batch_loglike(const double* h, const double* d, const int64_t* items,
+                             int64_t n_items, double inv_var, double* g, double* part,
+                             const int64_t* span, int64_t n_templates, double* out,
+                             hipStream_t s);
+hipError_t run_batch_sky_finalize(const double* part, const int64_t* span, int64_t n_templates,
+                                  double* g_sky, hipStream_t s);
+hipError_t run_reset_counter(int* c, hipStream_t s);
 hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s);
 
 // Runtime dispatch on the interpolation order (odd 1..31).

@@ -77,6 +77,85 @@ hipError_t run_loglike(const double* h, const double* d, int64_t n, double inv_v
   return hipGetLastError();
 }
 
+// Batched likelihood: items are element ranges [begin, end) of one
+// template's output block; the finalisation sums each template's item
+// partials in order.
+__global__ __launch_bounds__(256) void batch_loglike_kernel(const double* h, const double* d,
+                                                            const int64_t* items, double inv_var,
+                                                            double* g, double* part) {
+  __shared__ double s[256];
+  const int tid = threadIdx.x;
+  const int64_t b0 = items[2 * blockIdx.x], b1 = items[2 * blockIdx.x + 1];
+  double acc = 0.0;
+  for (int64_t k = b0 + tid; k < b1; k += 256) {
+    const double r = d[k] - h[k];
+    acc = fma(r, r, acc);
+    if (g) g[k] = r * inv_var;
+  }
+  s[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) s[tid] += s[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = s[0];
+}
+
+// One workgroup per template: out[index] = -1/2 inv_var * sum of its partials
+// (pairs: first item, item count, output index).
+__global__ __launch_bounds__(256) void batch_finalize_kernel(const double* part, int width,
+                                                             const int64_t* span,
+                                                             double scale, double* out) {
+  __shared__ double s[2][256];
+  const int tid = threadIdx.x;
+  const int64_t first = span[3 * blockIdx.x], count = span[3 * blockIdx.x + 1];
+  const int64_t index = span[3 * blockIdx.x + 2];
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t k = tid; k < count; k += 256) {
+    a0 += part[width * (first + k)];
+    if (width > 1) a1 += part[width * (first + k) + 1];
+  }
+  s[0][tid] = a0;
+  s[1][tid] = a1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) { s[0][tid] += s[0][tid + w]; s[1][tid] += s[1][tid + w]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[width * index] = scale * s[0][0];
+    if (width > 1) out[width * index + 1] = scale * s[1][0];
+  }
+}
+
+__global__ void reset_counter_kernel(int* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
+hipError_t run_batch_loglike(const double* h, const double* d, const int64_t* items,
+                             int64_t n_items, double inv_var, double* g, double* part,
+                             const int64_t* span, int64_t n_templates, double* out,
+                             hipStream_t s) {
+  if (n_items > 0)
+    hipLaunchKernelGGL(batch_loglike_kernel, dim3((unsigned)n_items), dim3(256), 0, s, h, d,
+                       items, inv_var, g, part);
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3((unsigned)n_templates), dim3(256), 0, s, part,
+                     1, span, -0.5 * inv_var, out);
+  return hipGetLastError();
+}
+
+hipError_t run_batch_sky_finalize(const double* part, const int64_t* span, int64_t n_templates,
+                                  double* g_sky, hipStream_t s) {
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3((unsigned)n_templates), dim3(256), 0, s, part, 2,
+                     span, 1.0, g_sky);
+  return hipGetLastError();
+}
+
+hipError_t run_reset_counter(int* c, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
 hipError_t run_fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;

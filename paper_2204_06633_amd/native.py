@@ -23,6 +23,10 @@ class LisaRespError(RuntimeError):
         super().__init__("%s failed: %s (%s)" % (where, message, _status_name(status)))
 
 
+# status codes of include/lisaresp.h
+LR_OK, LR_E_ARG, LR_E_RANGE, LR_E_UNSUPPORTED, LR_E_WORKSPACE, LR_E_HIP = range(6)
+
+
 class lr_orbits(ctypes.Structure):
     _fields_ = [("t0", ctypes.c_double), ("dt", ctypes.c_double), ("n", ctypes.c_int64),
                 ("coef", ctypes.c_void_p), ("L_min", ctypes.c_double),
@@ -243,3 +247,133 @@ def loglike(h, data, sigma, want_grad=True, out=None, g_h=None, work=None, strea
                             _dev(out, "loglike"), _opt(g_h if want_grad else None, "g_h"),
                             _dev(work, "work"), work.numel() * 8, _stream(stream)), "lr_loglike")
     return out, (g_h if want_grad else None)
+
+
+# ---------------------------------------------------------------------------
+# Batches (lr_batch_*): many templates sharing one output time grid
+# ---------------------------------------------------------------------------
+
+class lr_template(ctypes.Structure):
+    _fields_ = [("h_offset", ctypes.c_int64), ("n_h", ctypes.c_int64),
+                ("out_start", ctypes.c_int64), ("n_out", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64)]
+
+
+class lr_batch(ctypes.Structure):
+    _fields_ = [("proj", lr_orbits), ("tdi", lr_orbits), ("t0", ctypes.c_double),
+                ("dt", ctypes.c_double), ("order", ctypes.c_int), ("generation", ctypes.c_int),
+                ("channels", ctypes.c_int), ("group", ctypes.c_int), ("front", ctypes.c_int),
+                ("tile_out", ctypes.c_int), ("blocks", ctypes.c_int), ("adjoint", ctypes.c_int),
+                ("n_templates", ctypes.c_int64), ("n_items", ctypes.c_int64),
+                ("n_tdi_items", ctypes.c_int64), ("n_proj_items", ctypes.c_int64),
+                ("n_like_items", ctypes.c_int64), ("gy_doubles", ctypes.c_int64),
+                ("h_extent", ctypes.c_int64), ("out_extent", ctypes.c_int64),
+                ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 12)]
+
+
+def _batch_lib():
+    L = lib()
+    if getattr(L, "_batch_ready", False):
+        return L
+    d, i32, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    P = ctypes.POINTER
+    pt, po, pb = P(lr_template), P(lr_orbits), P(lr_batch)
+    L.lr_batch_workspace.restype = ctypes.c_size_t
+    L.lr_batch_workspace.argtypes = [pt, i64, po, d, i32, i32, i32, i32, i32]
+    L.lr_batch_prepare.argtypes = [pt, i64, po, po, d, d, i32, i32, i32, i32, i32, vp,
+                                   ctypes.c_size_t, pb, vp]
+    L.lr_response.argtypes = [pb, vp, vp, vp, vp, vp]
+    L.lr_response_adjoint.argtypes = [pb, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.lr_batch_loglike.argtypes = [pb, vp, vp, d, vp, vp, vp]
+    for name in ("lr_batch_prepare", "lr_response", "lr_response_adjoint", "lr_batch_loglike"):
+        getattr(L, name).restype = i32
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """A prepared batch (lr_batch_prepare) and its device workspace.
+
+    ``templates``: sequence of (h_offset, n_h, out_start, n_out, out_offset).
+    The orbit objects must outlive the batch (it holds their device pointers).
+    """
+
+    def __init__(self, templates, orb_proj: Orbits, orb_tdi: Orbits, t0, dt, order=25,
+                 generation=2, channels="XYZ", group=2, adjoint=False, device="cuda",
+                 stream=None):
+        import torch
+        L = _batch_lib()
+        n = len(templates)
+        arr = (lr_template * max(n, 1))()
+        for k, t in enumerate(templates):
+            arr[k] = lr_template(*[int(v) for v in t])
+        self.templates = [tuple(int(v) for v in t) for t in templates]
+        self.orb_proj, self.orb_tdi = orb_proj, orb_tdi
+        self.channels = channels
+        self.rows = 6 if channels == "XYZAET" else 3
+        nbytes = L.lr_batch_workspace(arr, n, orb_tdi.ref, float(dt), int(order), int(generation),
+                                      CHANNELS[channels], int(group), int(bool(adjoint)))
+        if nbytes == 0:
+            raise LisaRespError(1, "lr_batch_workspace", L.lr_last_error().decode())
+        self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+        self.c = lr_batch()
+        _check(L.lr_batch_prepare(arr, n, orb_proj.ref, orb_tdi.ref, float(t0), float(dt),
+                                  int(order), int(generation), CHANNELS[channels], int(group),
+                                  int(bool(adjoint)), ctypes.c_void_p(self.ws.data_ptr()),
+                                  self.ws.numel() * 8, ctypes.byref(self.c), _stream(stream)),
+               "lr_batch_prepare")
+
+    @property
+    def n(self):
+        return len(self.templates)
+
+    @property
+    def h_extent(self):
+        return int(self.c.h_extent)
+
+    @property
+    def out_extent(self):
+        return int(self.c.out_extent)
+
+    def response(self, hp, hc, sky, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(self.out_extent, 1), dtype=torch.float64, device=hp.device)
+        _check(_batch_lib().lr_response(ctypes.byref(self.c), _dev(hp, "hp"), _dev(hc, "hc"),
+                                        _dev(sky, "sky"), _dev(out, "out"), _stream(stream)),
+               "lr_response")
+        return out
+
+    def adjoint(self, hp, hc, sky, g_out, want_sky=True, g_hp=None, g_hc=None, g_sky=None,
+                stream=None):
+        import torch
+        dev = g_out.device
+        if g_hp is None:
+            g_hp = torch.empty(max(self.h_extent, 1), dtype=torch.float64, device=dev)
+        if g_hc is None:
+            g_hc = torch.empty(max(self.h_extent, 1), dtype=torch.float64, device=dev)
+        if want_sky and g_sky is None:
+            g_sky = torch.empty((max(self.n, 1), 2), dtype=torch.float64, device=dev)
+        _check(_batch_lib().lr_response_adjoint(
+            ctypes.byref(self.c), _opt(hp, "hp"), _opt(hc, "hc"), _dev(sky, "sky"),
+            _dev(g_out, "g_out"), _dev(g_hp, "g_hp"), _dev(g_hc, "g_hc"),
+            _opt(g_sky if want_sky else None, "g_sky"), _stream(stream)), "lr_response_adjoint")
+        return g_hp, g_hc, (g_sky if want_sky else None)
+
+    def loglike(self, out, data, sigma, want_grad=True, ll=None, g_out=None, stream=None):
+        import torch
+        dev = out.device
+        if ll is None:
+            ll = torch.empty(max(self.n, 1), dtype=torch.float64, device=dev)
+        if want_grad and g_out is None:
+            g_out = torch.zeros_like(out)
+        _check(_batch_lib().lr_batch_loglike(
+            ctypes.byref(self.c), _dev(out, "out"), _dev(data, "data"), float(sigma),
+            _dev(ll, "loglike"), _opt(g_out if want_grad else None, "g_out"), _stream(stream)),
+            "lr_batch_loglike")
+        return ll, (g_out if want_grad else None)
+
+    def output_block(self, out, k):
+        """View of template k's [rows][n_out] output block."""
+        _, _, _, n_out, off = self.templates[k]
+        return out[off:off + self.rows * n_out].view(self.rows, n_out)

@@ -1,0 +1,59 @@
+"""Kernel driver for rocprofv3 runs (kernel traces and hardware counters).
+
+    python -m paper_2204_06633_amd.profiling --what forward --reps 5
+    python -m paper_2204_06633_amd.profiling --what adjoint --reps 5
+    python -m paper_2204_06633_amd.profiling --what copy --copy-mib 1024
+
+``forward`` runs the per-template forward (projection + TDI-2 XYZ+AET) on the
+1-yr, dt = 10 s, order-25 Keplerian workload; ``adjoint`` adds the adjoint
+pair; ``copy`` runs one device-to-device copy of known size (the reference
+for scaling the HBM byte counters).  Each step prints a line so a profiler
+run shows progress.
+"""
+from __future__ import annotations
+
+import argparse
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--what", choices=["forward", "adjoint", "copy"], default="forward")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.what == "copy":
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for r in range(args.reps):
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            print("copy %d: %d bytes read, %d written" % (r, 8 * n, 8 * n), flush=True)
+        return
+
+    from . import native, response, workloads
+    case = workloads.config_c2("XYZAET")
+    g = case.grid
+    orb = native.Orbits.from_samples(case.orbits_proj, device=dev)
+    tpl = response.Template(orb, orb, g, case.order, case.generation, case.channels)
+    hp = torch.tensor(case.hp, dtype=torch.float64, device=dev)
+    hc = torch.tensor(case.hc, dtype=torch.float64, device=dev)
+    sky = torch.tensor([case.lam, case.beta], dtype=torch.float64, device=dev)
+    y = torch.empty((6, g.n_y), dtype=torch.float64, device=dev)
+    out = torch.empty((6, g.n_out), dtype=torch.float64, device=dev)
+    g_out = torch.ones_like(out)
+    for r in range(args.reps):
+        response.plain_forward(tpl, hp, hc, sky, y=y, out=out)
+        if args.what == "adjoint":
+            response.plain_adjoint(tpl, hp, hc, sky, g_out)
+        torch.cuda.synchronize()
+        print("%s step %d done (%d samples)" % (args.what, r, g.n_out), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

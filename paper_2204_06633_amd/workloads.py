@@ -65,3 +65,61 @@ def config_c1():
 def config_c2(channels="XYZAET"):
     return make_case("c2_year_keplerian_tdi2", "keplerian", int(round(inputs.YEAR / 10.0)), 10.0,
                      25, 2, channels, seed=2)
+
+
+@dataclasses.dataclass
+class BatchLayout:
+    """Templates laid out one after the other in shared h+ / hx / output
+    arrays (offsets in elements)."""
+    grids: list
+    h_offsets: list
+    out_offsets: list
+    rows: int
+
+    @property
+    def n_h_total(self):
+        return self.h_offsets[-1] + self.grids[-1].n_h if self.grids else 0
+
+    @property
+    def n_out_total(self):
+        return self.out_offsets[-1] + self.rows * self.grids[-1].n_out if self.grids else 0
+
+    def templates(self):
+        return [(ho, g.n_h, g.out_start, g.n_out, oo)
+                for g, ho, oo in zip(self.grids, self.h_offsets, self.out_offsets)]
+
+
+def batch_layout(grids, rows):
+    h_off, o_off, h, o = [], [], 0, 0
+    for g in grids:
+        h_off.append(h)
+        o_off.append(o)
+        h += g.n_h
+        o += rows * g.n_out
+    return BatchLayout(list(grids), h_off, o_off, rows)
+
+
+def make_batch(n_templates, orbit_kind, n_out_list, dt, order, generation, seed, t_start=1.0e6,
+               tdi_orbit_kind=None, params=None):
+    """A batch of templates sharing the output start time t_start and the
+    orbits, with per-template durations ``n_out_list`` and seeded source
+    parameters (or ``params`` [n][8]).  Returns (layout, params, orbits_proj,
+    orbits_tdi)."""
+    rng = np.random.default_rng(seed)
+    if params is None:
+        params = inputs.draw_gb_params(rng, n_templates)
+    n_max = int(max(n_out_list)) if len(n_out_list) else 0
+    t_end = t_start + n_max * dt
+    orb_p = inputs.make_orbit_samples(orbit_kind, t_start, t_end)
+    orb_t = orb_p if tdi_orbit_kind in (None, orbit_kind) else \
+        inputs.make_orbit_samples(tdi_orbit_kind, t_start, t_end)
+    grids = []
+    for n in n_out_list:
+        g = inputs.make_template_grid(orb_p, order, dt, t_start, int(n), generation)
+        g2 = inputs.make_template_grid(orb_t, order, dt, t_start, int(n), generation)
+        # a few samples beyond the generous estimate, so the library's own
+        # bound always fits inside
+        g.front_tdi = max(g.front_tdi, g2.front_tdi) + 4
+        g.back_tdi = max(g.back_tdi, g2.back_tdi) + 4
+        grids.append(g)
+    return grids, np.asarray(params, dtype=np.float64), orb_p, orb_t

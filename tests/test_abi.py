@@ -143,3 +143,76 @@ def test_orbits_init_rejects_bad_input_on_host():
     x[2, 1, 1] = np.nan
     assert L.lr_orbits_init(0.0, 1e4, 5, x.ctypes.data, lt.ctypes.data, dummy, 10 ** 6,
                             ctypes.byref(out), None) == 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the header's structs: sizes and field offsets as a C
+    compiler lays them out."""
+    import subprocess
+    structs = {"lr_orbits": native.lr_orbits, "lr_template": native.lr_template,
+               "lr_batch": native.lr_batch}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lisaresp.h"',
+             'int main(void) {']
+    for name, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
+        for f in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, f[0], name, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
+                                                         text=True, check=True).stdout.split("\n")
+               if l)
+    for name, cls in structs.items():
+        assert int(got["%s size" % name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got["%s %s" % (name, f[0])]) == getattr(cls, f[0]).offset, (name, f[0])
+
+
+def _batch_templates(rows=3):
+    """Three templates (700, 0 and 300 outputs) with 300 h samples of padding
+    on each side, laid out one after the other."""
+    from paper_2204_06633_amd import inputs
+    sp = inputs.make_orbit_samples("keplerian", 1.0e6, 1.0e6 + 1e4)
+    tpl, ho, oo = [], 0, 0
+    for n in (700, 0, 300):
+        tpl.append((ho, n + 600, 300, n, oo))
+        ho += n + 600
+        oo += rows * n
+    arr = (native.lr_template * 3)(*[native.lr_template(*t) for t in tpl])
+    return arr, tpl, sp
+
+
+def test_batch_workspace_and_rejections():
+    L = native._batch_lib()
+    arr, tpl, sp = _batch_templates()
+    o = _fake_orbits(n=sp.n, dt=sp.dt, t0=sp.t0)
+    nb = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, native.CHANNELS["AET"], 2, 1)
+    assert nb > 0 and nb % 256 == 0
+    nb0 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, native.CHANNELS["AET"], 2, 0)
+    assert 0 < nb0 < nb                       # the adjoint adds the link-gradient scratch
+    # unsupported group size, order, channels; dt too small for a tile
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 3, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 24, 2, 1, 2, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 7, 2, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 0.05, 25, 2, 1, 2, 0) == 0
+    assert b"too small" in L.lr_last_error()
+    # prepare rejects bad h coverage, overlapping outputs and a short workspace
+    # before any device work
+    b = native.lr_batch()
+    bad = (native.lr_template * 3)(*[native.lr_template(*t) for t in tpl])
+    bad[0].n_h = 10
+    assert L.lr_batch_prepare(bad, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
+                              1, 2, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
+                              None) == native.LR_E_RANGE
+    bad = (native.lr_template * 3)(*[native.lr_template(*t) for t in tpl])
+    bad[2].out_offset = 5
+    assert L.lr_batch_prepare(bad, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
+                              1, 2, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
+                              None) == native.LR_E_ARG
+    assert L.lr_batch_prepare(arr, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
+                              1, 2, 0, ctypes.c_void_p(0x1000), 64, ctypes.byref(b),
+                              None) == native.LR_E_WORKSPACE

@@ -1,0 +1,172 @@
+"""GPU parity of the batched response (fused persistent forward, batched
+adjoint and likelihood, graph capture) against the oracle and the
+per-template GPU path."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_06633_amd import inputs, workloads
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _t(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _build(torch, n_out_list, order=25, gen=2, channels="AET", group=2, adjoint=False, seed=3,
+           dt=10.0, tdi_orbit_kind=None):
+    from paper_2204_06633_amd import native
+    grids, params, sp, st = workloads.make_batch(len(n_out_list), "keplerian", n_out_list, dt,
+                                                 order, gen, seed, tdi_orbit_kind=tdi_orbit_kind)
+    rows = 6 if channels == "XYZAET" else 3
+    lay = workloads.batch_layout(grids, rows)
+    hp = np.zeros(max(lay.n_h_total, 1))
+    hc = np.zeros(max(lay.n_h_total, 1))
+    for g, ho, p in zip(grids, lay.h_offsets, params):
+        a, b = inputs.gb_polarizations(p, g.waveform_times())
+        hp[ho:ho + g.n_h] = a
+        hc[ho:ho + g.n_h] = b
+    gp = native.Orbits.from_samples(sp)
+    gt = gp if st is sp else native.Orbits.from_samples(st)
+    batch = native.Batch(lay.templates(), gp, gt, grids[0].t_start, dt, order, gen, channels,
+                         group=group, adjoint=adjoint)
+    sky = np.ascontiguousarray(params[:, 6:8])
+    return dict(batch=batch, lay=lay, grids=grids, params=params, sp=sp, st=st, hp=hp, hc=hc,
+                sky=sky, orbs=(gp, gt), order=order, gen=gen, channels=channels)
+
+
+def _oracle_out(B, k):
+    g = B["grids"][k]
+    ho = B["lay"].h_offsets[k]
+    p = B["params"][k]
+    op = oracle.Orbits.from_samples(B["sp"])
+    ot = op if B["st"] is B["sp"] else oracle.Orbits.from_samples(B["st"])
+    return oracle.response(op, ot, g, B["hp"][ho:ho + g.n_h], B["hc"][ho:ho + g.n_h], p[6], p[7],
+                           B["order"], B["gen"], B["channels"])
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+@pytest.mark.parametrize("gen,channels", [(2, "AET"), (1, "XYZ"), (2, "XYZAET")])
+def test_fused_forward_matches_oracle(torch_cuda, group, gen, channels):
+    torch = torch_cuda
+    n_out_list = [1500, 0, 977, 1, 2100, 480, 481, 1200, 33]
+    B = _build(torch, n_out_list, gen=gen, channels=channels, group=group, seed=group + 10 * gen)
+    out = B["batch"].response(_t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"]))
+    torch.cuda.synchronize()
+    for k, n in enumerate(n_out_list):
+        if n == 0:
+            continue
+        got = B["batch"].output_block(out, k).cpu().numpy()
+        assert cases.rel_err(got, _oracle_out(B, k)) <= TOL, (k, n)
+
+
+def test_fused_forward_hybrid_orbits_and_order(torch_cuda):
+    """Keplerian projection with rigid equal-arm TDI (the paper's hybrid
+    template, Sec. V), order 9, dt = 15 s."""
+    torch = torch_cuda
+    n_out_list = [900, 1300, 640]
+    B = _build(torch, n_out_list, order=9, group=2, dt=15.0, tdi_orbit_kind="rigid", seed=21)
+    out = B["batch"].response(_t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"]))
+    torch.cuda.synchronize()
+    for k in range(len(n_out_list)):
+        got = B["batch"].output_block(out, k).cpu().numpy()
+        assert cases.rel_err(got, _oracle_out(B, k)) <= TOL
+
+
+def test_batch_adjoint_and_loglike(torch_cuda):
+    """Batched adjoint against the per-template GPU adjoint and the oracle;
+    batched likelihood against the oracle."""
+    torch = torch_cuda
+    from paper_2204_06633_amd import native, response
+    n_out_list = [1100, 700, 0, 1500]
+    B = _build(torch, n_out_list, group=2, adjoint=True, seed=5)
+    batch = B["batch"]
+    hp, hc, sky = _t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"])
+    out = batch.response(hp, hc, sky)
+    rng = np.random.default_rng(1)
+    data = out.cpu().numpy() + 1e-24 * rng.standard_normal(out.shape)
+    ll, g_out = batch.loglike(out, _t(torch, data), 1e-24)
+    ghp, ghc, gsky = batch.adjoint(hp, hc, sky, g_out)
+    torch.cuda.synchronize()
+    gp, gt = B["orbs"]
+    for k, n in enumerate(n_out_list):
+        g = B["grids"][k]
+        ho, oo = B["lay"].h_offsets[k], B["lay"].out_offsets[k]
+        blk = slice(oo, oo + 3 * n)
+        ref_ll = oracle.loglike(out.cpu().numpy()[blk], data[blk], 1e-24)
+        assert abs(float(ll[k]) - ref_ll) <= 1e-12 * max(abs(ref_ll), 1.0)
+        if n == 0:
+            assert float(ll[k]) == 0.0 and float(gsky[k, 0]) == 0.0
+            continue
+        tpl = response.Template(gp, gt, g, 25, 2, "AET")
+        hk, ck = hp[ho:ho + g.n_h].contiguous(), hc[ho:ho + g.n_h].contiguous()
+        gk = g_out[blk].view(3, n).contiguous()
+        rhp, rhc, rsky = response.plain_adjoint(tpl, hk, ck, sky[k].contiguous(), gk)
+        got = np.stack([ghp[ho:ho + g.n_h].cpu().numpy(), ghc[ho:ho + g.n_h].cpu().numpy()])
+        ref = np.stack([rhp.cpu().numpy(), rhc.cpu().numpy()])
+        assert cases.rel_err(got, ref) <= 1e-12
+        assert np.allclose(gsky[k].cpu().numpy(), rsky.cpu().numpy(), rtol=1e-12, atol=0)
+    # one template against the oracle transpose
+    k = 0
+    g = B["grids"][k]
+    ho, oo, n = B["lay"].h_offsets[k], B["lay"].out_offsets[k], n_out_list[k]
+    op = oracle.Orbits.from_samples(B["sp"])
+    rhp, rhc = oracle.response_adjoint(op, op, g, B["params"][k][6], B["params"][k][7], 25, 2,
+                                       g_out[oo:oo + 3 * n].view(3, n).cpu().numpy(), "AET")
+    got = np.stack([ghp[ho:ho + g.n_h].cpu().numpy(), ghc[ho:ho + g.n_h].cpu().numpy()])
+    assert cases.rel_err(got, np.stack([rhp, rhc])) <= 1e-10
+
+
+def test_graph_capture_replays_match_eager(torch_cuda):
+    """Forward, likelihood and adjoint captured in one HIP graph; replays with
+    new sky angles and new polarisations match eager calls each time."""
+    torch = torch_cuda
+    n_out_list = [1300, 800, 1000]
+    B = _build(torch, n_out_list, group=2, adjoint=True, seed=9)
+    batch = B["batch"]
+    hp, hc, sky = _t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"])
+    out = torch.empty(batch.out_extent, dtype=torch.float64, device="cuda")
+    data = torch.zeros_like(out)
+    ll = torch.empty(batch.n, dtype=torch.float64, device="cuda")
+    g_out = torch.zeros_like(out)
+    ghp = torch.empty(batch.h_extent, dtype=torch.float64, device="cuda")
+    ghc = torch.empty_like(ghp)
+    gsky = torch.empty((batch.n, 2), dtype=torch.float64, device="cuda")
+
+    def step():
+        batch.response(hp, hc, sky, out=out)
+        batch.loglike(out, data, 1e-21, ll=ll, g_out=g_out)
+        batch.adjoint(hp, hc, sky, g_out, g_hp=ghp, g_hc=ghc, g_sky=gsky)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()                                    # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    rng = np.random.default_rng(4)
+    for r in range(4):
+        sky.copy_(_t(torch, B["sky"] + 1e-3 * rng.standard_normal(B["sky"].shape)))
+        hp.mul_(1.0 + 0.1 * r)
+        data.copy_(out * 0.5)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        snap = [x.clone() for x in (out, ll, ghp, ghc, gsky)]
+        step()                                    # eager on the same inputs
+        torch.cuda.synchronize()
+        for a, b in zip(snap, (out, ll, ghp, ghc, gsky)):
+            assert torch.allclose(a, b, rtol=1e-12, atol=0), r

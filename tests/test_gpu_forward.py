@@ -172,3 +172,38 @@ def test_non_finite_sky_stays_in_bounds(torch_cuda):
                              _t(torch, [float("nan"), 0.3]), 25, g.y_start, g.n_y)
     torch.cuda.synchronize()
     assert torch.isnan(y).all()
+
+
+def test_fast_varying_delays_exercise_misaligned_windows(torch_cuda):
+    """Light times that change by ~1e-4 s per second make the two samples of
+    a lane straddle integer positions in many waves, which takes the
+    separate-window branch of both kernels; results must not change."""
+    torch = torch_cuda
+    from paper_2204_06633_amd import native, response
+    t0, dto, n = 0.0, 1e4, 40
+    tk = t0 + dto * np.arange(n)
+    pos = inputs.keplerian_orbits(tk)
+    base = np.array([8.21, 8.47, 8.05, 8.36, 8.12, 8.58])
+    ltt = base[None, :] + 0.6 * np.sin(2 * math.pi * tk[:, None] / 7e4 + np.arange(6)[None, :])
+    s = inputs.OrbitSamples(t0, dto, pos, ltt)
+    case = cases.make_case("fast", "keplerian", 20000, 1.0, 25, 2, "XYZ", seed=17,
+                           t_start=5e4)
+    grid = inputs.make_template_grid(s, 25, 1.0, 5e4, 20000, 2)
+    grid.front_tdi += 16                        # the spline bound of fast light times is loose
+    case = cases.Case(case.name, s, s, grid, case.params, None, None, 25, 2, "XYZAET")
+    case.hp, case.hc = inputs.gb_polarizations(case.params, case.grid.waveform_times())
+    got = _gpu_response(torch, case)
+    orb = oracle.Orbits.from_samples(s)
+    ref = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta, 25, 2,
+                          "XYZAET")
+    assert cases.rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("n_out", [511, 512, 513, 1025])
+def test_tile_boundaries(torch_cuda, n_out):
+    case = cases.make_case("tiles", "keplerian", n_out, 10.0, 11, 2, "XYZAET", seed=n_out)
+    got = _gpu_response(torch_cuda, case)
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    ref = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta, case.order,
+                          case.generation, case.channels)
+    assert cases.rel_err(got, ref) <= TOL
