@@ -12,7 +12,18 @@ on the launch stream, the roofline of the dominant kernel (FP64 vector ALU),
 algorithmic HBM bandwidth, a sampled parity check against the CPU oracle and
 the oracle's own throughput on a bounded sample on the host cores.
 
+Beside the headline it reports, in the same line:
+  fwd_adjoint          the same template, forward + likelihood + adjoint
+                       (gradients to h+, hx and the sky angles) per step;
+  batched_forward      512 templates of uneven durations (0.25-1 yr at
+                       dt = 10 s) in one persistent fused launch, replayed
+                       from a HIP graph, autotuned, against the plain
+                       per-template forward on templates of the same batch;
+  batched_fwd_adjoint  256 walkers, 1 yr at dt = 15 s, hybrid orbits:
+                       forward + likelihood + adjoint in one HIP graph.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-batch]
 """
 from __future__ import annotations
 
@@ -83,6 +94,177 @@ def cpu_baseline(case, target_s=10.0):
             "sample": "%d contiguous output samples of the same 1-yr template (%.1f s)" % (m, el)}
 
 
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _timed(fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls after `warmup`, from HIP
+    events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = _events(steps + 1)
+    ev[0].record()
+    for k in range(steps):
+        fn()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+def _batch_parity(bc, k_list, hp, hc, out, batch, n_samples=48):
+    """Joint relative error of sampled outputs of templates k_list against the
+    oracle fed with the same (device-generated) polarisations."""
+    import torch
+
+    import oracle
+    from paper_2204_06633_amd import workloads
+    from tests import cases
+    op = oracle.Orbits.from_samples(bc.orbits_proj)
+    ot = op if bc.orbits_tdi is bc.orbits_proj else oracle.Orbits.from_samples(bc.orbits_tdi)
+    worst = 0.0
+    for k in k_list:
+        g = bc.grids[k]
+        ho = bc.layout.h_offsets[k]
+        case = workloads.Case("batch%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
+                              hp[ho:ho + g.n_h].cpu().numpy(), hc[ho:ho + g.n_h].cpu().numpy(),
+                              bc.order, bc.generation, bc.channels)
+        idx = cases.sample_indices(g.n_out, n_samples, seed=1000 + k, edge=2)
+        ref = cases.oracle_sampled_response(op, ot, case, idx)
+        got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(out.device)].cpu().numpy()
+        worst = max(worst, cases.rel_err(got, ref))
+    return worst
+
+
+def bench_batched_forward(steps, warmup, log):
+    """512 uneven templates, fused forward from a captured graph; the plain
+    per-template forward timed on 8 of the same templates."""
+    import numpy as np
+    import torch
+
+    from paper_2204_06633_amd import autotune, costs, native, response, workloads
+    dev = torch.device("cuda:0")
+    bc = workloads.config_c3()
+    log("batched forward: %s, %d templates, %d samples" % (bc.name, len(bc.grids), bc.n_samples))
+    orb = native.Orbits.from_samples(bc.orbits_proj, device=dev)
+    hp, hc = workloads.device_polarizations(bc, dev)
+    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    tpl = bc.layout.templates()
+    batch, tuned = autotune.tuned_batch(tpl, orb, orb, bc.t0, bc.dt, bc.order, bc.generation,
+                                        bc.channels, hp, hc, sky)
+    log("autotuned: group %d, grid x%.1f (%d work-groups)" % (tuned["group"],
+                                                             tuned["grid_scale"], batch.blocks))
+    out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.response(hp, hc, sky, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.response(hp, hc, sky, out=out)
+    ms = _timed(graph.replay, steps, warmup)
+    n = bc.n_samples
+    err = _batch_parity(bc, [0, len(bc.grids) // 2, len(bc.grids) - 1], hp, hc, out, batch)
+
+    # plain per-template forward (project_links then tdi_combine) on 8 templates
+    pick = list(range(0, len(bc.grids), len(bc.grids) // 8))[:8]
+    n_plain, ms_plain = 0, 0.0
+    for k in pick:
+        g = bc.grids[k]
+        ho = bc.layout.h_offsets[k]
+        t = response.Template(orb, orb, g, bc.order, bc.generation, bc.channels)
+        hk, ck = hp[ho:ho + g.n_h], hc[ho:ho + g.n_h]
+        y = torch.empty((6, g.n_y), dtype=torch.float64, device=dev)
+        o = torch.empty((3, g.n_out), dtype=torch.float64, device=dev)
+        ms_plain += _timed(lambda: response.plain_forward(t, hk, ck, sky[k], y=y, out=o),
+                           max(2, steps // 2), 1)
+        n_plain += g.n_out
+    plain_rate = 6.0 * n_plain / (ms_plain * 1e-3)
+    rate = 6.0 * n / (ms * 1e-3)
+    f = sum(costs.tdi_flops_per_sample(bc.order, bc.generation, bc.channels) * g.n_out +
+            costs.projection_flops_per_sample(bc.order) * g.n_y for g in bc.grids)
+    b = sum(costs.tdi_bytes_per_sample(bc.channels) * g.n_out for g in bc.grids) + \
+        sum(16.0 * g.n_y for g in bc.grids)
+    del graph, out, hp, hc
+    return {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
+            "value": rate, "unit": "samples/s (templates×links×time)", "ms_per_step": ms,
+            "steps": steps, "graph": True, "group": tuned["group"],
+            "grid_scale": tuned["grid_scale"], "blocks": batch.blocks,
+            "alu_frac": f / (ms * 1e-3) / costs.FP64_VECTOR_PEAK,
+            "hbm_frac": b / (ms * 1e-3) / costs.HBM_PEAK,
+            "plain_per_template": {"value": plain_rate, "templates_timed": len(pick),
+                                   "speedup": rate / plain_rate},
+            "parity": {"rel_err": err, "templates": 3, "tolerance": 1e-11}}
+
+
+def bench_batched_fwd_adjoint(steps, warmup, log):
+    """256 walkers: forward + likelihood + adjoint (with sky gradient) in one
+    captured graph."""
+    import torch
+
+    from paper_2204_06633_amd import autotune, costs, native, workloads
+    dev = torch.device("cuda:0")
+    bc = workloads.config_c5()
+    log("batched fwd+adjoint: %s, %d walkers, %d samples" % (bc.name, len(bc.grids),
+                                                            bc.n_samples))
+    orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
+    orb_t = native.Orbits.from_samples(bc.orbits_tdi, device=dev)
+    hp, hc = workloads.device_polarizations(bc, dev)
+    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    tpl = bc.layout.templates()
+    tuned = autotune.tune(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                          hp, hc, sky)
+    batch = native.Batch(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                         group=tuned["group"], adjoint=True, device=dev)
+    batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
+    out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
+    # data: walker 0's response plus white noise (sigma = 1e-21), one copy per walker block
+    batch.response(hp, hc, sky, out=out)
+    sigma = 1e-21
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    blk = batch.output_block(out, 0).reshape(-1)
+    one = blk + sigma * torch.randn(blk.shape, dtype=torch.float64, device=dev, generator=gen)
+    data = one.repeat(len(bc.grids))
+    del one
+    ll = torch.empty(batch.n, dtype=torch.float64, device=dev)
+    g_out = torch.empty_like(out)
+    ghp = torch.empty(batch.h_extent, dtype=torch.float64, device=dev)
+    ghc = torch.empty_like(ghp)
+    gsky = torch.empty((batch.n, 2), dtype=torch.float64, device=dev)
+
+    def step():
+        batch.response(hp, hc, sky, out=out)
+        batch.loglike(out, data, sigma, ll=ll, g_out=g_out)
+        batch.adjoint(hp, hc, sky, g_out, g_hp=ghp, g_hc=ghc, g_sky=gsky)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    ms = _timed(graph.replay, steps, warmup)
+    ms_fwd = _timed(lambda: batch.response(hp, hc, sky, out=out), steps, 1)
+    err = _batch_parity(bc, [0, len(bc.grids) - 1], hp, hc, out, batch)
+    n = bc.n_samples
+    finite = bool(torch.isfinite(ll).all()) and bool(torch.isfinite(gsky).all())
+    del graph, out, data, g_out, ghp, ghc, hp, hc
+    return {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
+            "value": 6.0 * n / (ms * 1e-3), "unit": "samples/s (templates×links×time)",
+            "ms_per_step": ms, "forward_only_ms": ms_fwd, "steps": steps, "graph": True,
+            "group": tuned["group"], "gradients_finite": finite,
+            "parity_forward": {"rel_err": err, "templates": 2, "tolerance": 1e-11}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +272,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batch", action="store_true", help="headline workload only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the response runs on one MI355X; "
@@ -148,6 +331,25 @@ def main():
     ref = cases.oracle_sampled_response(o, o, case, idx)
     err = cases.rel_err(out[:, torch.from_numpy(idx).to(dev)].cpu().numpy(), ref)
 
+    def log(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
+    # forward + likelihood + adjoint of the same template
+    tpl = response.Template(orb, orb, g, case.order, case.generation, case.channels)
+    # likelihood over A, E, T (rows 3..5); X, Y, Z get no gradient
+    data = out[3:].clone()
+    ll_buf = torch.empty(1, dtype=torch.float64, device=dev)
+    g_buf = torch.zeros_like(out)
+    work = torch.empty(native.lib().lr_loglike_workspace() // 8, dtype=torch.float64, device=dev)
+
+    def fwd_adj():
+        response.plain_forward(tpl, hp, hc, sky, y=y, out=out)
+        native.loglike(out[3:], data, 1e-21, out=ll_buf, g_h=g_buf[3:], work=work)
+        response.plain_adjoint(tpl, hp, hc, sky, g_buf)
+
+    log("forward + adjoint of the same template")
+    ms_fa = _timed(fwd_adj, max(3, args.steps // 2), 1)
+
     n = g.n_out
     value = 6.0 * n / (ms_step * 1e-3)
     f_tdi = costs.tdi_flops_per_sample(case.order, case.generation, case.channels) * n
@@ -189,7 +391,18 @@ def main():
         },
         "hbm_frac_step": (b_tdi + b_proj) / (ms_step * 1e-3) / costs.HBM_PEAK,
         "parity": {"rel_err": err, "samples": int(idx.size), "tolerance": 1e-11},
+        "fwd_adjoint": {"value": 6.0 * n / (ms_fa * 1e-3), "unit": "samples/s (templates×links×time)",
+                        "ms_per_step": ms_fa,
+                        "step": "forward, white-noise likelihood over A/E/T with gradient, "
+                                "adjoint to h+, hx and (lam, beta)"},
     }
+    if not args.no_batch:
+        del y, data, g_buf
+        torch.cuda.empty_cache()
+        result["batched_forward"] = bench_batched_forward(max(3, args.steps // 4), 1, log)
+        torch.cuda.empty_cache()
+        result["batched_fwd_adjoint"] = bench_batched_fwd_adjoint(3, 1, log)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)

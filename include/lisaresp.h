@@ -254,6 +254,12 @@ int lr_response_adjoint(const lr_batch *b, const double *hp, const double *hc,
 int lr_batch_loglike(const lr_batch *b, const double *out, const double *data, double sigma,
                      double *loglike, double *g_out, void *stream);
 
+/* Work-group count of lr_response's persistent launch (the autotuner's grid
+ * knob).  lr_batch_prepare sets it to min(work items, CUs x resident groups
+ * per CU); any value >= 1 is valid, groups beyond the resident ones start
+ * late and find the work list drained.  Errors: LR_E_ARG. */
+int lr_batch_set_grid(lr_batch *b, int blocks);
+
 #ifdef __cplusplus
 }
 #endif

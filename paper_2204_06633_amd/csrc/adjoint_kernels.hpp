@@ -3,12 +3,12 @@
 //   tdi_adjoint_kernel      g_out -> g_y: every delayed term's interpolation
 //                           transposed into a scatter of w_m * g onto the
 //                           stencil taps (Sec. IV.C terms, Sec. IV.E weights)
-//   project_adjoint_kernel  g_y -> g_h+, g_hx (and optionally the gradient with
-//                           respect to the ecliptic sky angles lam, beta)
+//   project_adjoint_kernel  g_y -> g_h+, g_hx
+//   project_sky_kernel      g_y, h+, hx -> partial gradients with respect to
+//                           the ecliptic sky angles lam, beta
 //
-// Scatter strategy: a workgroup owns the same output tile as the forward
-// kernel, accumulates its contributions to its stencil footprint in LDS with
-// FP64 LDS atomics, then adds the footprint to the zero-filled global
+// Scatter strategy: a workgroup owns a tile of samples, accumulates its
+// contributions to its stencil footprint in LDS with FP64 LDS atomics, then adds the footprint to the zero-filled global
 // gradient with FP64 global atomics.  Neighbouring footprints overlap by
 // about one stencil, so a global entry receives at most two tile sums; with a
 // zero-filled destination the result does not depend on their order.
@@ -43,56 +43,38 @@ __device__ __forceinline__ void load_channel_grads(const double* g_out, int chan
 // ---------------------------------------------------------------------------
 // TDI adjoint
 // ---------------------------------------------------------------------------
-template <int N, int GEN, int G, bool LDS>
-__device__ __forceinline__ void scatter_group(const double (&L)[6], double inv_dt, double* lds,
-                                              int lds_stride, int c0, double* gy, int64_t n_y,
-                                              int64_t p, const double (&gch)[3]) {
-  constexpr int H = N / 2;
-  constexpr DelayGroup grp = TdiTab<GEN>::v.group[G];
-  double eps;
-  const int sh = split_delay(delay_of<GEN, G>(L), inv_dt, eps);
-  double w[N];
-  lagrange_weights<N>(eps, w);
+constexpr int kAdjTdiCap(int N) { return kBlock + N + kSlack; }
+
+// Scatter v * w_m onto N consecutive LDS entries dst[0..N-1].
+template <int N>
+__device__ __forceinline__ void scatter_lds(double* dst, const double (&w)[N], double v) {
 #pragma unroll
-  for (int k = 0; k < grp.nuse; ++k) {
-    const double v = (double)grp.use[k].sign * gch[grp.use[k].chan];
-    if constexpr (LDS) {
-      double* dst = lds + grp.use[k].link * lds_stride + (c0 + sh - (H - 1));
-#pragma unroll
-      for (int m = 0; m < N; ++m) atomicAdd(dst + m, w[m] * v);
-    } else {
-      const int64_t j0 = p + sh - (H - 1);
-      double* ys = gy + (int64_t)grp.use[k].link * n_y;
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        int64_t j = j0 + m;
-        j = j < 0 ? 0 : (j > n_y - 1 ? n_y - 1 : j);
-        atomicAdd(ys + j, w[m] * v);
-      }
-    }
+  for (int m = 0; m < N; ++m) atomicAdd(dst + m, w[m] * v);
+}
+
+// Scatter v * w_m(eps) onto ys[j0 + m], indices clamped to [0, n - 1]; a
+// rolled loop computing each weight on its own (rare wide-footprint path).
+template <int N>
+__device__ __forceinline__ void scatter_global(double* ys, int64_t j0, int64_t n, double eps,
+                                               double v) {
+#pragma unroll 1
+  for (int m = 0; m < N; ++m) {
+    int64_t j = j0 + m;
+    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
+    atomicAdd(ys + j, lagrange_weight_at<N>(eps, m) * v);
   }
 }
 
-template <int N, int GEN, bool LDS, int... G>
-__device__ __forceinline__ void scatter_groups(const double (&L)[6], double inv_dt, double* lds,
-                                               int lds_stride, int c0, double* gy, int64_t n_y,
-                                               int64_t p, const double (&gch)[3],
-                                               std::integer_sequence<int, G...>) {
-  (scatter_group<N, GEN, G, LDS>(L, inv_dt, lds, lds_stride, c0, gy, n_y, p, gch), ...);
-}
-
-constexpr int kAdjTdiCap(int N) { return kBlock + N + kSlack; }
-
 // One output tile (kBlock samples) of the TDI adjoint; `acc` and `red` are
-// the workgroup's LDS scratch.
+// the workgroup's LDS scratch.  The delay groups are walked by a runtime
+// loop over the constant-memory table, so one weight set is live at a time.
 template <int N, int GEN>
 __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t tile, double* acc,
                                                  int (&red)[2][kBlock / 64]) {
   constexpr int H = N / 2;
   constexpr int CAP = kAdjTdiCap(N);
-  constexpr int NG = TdiTab<GEN>::v.ngroup;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
-  using Groups = std::make_integer_sequence<int, NG>;
+  const GroupTable<GEN>& GT = group_table<GEN>();
 
   const int tid = threadIdx.x;
   const int64_t i0 = tile * kBlock;
@@ -103,11 +85,10 @@ __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t ti
 
   double L[6];
   light_times(a.orb, a.t_off + (double)p * a.dt, L);
-  double dmin, dmax;
-  delay_range<GEN>(L, dmin, dmax, Groups{});
-  double e_unused;
-  int lo = min(0, split_delay(dmax, a.inv_dt, e_unused) - (H - 1));
-  int hi = max(0, split_delay(dmin, a.inv_dt, e_unused) + H);
+  double dlo, dhi, e_unused;
+  group_delay_bounds(L, GT.chain, dlo, dhi);
+  const int lo = min(0, split_delay(dhi, a.inv_dt, e_unused) - (H - 1));
+  const int hi = max(0, split_delay(dlo, a.inv_dt, e_unused) + H);
   int wlo, whi;
   block_range<kBlock>(rel + lo, rel + hi, red, wlo, whi);
   const int count = whi - wlo + 1;
@@ -125,7 +106,20 @@ __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t ti
       const Direct dr = TdiTab<GEN>::v.direct[t];
       atomicAdd(&acc[dr.link * CAP + c0], (double)dr.sign * gch[dr.chan]);
     }
-    scatter_groups<N, GEN, true>(L, a.inv_dt, acc, CAP, c0, a.g_y, a.n_y, p, gch, Groups{});
+#pragma unroll 1
+    for (int g = 0; g < GT.n; ++g) {
+      const GroupRow& G = GT.row[g];
+      double eps;
+      const int sh = split_delay(row_delay(G, L), a.inv_dt, eps);
+      double w[N];
+      lagrange_weights<N>(eps, w);
+      const int j0 = c0 + sh - (H - 1);
+#pragma unroll 1
+      for (int u = 0; u < G.nuse; ++u) {
+        const double v = G.sgn[u][0] * gch[0] + G.sgn[u][1] * gch[1] + G.sgn[u][2] * gch[2];
+        scatter_lds<N>(acc + G.link[u] * CAP + j0, w, v);
+      }
+    }
     __syncthreads();
     for (int k = tid; k < count; k += kBlock) {
       const int64_t j = base + k;
@@ -134,12 +128,24 @@ __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t ti
       for (int l = 0; l < 6; ++l) atomicAdd(a.g_y + (int64_t)l * a.n_y + j, acc[l * CAP + k]);
     }
   } else {
+    // stencil footprint wider than the LDS tile: scatter to global memory
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
       const Direct dr = TdiTab<GEN>::v.direct[t];
-      atomicAdd(a.g_y + (int64_t)dr.link * a.n_y + p, (double)dr.sign * gch[dr.chan]);
+      if (active) atomicAdd(a.g_y + (int64_t)dr.link * a.n_y + p, (double)dr.sign * gch[dr.chan]);
     }
-    scatter_groups<N, GEN, false>(L, a.inv_dt, acc, CAP, c0, a.g_y, a.n_y, p, gch, Groups{});
+#pragma unroll 1
+    for (int g = 0; g < GT.n; ++g) {
+      const GroupRow& G = GT.row[g];
+      double eps;
+      const int sh = split_delay(row_delay(G, L), a.inv_dt, eps);
+#pragma unroll 1
+      for (int u = 0; u < G.nuse; ++u) {
+        const double v = G.sgn[u][0] * gch[0] + G.sgn[u][1] * gch[1] + G.sgn[u][2] * gch[2];
+        if (active)
+          scatter_global<N>(a.g_y + (int64_t)G.link[u] * a.n_y, p + sh - (H - 1), a.n_y, eps, v);
+      }
+    }
   }
 }
 
@@ -161,116 +167,83 @@ struct ProjAdjShared {
   double s_part[2][kBlock / 64];
 };
 
-// One link-sample tile (kBlock samples) of the projection adjoint; its sky
-// partial pair goes to part[0..1] (if SKY).  acc: 2 * CAP doubles of LDS,
-// win: CAP double2 (SKY only).
-template <int N, bool SKY>
-__device__ __forceinline__ void project_adjoint_tile(const ProjAdjArgs& a, int64_t tile,
-                                                     double* acc, double2* win,
-                                                     ProjAdjShared& sh_, double* part_out) {
-  constexpr int H = N / 2;
-  constexpr int CAP = kAdjProjCap(N);
-  auto& red = sh_.red;
-  auto& s_trig = sh_.s_trig;
-  auto& s_part = sh_.s_part;
-
-  const int tid = threadIdx.x;
-  const int64_t i0 = tile * kBlock;
-  const int64_t i = i0 + tid;
-  const bool active = i < a.n_y;
-  const int rel = active ? tid : (int)(a.n_y - 1 - i0);
-  const int64_t q = a.y_start + i0 + rel;
-
-  const SkyTrig tr = load_sky(a.sky, s_trig);
-  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
-  LinkGeom g;
-  link_geometry(a.orb, a.t_off + (double)q * a.dt, sk, g);
-
+// Per link sample of a tile: geometry, the nine retarded positions split into
+// shift + fraction, and the window of h indices the tile's stencils touch.
+struct ProjAdjSample {
+  bool active;
+  int rel;              // tile-relative link sample (idle lanes mirror the last)
+  int64_t q;            // h index of the link sample
   int sh[9];
   double ep[9];
+};
+
+template <int N>
+__device__ __forceinline__ void proj_adj_sample(const ProjAdjArgs& a, int64_t tile,
+                                                const Sky& sk, LinkGeom& g, ProjAdjSample& s) {
+  const int tid = threadIdx.x;
+  const int64_t i0 = tile * kBlock;
+  s.active = i0 + tid < a.n_y;
+  s.rel = s.active ? tid : (int)(a.n_y - 1 - i0);
+  s.q = a.y_start + i0 + s.rel;
+  link_geometry(a.orb, a.t_off + (double)s.q * a.dt, sk, g);
 #pragma unroll
-  for (int p = 0; p < 9; ++p) sh[p] = split_delay(position_delay(g, p), a.inv_dt, ep[p]);
-  int lo = sh[0], hi = sh[0];
+  for (int p = 0; p < 9; ++p) s.sh[p] = split_delay(position_delay(g, p), a.inv_dt, s.ep[p]);
+}
+
+// One link-sample tile (kBlock samples) of the projection adjoint: the
+// transpose of the nine interpolations, g_y -> g_h+, g_hx.  acc: 2 * CAP
+// doubles of LDS.
+template <int N>
+__device__ __forceinline__ void project_adjoint_tile(const ProjAdjArgs& a, int64_t tile,
+                                                     double* acc, ProjAdjShared& sh_) {
+  constexpr int H = N / 2;
+  constexpr int CAP = kAdjProjCap(N);
+  const int tid = threadIdx.x;
+  const int64_t i0 = tile * kBlock;
+
+  const SkyTrig tr = load_sky(a.sky, sh_.s_trig);
+  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
+  ProjAdjSample S;
+  double amp[2][9];
+  {
+    LinkGeom g;
+    proj_adj_sample<N>(a, tile, sk, g, S);
+    // upstream gradient scaled by 1/(2(1 - k.n)) per link, then the amplitude
+    // each position scatters onto h+ and hx
 #pragma unroll
-  for (int p = 1; p < 9; ++p) { lo = min(lo, sh[p]); hi = max(hi, sh[p]); }
+    for (int s = 0; s < 3; ++s) { amp[0][s] = 0.0; amp[1][s] = 0.0; }
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const double gy = S.active ? a.g_y[(int64_t)l * a.n_y + i0 + tid] : 0.0;
+      const double c = gy / (2.0 * (1.0 - kDir[l] * g.kn[kArm[l]]));
+      const int arm = kArm[l], r = kLinkRecv[l] - 1;
+      amp[0][3 + l] = c * g.xip[arm];
+      amp[1][3 + l] = c * g.xic[arm];
+      amp[0][r] -= c * g.xip[arm];
+      amp[1][r] -= c * g.xic[arm];
+    }
+  }
+  int lo = S.sh[0], hi = S.sh[0];
+#pragma unroll
+  for (int p = 1; p < 9; ++p) { lo = min(lo, S.sh[p]); hi = max(hi, S.sh[p]); }
   int wlo, whi;
-  block_range<kBlock>(rel + lo - (H - 1), rel + hi + H, red, wlo, whi);
+  block_range<kBlock>(S.rel + lo - (H - 1), S.rel + hi + H, sh_.red, wlo, whi);
   const int count = whi - wlo + 1;
   const int64_t base = a.y_start + i0 + wlo;
   const int64_t hmax = a.n_h - 1;
 
-  // Upstream gradient scaled by 1/(2(1 - k.n)) per link, then the amplitude
-  // each of the nine positions scatters onto h+ and hx.
-  double gy[6], c[6];
-#pragma unroll
-  for (int l = 0; l < 6; ++l) {
-    gy[l] = active ? a.g_y[(int64_t)l * a.n_y + i] : 0.0;
-    c[l] = gy[l] / (2.0 * (1.0 - kDir[l] * g.kn[kArm[l]]));
-  }
-  double amp[2][9];
-#pragma unroll
-  for (int s = 0; s < 3; ++s) { amp[0][s] = 0.0; amp[1][s] = 0.0; }
-#pragma unroll
-  for (int l = 0; l < 6; ++l) {
-    const int arm = kArm[l], r = kLinkRecv[l] - 1;
-    amp[0][3 + l] = c[l] * g.xip[arm];
-    amp[1][3 + l] = c[l] * g.xic[arm];
-    amp[0][r] -= c[l] * g.xip[arm];
-    amp[1][r] -= c[l] * g.xic[arm];
-  }
-
-  double hv[2][9], dh[2][9];
-  const bool use_lds = count > 0 && count <= CAP;
-  if (use_lds) {
+  if (count > 0 && count <= CAP) {
     for (int k = tid; k < 2 * CAP; k += kBlock) acc[k] = 0.0;
-    if constexpr (SKY) {
-      for (int k = tid; k < count; k += kBlock) {
-        int64_t j = base + k;
-        j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        win[k] = make_double2(a.hp[j], a.hc[j]);
-      }
-    }
     __syncthreads();
-  }
 #pragma unroll
-  for (int p = 0; p < 9; ++p) {
-    double w[N], dw[N];
-    if constexpr (SKY) lagrange_weights_d<N>(ep[p], w, dw);
-    else lagrange_weights<N>(ep[p], w);
-    const int off = rel + sh[p] - (H - 1) - wlo;
-    const int64_t j0 = q + sh[p] - (H - 1);
-    double sp = 0.0, sc = 0.0, dsp = 0.0, dsc = 0.0;
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      if (use_lds) {
-        atomicAdd(&acc[off + m], amp[0][p] * w[m]);
-        atomicAdd(&acc[CAP + off + m], amp[1][p] * w[m]);
-      } else {
-        int64_t j = j0 + m;
-        j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        atomicAdd(a.g_hp + j, amp[0][p] * w[m]);
-        atomicAdd(a.g_hc + j, amp[1][p] * w[m]);
-      }
-      if constexpr (SKY) {
-        double2 v;
-        if (use_lds) {
-          v = win[off + m];
-        } else {
-          int64_t j = j0 + m;
-          j = j < 0 ? 0 : (j > hmax ? hmax : j);
-          v = make_double2(a.hp[j], a.hc[j]);
-        }
-        sp = fma(w[m], v.x, sp);
-        sc = fma(w[m], v.y, sc);
-        dsp = fma(dw[m], v.x, dsp);
-        dsc = fma(dw[m], v.y, dsc);
-      }
+    for (int p = 0; p < 9; ++p) {
+      double w[N];
+      lagrange_weights<N>(S.ep[p], w);
+      const int off = S.rel + S.sh[p] - (H - 1) - wlo;
+      scatter_lds<N>(acc + off, w, amp[0][p]);
+      scatter_lds<N>(acc + CAP + off, w, amp[1][p]);
+      __builtin_amdgcn_sched_barrier(0);   // one weight set live at a time
     }
-    hv[0][p] = sp; hv[1][p] = sc;
-    dh[0][p] = dsp; dh[1][p] = dsc;
-  }
-
-  if (use_lds) {
     __syncthreads();
     for (int k = tid; k < count; k += kBlock) {
       const int64_t j = base + k;
@@ -278,67 +251,151 @@ __device__ __forceinline__ void project_adjoint_tile(const ProjAdjArgs& a, int64
       atomicAdd(a.g_hp + j, acc[k]);
       atomicAdd(a.g_hc + j, acc[CAP + k]);
     }
-  }
-
-  if constexpr (SKY) {
-    // d y_l / d(k, u, v) contracted with g_y, then with d(k, u, v)/d(lam, beta).
-    double Gk[3] = {0.0, 0.0, 0.0}, Gu[3] = {0.0, 0.0, 0.0}, Gv[3] = {0.0, 0.0, 0.0};
-    const double inv_cdt = a.inv_dt / kC;
+  } else {
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      const int arm = kArm[l], r = kLinkRecv[l] - 1, e = kLinkEmit[l] - 1, pe = 3 + l;
-      const double dir = kDir[l];
-      const double inv = 1.0 / (2.0 * (1.0 - dir * g.kn[arm]));
-      const double dp = hv[0][pe] - hv[0][r], dc = hv[1][pe] - hv[1][r];
-      const double yl = inv * (g.xip[arm] * dp + g.xic[arm] * dc);
-      const double He = g.xip[arm] * dh[0][pe] + g.xic[arm] * dh[1][pe];
-      const double Hr = g.xip[arm] * dh[0][r] + g.xic[arm] * dh[1][r];
-      const double sn = 2.0 * inv * yl * dir;          // through 1/(2(1 - k.n))
-      const double su = 2.0 * inv * (g.un[arm] * dp + g.vn[arm] * dc);
-      const double sv = 2.0 * inv * (g.un[arm] * dc - g.vn[arm] * dp);
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        const double pos = -inv * inv_cdt * (He * g.x[e][cc] - Hr * g.x[r][cc]);
-        Gk[cc] = fma(gy[l], fma(sn, g.n[arm][cc], pos), Gk[cc]);
-        Gu[cc] = fma(gy[l], su * g.n[arm][cc], Gu[cc]);
-        Gv[cc] = fma(gy[l], sv * g.n[arm][cc], Gv[cc]);
-      }
-    }
-    const SkyDeriv D = sky_derivatives(tr.sl, tr.cl, tr.sb, tr.cb);
-    double part[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      double s = 0.0;
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-        s += Gk[cc] * D.dk[t][cc] + Gu[cc] * D.du[t][cc] + Gv[cc] * D.dv[t][cc];
-      part[t] = s;
-    }
-    // deterministic block reduction -> one partial pair per workgroup
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) part[t] += __shfl_xor(part[t], o, 64);
-    }
-    if ((tid & 63) == 0) { s_part[0][tid >> 6] = part[0]; s_part[1][tid >> 6] = part[1]; }
-    __syncthreads();
-    if (tid == 0) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int w = 0; w < kBlock / 64; ++w) { s0 += s_part[0][w]; s1 += s_part[1][w]; }
-      part_out[0] = s0;
-      part_out[1] = s1;
+    for (int p = 0; p < 9; ++p) {
+      const int64_t j0 = S.q + S.sh[p] - (H - 1);
+      scatter_global<N>(a.g_hp, j0, a.n_h, S.ep[p], amp[0][p]);
+      scatter_global<N>(a.g_hc, j0, a.n_h, S.ep[p], amp[1][p]);
     }
   }
 }
 
-template <int N, bool SKY>
+// One link-sample tile of the sky gradient: sum over links and samples of
+// g_y * d y / d(lam, beta), from the interpolated h+, hx at the nine
+// positions and their derivatives with respect to the position (streamed,
+// no weight arrays).  Writes the tile's partial pair to part_out[0..1].
+// win: CAP double2 of LDS.
+template <int N>
+__device__ __forceinline__ void project_sky_tile(const ProjAdjArgs& a, int64_t tile,
+                                                 double2* win, ProjAdjShared& sh_,
+                                                 double* part_out) {
+  constexpr int H = N / 2;
+  constexpr int CAP = kAdjProjCap(N);
+  const int tid = threadIdx.x;
+  const int64_t i0 = tile * kBlock;
+
+  const SkyTrig tr = load_sky(a.sky, sh_.s_trig);
+  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
+  ProjAdjSample S;
+  LinkGeom g;
+  proj_adj_sample<N>(a, tile, sk, g, S);
+  int lo = S.sh[0], hi = S.sh[0];
+#pragma unroll
+  for (int p = 1; p < 9; ++p) { lo = min(lo, S.sh[p]); hi = max(hi, S.sh[p]); }
+  int wlo, whi;
+  block_range<kBlock>(S.rel + lo - (H - 1), S.rel + hi + H, sh_.red, wlo, whi);
+  const int count = whi - wlo + 1;
+  const int64_t base = a.y_start + i0 + wlo;
+  const int64_t hmax = a.n_h - 1;
+
+  double hv[2][9], dh[2][9];
+  if (count > 0 && count <= CAP) {
+    for (int k = tid; k < count; k += kBlock) {
+      int64_t j = base + k;
+      j = j < 0 ? 0 : (j > hmax ? hmax : j);
+      win[k] = make_double2(a.hp[j], a.hc[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      LagrangeStreamD<N> st(S.ep[p]);
+      const int off = S.rel + S.sh[p] - (H - 1) - wlo;
+      double sp = 0.0, sc = 0.0, dsp = 0.0, dsc = 0.0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        const double2 v = win[off + m];
+        const double c = st.coef(m), cd = st.coef_d(m);
+        st.step(c, cd, v.x, sp, dsp);
+        st.step(c, cd, v.y, sc, dsc);
+        st.next();
+      }
+      hv[0][p] = sp; hv[1][p] = sc;
+      dh[0][p] = dsp; dh[1][p] = dsc;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      LagrangeStreamD<N> st(S.ep[p]);
+      const int64_t j0 = S.q + S.sh[p] - (H - 1);
+      double sp = 0.0, sc = 0.0, dsp = 0.0, dsc = 0.0;
+#pragma unroll 1
+      for (int m = 0; m < N; ++m) {
+        int64_t j = j0 + m;
+        j = j < 0 ? 0 : (j > hmax ? hmax : j);
+        const double c = st.coef(m), cd = st.coef_d(m);
+        st.step(c, cd, a.hp[j], sp, dsp);
+        st.step(c, cd, a.hc[j], sc, dsc);
+        st.next();
+      }
+      hv[0][p] = sp; hv[1][p] = sc;
+      dh[0][p] = dsp; dh[1][p] = dsc;
+    }
+  }
+
+  // d y_l / d(k, u, v) contracted with g_y, then with d(k, u, v)/d(lam, beta).
+  double Gk[3] = {0.0, 0.0, 0.0}, Gu[3] = {0.0, 0.0, 0.0}, Gv[3] = {0.0, 0.0, 0.0};
+  const double inv_cdt = a.inv_dt / kC;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const double gy = S.active ? a.g_y[(int64_t)l * a.n_y + i0 + tid] : 0.0;
+    const int arm = kArm[l], r = kLinkRecv[l] - 1, e = kLinkEmit[l] - 1, pe = 3 + l;
+    const double dir = kDir[l];
+    const double inv = 1.0 / (2.0 * (1.0 - dir * g.kn[arm]));
+    const double dp = hv[0][pe] - hv[0][r], dc = hv[1][pe] - hv[1][r];
+    const double yl = inv * (g.xip[arm] * dp + g.xic[arm] * dc);
+    const double He = g.xip[arm] * dh[0][pe] + g.xic[arm] * dh[1][pe];
+    const double Hr = g.xip[arm] * dh[0][r] + g.xic[arm] * dh[1][r];
+    const double sn = 2.0 * inv * yl * dir;          // through 1/(2(1 - k.n))
+    const double su = 2.0 * inv * (g.un[arm] * dp + g.vn[arm] * dc);
+    const double sv = 2.0 * inv * (g.un[arm] * dc - g.vn[arm] * dp);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const double pos = -inv * inv_cdt * (He * g.x[e][cc] - Hr * g.x[r][cc]);
+      Gk[cc] = fma(gy, fma(sn, g.n[arm][cc], pos), Gk[cc]);
+      Gu[cc] = fma(gy, su * g.n[arm][cc], Gu[cc]);
+      Gv[cc] = fma(gy, sv * g.n[arm][cc], Gv[cc]);
+    }
+  }
+  const SkyDeriv D = sky_derivatives(tr.sl, tr.cl, tr.sb, tr.cb);
+  double part[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    double s = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      s += Gk[cc] * D.dk[t][cc] + Gu[cc] * D.du[t][cc] + Gv[cc] * D.dv[t][cc];
+    part[t] = s;
+  }
+  // deterministic block reduction -> one partial pair per workgroup
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part[t] += __shfl_xor(part[t], o, 64);
+  }
+  if ((tid & 63) == 0) { sh_.s_part[0][tid >> 6] = part[0]; sh_.s_part[1][tid >> 6] = part[1]; }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) { s0 += sh_.s_part[0][w]; s1 += sh_.s_part[1][w]; }
+    part_out[0] = s0;
+    part_out[1] = s1;
+  }
+}
+
+template <int N>
 __global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) {
   __shared__ double acc[2 * kAdjProjCap(N)];
-  __shared__ double2 win[SKY ? kAdjProjCap(N) : 1];
   __shared__ ProjAdjShared sh_;
-  project_adjoint_tile<N, SKY>(a, blockIdx.x, acc, win, sh_,
-                               SKY ? a.sky_part + 2 * blockIdx.x : nullptr);
+  project_adjoint_tile<N>(a, blockIdx.x, acc, sh_);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void project_sky_kernel(ProjAdjArgs a) {
+  __shared__ double2 win[kAdjProjCap(N)];
+  __shared__ ProjAdjShared sh_;
+  project_sky_tile<N>(a, blockIdx.x, win, sh_, a.sky_part + 2 * blockIdx.x);
 }
 
 template <int N>
@@ -351,16 +408,18 @@ hipError_t launch_tdi_adjoint(const TdiAdjArgs& a, int gen, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Scatter kernel, then (if a.sky_part) the sky-gradient kernel on the same
+// tiles.
 template <int N>
 hipError_t launch_project_adjoint(const ProjAdjArgs& a, hipStream_t s) {
   const int64_t blocks = (a.n_y + kBlock - 1) / kBlock;
-  if (a.sky_part)
-    hipLaunchKernelGGL((project_adjoint_kernel<N, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                       s, a);
-  else
-    hipLaunchKernelGGL((project_adjoint_kernel<N, false>), dim3((unsigned)blocks), dim3(kBlock),
-                       0, s, a);
-  return hipGetLastError();
+  hipLaunchKernelGGL((project_adjoint_kernel<N>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.sky_part) {
+    hipLaunchKernelGGL((project_sky_kernel<N>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 #define LR_INSTANTIATE_ADJOINT(NT)                                                   \

@@ -368,4 +368,11 @@ int lr_batch_loglike(const lr_batch* b, const double* out, const double* data, d
   return LR_OK;
 }
 
+int lr_batch_set_grid(lr_batch* b, int blocks) {
+  if (int st = check_batch(b)) return st;
+  if (blocks < 1) return set_error(LR_E_ARG, "grid of %d work-groups", blocks);
+  b->blocks = blocks;
+  return LR_OK;
+}
+
 }  // extern "C"

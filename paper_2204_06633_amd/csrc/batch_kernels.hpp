@@ -27,23 +27,14 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
   constexpr int YT = kFwdTile;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
   const GroupTable<GEN>& GT = group_table<GEN>();
+  // delayed terms accumulate unscaled streams; the undelayed ones are added
+  // after the scale, at the end
 #pragma unroll
   for (int k = 0; k < M; ++k)
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[k][s][c] = 0.0;
-
-#pragma unroll
-  for (int t = 0; t < ND; ++t) {
-    const Direct dr = TdiTab<GEN>::v.direct[t];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const double* w = ylds + (k * 6 + dr.link) * YT;
-      acc[k][0][dr.chan] += (double)dr.sign * w[par<YT>(c0)];
-      acc[k][1][dr.chan] += (double)dr.sign * w[par<YT>(c0 + 1)];
-    }
-  }
 #pragma unroll 1
   for (int g = 0; g < GT.n; ++g) {
     const GroupRow& G = GT.row[g];
@@ -70,29 +61,26 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
 #pragma unroll
           for (int k = 0; k < M; ++k) v[k] = ylds[(k * 6 + link) * YT + pa_.at(m)];
           if (m < N) {
-            const double c = A.coef(m);
+            A.tap(m);
 #pragma unroll
-            for (int k = 0; k < M; ++k) xa[k] = fma(c, v[k], xa[k] * A.d);
-            A.next();
+            for (int k = 0; k < M; ++k) xa[k] = A.step(xa[k], v[k], m);
           }
           if (m > 0) {
-            const double c = B.coef(m - 1);
+            B.tap(m - 1);
 #pragma unroll
-            for (int k = 0; k < M; ++k) xb[k] = fma(c, v[k], xb[k] * B.d);
-            B.next();
+            for (int k = 0; k < M; ++k) xb[k] = B.step(xb[k], v[k], m - 1);
           }
         }
       } else {
 #pragma unroll
         for (int m = 0; m < N; ++m) {
-          const double c = A.coef(m), e = B.coef(m);
+          A.tap(m);
+          B.tap(m);
 #pragma unroll
           for (int k = 0; k < M; ++k) {
-            xa[k] = fma(c, ylds[(k * 6 + link) * YT + pa_.at(m)], xa[k] * A.d);
-            xb[k] = fma(e, ylds[(k * 6 + link) * YT + pb_.at(m)], xb[k] * B.d);
+            xa[k] = A.step(xa[k], ylds[(k * 6 + link) * YT + pa_.at(m)], m);
+            xb[k] = B.step(xb[k], ylds[(k * 6 + link) * YT + pb_.at(m)], m);
           }
-          A.next();
-          B.next();
         }
       }
 #pragma unroll
@@ -103,6 +91,22 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
           acc[k][1][c] = fma(G.sgn[u][c], xb[k], acc[k][1][c]);
         }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double dir[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const Direct dr = TdiTab<GEN>::v.direct[t];
+      const double* w = ylds + (k * 6 + dr.link) * YT;
+      dir[0][dr.chan] += (double)dr.sign * w[par<YT>(c0)];
+      dir[1][dr.chan] += (double)dr.sign * w[par<YT>(c0 + 1)];
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        acc[k][s][c] = fma(LagrangeStream<N>::kScale, acc[k][s][c], dir[s][c]);
   }
   (void)live;
 }
@@ -230,17 +234,13 @@ __global__ __launch_bounds__(kBlock) void batch_tdi_adjoint_kernel(BatchAdjArgs 
   tdi_adjoint_tile<N, GEN>(x, tile, acc, red);
 }
 
-template <int N, bool SKY>
-__global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjArgs a) {
-  __shared__ double acc[2 * kAdjProjCap(N)];
-  __shared__ double2 win[SKY ? kAdjProjCap(N) : 1];
-  __shared__ ProjAdjShared sh_;
-  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
-  const BatchAdjTemplate T = a.tpl[b];
+// Per-template projection-adjoint arguments of work item b.
+__device__ __forceinline__ ProjAdjArgs batch_proj_args(const BatchAdjArgs& a,
+                                                       const BatchAdjTemplate& T) {
   ProjAdjArgs x;
   x.orb = a.orb_p;
-  x.hp = a.hp + T.h_off;
-  x.hc = a.hc + T.h_off;
+  x.hp = a.hp ? a.hp + T.h_off : nullptr;
+  x.hc = a.hc ? a.hc + T.h_off : nullptr;
   x.n_h = T.n_h;
   x.t_off = T.t_off_h;
   x.dt = a.dt;
@@ -252,8 +252,23 @@ __global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjA
   x.g_hp = a.g_hp + T.h_off;
   x.g_hc = a.g_hc + T.h_off;
   x.sky_part = nullptr;
-  project_adjoint_tile<N, SKY>(x, tile, acc, win, sh_,
-                               SKY ? a.sky_part + 2 * blockIdx.x : nullptr);
+  return x;
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjArgs a) {
+  __shared__ double acc[2 * kAdjProjCap(N)];
+  __shared__ ProjAdjShared sh_;
+  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  project_adjoint_tile<N>(batch_proj_args(a, a.tpl[b]), tile, acc, sh_);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void batch_project_sky_kernel(BatchAdjArgs a) {
+  __shared__ double2 win[kAdjProjCap(N)];
+  __shared__ ProjAdjShared sh_;
+  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  project_sky_tile<N>(batch_proj_args(a, a.tpl[b]), tile, win, sh_, a.sky_part + 2 * blockIdx.x);
 }
 
 template <int N, int GEN>
@@ -265,13 +280,15 @@ hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipS
 
 template <int N>
 hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s) {
-  if (a.sky_part)
-    hipLaunchKernelGGL((batch_project_adjoint_kernel<N, true>), dim3((unsigned)n_items),
-                       dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((batch_project_adjoint_kernel<N, false>), dim3((unsigned)n_items),
-                       dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+  hipLaunchKernelGGL((batch_project_adjoint_kernel<N>), dim3((unsigned)n_items), dim3(kBlock), 0,
+                     s, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.sky_part) {
+    hipLaunchKernelGGL((batch_project_sky_kernel<N>), dim3((unsigned)n_items), dim3(kBlock), 0,
+                       s, a);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 #define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M)                                                 \

@@ -37,9 +37,11 @@ def flags():
             "-I" + os.path.join(ROOT, "include")]
 
 
-def build(verbose=True, jobs=None):
-    """Compile every source to an object in parallel, then link the library."""
-    out_dir = os.path.join(HERE, "_build")
+def build(verbose=True, jobs=None, target=TARGET, defines=(), out_dir=None):
+    """Compile every source to an object in parallel, then link the library.
+    ``defines``: extra -D options (tuning macros such as LR_PROJ_MIN_WAVES),
+    for variant libraries built to ``target`` with objects in ``out_dir``."""
+    out_dir = out_dir or os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
     cc = hipcc()
     t0 = time.time()
@@ -50,7 +52,8 @@ def build(verbose=True, jobs=None):
     while pending or running:
         while pending and len(running) < jobs:
             src, obj = pending.pop(0)
-            cmd = [cc, *flags(), "-c", os.path.join(HERE, src), "-o", obj]
+            cmd = [cc, *flags(), *["-D" + d for d in defines], "-c", os.path.join(HERE, src),
+                   "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             running.append((src, subprocess.Popen(cmd)))
@@ -59,15 +62,15 @@ def build(verbose=True, jobs=None):
             for _, q in running:
                 q.wait()
             raise RuntimeError("compilation of %s failed" % src)
-    tmp = TARGET + ".tmp%d" % os.getpid()
+    tmp = target + ".tmp%d" % os.getpid()
     cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, TARGET)
+    os.replace(tmp, target)
     if verbose:
-        print("built %s in %.1f s" % (TARGET, time.time() - t0), flush=True)
-    return TARGET
+        print("built %s in %.1f s" % (target, time.time() - t0), flush=True)
+    return target
 
 
 if __name__ == "__main__":

@@ -197,22 +197,73 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N]) {
 //   I = sum_m c_m P_m S_m f_m,  P_m = prod_{j<m}(eps - x_j), S_m = prod_{j>m}(eps - x_j),
 // evaluated by the recurrence T_k = T_{k-1} (eps - x_k) + c_k P_k f_k (so that
 // T_{N-1} = I) with P_{k+1} = P_k (eps - x_k).  Per tap: 3 FP64 ops shared by
-// all series on the stencil plus 2 per series, and O(1) registers.
+// all series on the stencil (c_k P_k with c_k from an SGPR, the product
+// update, and eps - x_k by an inline-constant subtraction) plus 2 per series,
+// and O(1) registers.  Usage per tap k = 0, 1, ...: tap(k), then for every
+// series x = step(x, f_k, k); the interpolant is finish(x).
 template <int N>
 struct LagrangeStream {
-  double d, P;
+  static constexpr double kScale = 1.0;   // finish() multiplier
+  double d, P, c;
   __device__ __forceinline__ explicit LagrangeStream(double eps)
-      : d(eps + (double)(N / 2 - 1)), P(1.0) {}
-  // coefficient c_k P_k of tap k; advance to tap k+1 afterwards with next()
+      : d(eps + (double)(N / 2 - 1)), P(1.0), c(0.0) {}
+  __device__ __forceinline__ void tap(int k) {
+    constexpr LagrangeDenoms<N> C = make_denoms<N>();
+    if (k > 0) {
+      P *= d;
+      d -= 1.0;
+    }
+    c = C.c[k] * P;
+  }
+  __device__ __forceinline__ double step(double x, double f, int k) const {
+    return k == 0 ? c * f : fma(c, f, x * d);
+  }
+  __device__ __forceinline__ static double finish(double x) { return x * kScale; }
+};
+
+// LagrangeStream with the derivative with respect to eps carried along:
+// P'_{k+1} = P'_k (eps - x_k) + P_k, and a series follows
+// T'_k = T'_{k-1} (eps - x_k) + T_{k-1} + c_k P'_k f_k.
+template <int N>
+struct LagrangeStreamD {
+  double d, P, Pd;
+  __device__ __forceinline__ explicit LagrangeStreamD(double eps)
+      : d(eps + (double)(N / 2 - 1)), P(1.0), Pd(0.0) {}
   __device__ __forceinline__ double coef(int k) const {
     constexpr LagrangeDenoms<N> C = make_denoms<N>();
     return C.c[k] * P;
   }
+  __device__ __forceinline__ double coef_d(int k) const {
+    constexpr LagrangeDenoms<N> C = make_denoms<N>();
+    return C.c[k] * Pd;
+  }
+  // one tap of a series: value t and derivative td, sample f
+  __device__ __forceinline__ void step(double c, double cd, double f, double& t,
+                                       double& td) const {
+    td = fma(cd, f, fma(td, d, t));
+    t = fma(c, f, t * d);
+  }
   __device__ __forceinline__ void next() {
+    Pd = fma(Pd, d, P);
     P *= d;
     d -= 1.0;
   }
 };
+
+// Weight of tap m alone, O(N) work, for paths that cannot hold a weight
+// array (tap index not known at compile time).
+template <int N>
+__device__ __forceinline__ double lagrange_weight_at(double eps, int m) {
+  constexpr int H = N / 2;
+  double num = 1.0, den = 1.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const bool skip = j == m;
+    num *= skip ? 1.0 : eps - (double)(j - (H - 1));
+    den *= skip ? 1.0 : (double)(m - j);
+  }
+  return num / den;
+}
 
 // Two weight sets at once (two independent product chains).
 template <int N>

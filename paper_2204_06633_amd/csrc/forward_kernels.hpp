@@ -176,16 +176,14 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
         for (int k = 0; k <= N; ++k) {
           const double2 v = win[src.at(k)];
           if (k < N) {
-            const double c = sa.coef(k);
-            pa = fma(c, v.x, pa * sa.d);
-            ca = fma(c, v.y, ca * sa.d);
-            sa.next();
+            sa.tap(k);
+            pa = sa.step(pa, v.x, k);
+            ca = sa.step(ca, v.y, k);
           }
           if (k > 0) {
-            const double c = sb.coef(k - 1);
-            pb = fma(c, v.x, pb * sb.d);
-            cb = fma(c, v.y, cb * sb.d);
-            sb.next();
+            sb.tap(k - 1);
+            pb = sb.step(pb, v.x, k - 1);
+            cb = sb.step(cb, v.y, k - 1);
           }
         }
       } else {
@@ -193,13 +191,12 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
 #pragma unroll
         for (int k = 0; k < N; ++k) {
           const double2 v = win[src.at(k)], w = win[srb.at(k)];
-          const double c = sa.coef(k), e = sb.coef(k);
-          pa = fma(c, v.x, pa * sa.d);
-          ca = fma(c, v.y, ca * sa.d);
-          pb = fma(e, w.x, pb * sb.d);
-          cb = fma(e, w.y, cb * sb.d);
-          sa.next();
-          sb.next();
+          sa.tap(k);
+          sb.tap(k);
+          pa = sa.step(pa, v.x, k);
+          ca = sa.step(ca, v.y, k);
+          pb = sb.step(pb, w.x, k);
+          cb = sb.step(cb, w.y, k);
         }
       }
       add_position(p, A.xip, A.xic, pa, ca, na);
@@ -218,31 +215,39 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
       for (int m = 0; m < N; ++m) {
         int64_t j = ja + m;
         j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        const double c = sa.coef(m);
-        pa = fma(c, hp[j], pa * sa.d);
-        ca = fma(c, hc[j], ca * sa.d);
-        sa.next();
+        sa.tap(m);
+        pa = sa.step(pa, hp[j], m);
+        ca = sa.step(ca, hc[j], m);
         j = jb + m;
         j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        const double e = sb.coef(m);
-        pb = fma(e, hp[j], pb * sb.d);
-        cb = fma(e, hc[j], cb * sb.d);
-        sb.next();
+        sb.tap(m);
+        pb = sb.step(pb, hp[j], m);
+        cb = sb.step(cb, hc[j], m);
       }
       add_position(p, A.xip, A.xic, pa, ca, na);
       add_position(p, B.xip, B.xic, pb, cb, nb);
     }
   }
+  // the streams' common scale folded into the link normalisation
 #pragma unroll
   for (int l = 0; l < 6; ++l) {
     const int arm = kArm[l];
-    ya[l] = na[l] / (2.0 * (1.0 - kDir[l] * A.kn[arm]));
-    yb[l] = nb[l] / (2.0 * (1.0 - kDir[l] * B.kn[arm]));
+    ya[l] = LagrangeStream<N>::finish(na[l]) / (2.0 * (1.0 - kDir[l] * A.kn[arm]));
+    yb[l] = LagrangeStream<N>::finish(nb[l]) / (2.0 * (1.0 - kDir[l] * B.kn[arm]));
   }
 }
 
+// Minimum resident waves per SIMD the compiler must allow (register budget);
+// build-time tuning knobs.
+#ifndef LR_PROJ_MIN_WAVES
+#define LR_PROJ_MIN_WAVES 1
+#endif
+#ifndef LR_TDI_MIN_WAVES
+#define LR_TDI_MIN_WAVES 4
+#endif
+
 template <int N>
-__global__ __launch_bounds__(kBlock)
+__global__ __launch_bounds__(kBlock, LR_PROJ_MIN_WAVES)
 void project_links_kernel(ProjArgs a) {
   constexpr int CAP = kFwdTile + N + kSlack;
   __shared__ double2 win[CAP];
@@ -301,27 +306,6 @@ template <int GEN>
 struct TdiTab {
   static constexpr TdiTable<GEN> v = make_tdi_table<GEN>();
 };
-
-// Delay of group G at the light times L (compile-time table entry).
-template <int GEN, int G>
-__device__ __forceinline__ double delay_of(const double (&L)[6]) {
-  constexpr DelayGroup grp = TdiTab<GEN>::v.group[G];
-  double d = 0.0;
-#pragma unroll
-  for (int l = 0; l < 6; ++l) {
-    if (grp.cnt[l] == 1) d += L[l];
-    else if (grp.cnt[l] > 1) d = fma((double)grp.cnt[l], L[l], d);
-  }
-  return d;
-}
-
-template <int GEN, int... G>
-__device__ __forceinline__ void delay_range(const double (&L)[6], double& dmin, double& dmax,
-                                            std::integer_sequence<int, G...>) {
-  dmin = INFINITY;
-  dmax = -INFINITY;
-  ((dmin = fmin(dmin, delay_of<GEN, G>(L)), dmax = fmax(dmax, delay_of<GEN, G>(L))), ...);
-}
 
 // Delay groups as a run-time table in constant memory: the kernels loop over
 // groups without unrolling, so only one group's state is live at a time.
@@ -388,6 +372,7 @@ __device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int cha
 // One use (measured link) of a delay group for both samples of a lane, from
 // the parity-split LDS window w: sa_ starts sample a's stencil; if `same`,
 // sample b's stencil is the next window position, otherwise it starts at sb_.
+// Returns the streams' unscaled values (LagrangeStream<N>::finish scales).
 template <int N, int CAP>
 __device__ __forceinline__ void stream_pair(double ea, double eb, bool same, const double* w,
                                             const ParStream<CAP>& sa_, const ParStream<CAP>& sb_,
@@ -399,16 +384,16 @@ __device__ __forceinline__ void stream_pair(double ea, double eb, bool same, con
 #pragma unroll
     for (int k = 0; k <= N; ++k) {
       const double v = w[sa_.at(k)];
-      if (k < N) { xa = fma(A.coef(k), v, xa * A.d); A.next(); }
-      if (k > 0) { xb = fma(B.coef(k - 1), v, xb * B.d); B.next(); }
+      if (k < N) { A.tap(k); xa = A.step(xa, v, k); }
+      if (k > 0) { B.tap(k - 1); xb = B.step(xb, v, k - 1); }
     }
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      xa = fma(A.coef(k), w[sa_.at(k)], xa * A.d);
-      xb = fma(B.coef(k), w[sb_.at(k)], xb * B.d);
-      A.next();
-      B.next();
+      A.tap(k);
+      B.tap(k);
+      xa = A.step(xa, w[sa_.at(k)], k);
+      xb = B.step(xb, w[sb_.at(k)], k);
     }
   }
 }
@@ -426,28 +411,25 @@ __device__ __forceinline__ void stream_pair2(double ea, double eb, bool same, co
     for (int k = 0; k <= N; ++k) {
       const double v0 = w0[sa_.at(k)], v1 = w1[sa_.at(k)];
       if (k < N) {
-        const double c = A.coef(k);
-        xa[0] = fma(c, v0, xa[0] * A.d);
-        xa[1] = fma(c, v1, xa[1] * A.d);
-        A.next();
+        A.tap(k);
+        xa[0] = A.step(xa[0], v0, k);
+        xa[1] = A.step(xa[1], v1, k);
       }
       if (k > 0) {
-        const double c = B.coef(k - 1);
-        xb[0] = fma(c, v0, xb[0] * B.d);
-        xb[1] = fma(c, v1, xb[1] * B.d);
-        B.next();
+        B.tap(k - 1);
+        xb[0] = B.step(xb[0], v0, k - 1);
+        xb[1] = B.step(xb[1], v1, k - 1);
       }
     }
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const double c = A.coef(k), e = B.coef(k);
-      xa[0] = fma(c, w0[sa_.at(k)], xa[0] * A.d);
-      xa[1] = fma(c, w1[sa_.at(k)], xa[1] * A.d);
-      xb[0] = fma(e, w0[sb_.at(k)], xb[0] * B.d);
-      xb[1] = fma(e, w1[sb_.at(k)], xb[1] * B.d);
-      A.next();
-      B.next();
+      A.tap(k);
+      B.tap(k);
+      xa[0] = A.step(xa[0], w0[sa_.at(k)], k);
+      xa[1] = A.step(xa[1], w1[sa_.at(k)], k);
+      xb[0] = B.step(xb[0], w0[sb_.at(k)], k);
+      xb[1] = B.step(xb[1], w1[sb_.at(k)], k);
     }
   }
 }
@@ -462,10 +444,10 @@ __device__ __forceinline__ double stream_global(double eps, const double* ys, in
   for (int k = 0; k < N; ++k) {
     int64_t j = j0 + k;
     j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
-    x = fma(A.coef(k), ys[j], x * A.d);
-    A.next();
+    A.tap(k);
+    x = A.step(x, ys[j], k);
   }
-  return x;
+  return x;                         // unscaled, like stream_pair
 }
 
 __device__ __forceinline__ void light_times(const OrbitView& o, double tau, double (&L)[6]) {
@@ -473,7 +455,7 @@ __device__ __forceinline__ void light_times(const OrbitView& o, double tau, doub
 }
 
 template <int N, int GEN>
-__global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
+__global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a) {
   constexpr int H = N / 2;
   constexpr int CAP = kFwdTile + N + kSlack;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
@@ -507,8 +489,12 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
   const int64_t ymax = a.n_y - 1;
   const int c0 = ra - wlo;
 
+  // delayed terms accumulate unscaled streams; the undelayed ones are added
+  // after the scale, at the end
   double acc_a[3] = {0.0, 0.0, 0.0}, acc_b[3] = {0.0, 0.0, 0.0};
-  if (count > 0 && count <= CAP) {
+  double dir_a[3] = {0.0, 0.0, 0.0}, dir_b[3] = {0.0, 0.0, 0.0};
+  const bool lds = count > 0 && count <= CAP;
+  if (lds) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > ymax ? ymax : j);
@@ -516,12 +502,6 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
       for (int l = 0; l < 6; ++l) win[l * CAP + par<CAP>(k)] = a.y[(int64_t)l * a.n_y + j];
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < ND; ++t) {
-      const Direct dr = TdiTab<GEN>::v.direct[t];
-      acc_a[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0)];
-      acc_b[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0 + 1)];
-    }
 #pragma unroll 1
     for (int g = 0; g < GT.n; ++g) {
       const GroupRow& G = GT.row[g];
@@ -550,13 +530,6 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
       }
     }
   } else {
-#pragma unroll
-    for (int t = 0; t < ND; ++t) {
-      const Direct dr = TdiTab<GEN>::v.direct[t];
-      const double* ys = a.y + (int64_t)dr.link * a.n_y;
-      acc_a[dr.chan] += (double)dr.sign * ys[pa];
-      acc_b[dr.chan] += (double)dr.sign * ys[min(pa + 1, ymax)];
-    }
 #pragma unroll 1
     for (int g = 0; g < GT.n; ++g) {
       const GroupRow& G = GT.row[g];
@@ -577,6 +550,23 @@ __global__ __launch_bounds__(kBlock) void tdi_kernel(TdiArgs a) {
     }
   }
 
+#pragma unroll
+  for (int t = 0; t < ND; ++t) {
+    const Direct dr = TdiTab<GEN>::v.direct[t];
+    if (lds) {
+      dir_a[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0)];
+      dir_b[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0 + 1)];
+    } else {
+      const double* ys = a.y + (int64_t)dr.link * a.n_y;
+      dir_a[dr.chan] += (double)dr.sign * ys[pa];
+      dir_b[dr.chan] += (double)dr.sign * ys[min(pa + 1, ymax)];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc_a[c] = fma(LagrangeStream<N>::kScale, acc_a[c], dir_a[c]);
+    acc_b[c] = fma(LagrangeStream<N>::kScale, acc_b[c], dir_b[c]);
+  }
   if (!act_a) return;
   const int64_t i = i0 + ra;
   store_channels(acc_a, a.channels, a.out, a.n_out, i);

@@ -11,7 +11,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lisaresp.so")
+# LISARESP_LIB selects another build of the same library (tuning variants).
+LIB_PATH = os.environ.get("LISARESP_LIB") or os.path.join(_HERE, "_lisaresp.so")
 
 LR_XYZ, LR_AET, LR_XYZ_AET = 0, 1, 2
 CHANNELS = {"XYZ": LR_XYZ, "AET": LR_AET, "XYZAET": LR_XYZ_AET}
@@ -285,7 +286,9 @@ def _batch_lib():
     L.lr_response.argtypes = [pb, vp, vp, vp, vp, vp]
     L.lr_response_adjoint.argtypes = [pb, vp, vp, vp, vp, vp, vp, vp, vp]
     L.lr_batch_loglike.argtypes = [pb, vp, vp, d, vp, vp, vp]
-    for name in ("lr_batch_prepare", "lr_response", "lr_response_adjoint", "lr_batch_loglike"):
+    L.lr_batch_set_grid.argtypes = [pb, i32]
+    for name in ("lr_batch_prepare", "lr_response", "lr_response_adjoint", "lr_batch_loglike",
+                 "lr_batch_set_grid"):
         getattr(L, name).restype = i32
     L._batch_ready = True
     return L
@@ -326,6 +329,15 @@ class Batch:
     @property
     def n(self):
         return len(self.templates)
+
+    @property
+    def blocks(self):
+        """Work-groups of the persistent forward launch."""
+        return int(self.c.blocks)
+
+    def set_grid(self, blocks):
+        _check(_batch_lib().lr_batch_set_grid(ctypes.byref(self.c), int(blocks)),
+               "lr_batch_set_grid")
 
     @property
     def h_extent(self):

@@ -3,12 +3,17 @@
     python -m paper_2204_06633_amd.profiling --what forward --reps 5
     python -m paper_2204_06633_amd.profiling --what adjoint --reps 5
     python -m paper_2204_06633_amd.profiling --what copy --copy-mib 1024
+    python -m paper_2204_06633_amd.profiling --what batch --templates 64
+    python -m paper_2204_06633_amd.profiling --what batch-adjoint --templates 32
 
 ``forward`` runs the per-template forward (projection + TDI-2 XYZ+AET) on the
 1-yr, dt = 10 s, order-25 Keplerian workload; ``adjoint`` adds the adjoint
 pair; ``copy`` runs one device-to-device copy of known size (the reference
-for scaling the HBM byte counters).  Each step prints a line so a profiler
-run shows progress.
+for scaling the HBM byte counters); ``batch`` runs the fused batched forward
+on the first ``--templates`` templates of the 512-template uneven batch
+(group 2); ``batch-adjoint`` runs forward, likelihood and adjoint of that
+many 1-yr, dt = 15 s walkers with hybrid orbits.  Each step prints a line so
+a profiler run shows progress.
 """
 from __future__ import annotations
 
@@ -18,7 +23,10 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["forward", "adjoint", "copy"], default="forward")
+    ap.add_argument("--what", choices=["forward", "adjoint", "copy", "batch", "batch-adjoint"],
+                    default="forward")
+    ap.add_argument("--templates", type=int, default=64)
+    ap.add_argument("--group", type=int, default=2)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args(argv)
@@ -37,6 +45,8 @@ def main(argv=None):
         return
 
     from . import native, response, workloads
+    if args.what in ("batch", "batch-adjoint"):
+        return run_batch(args, dev)
     case = workloads.config_c2("XYZAET")
     g = case.grid
     orb = native.Orbits.from_samples(case.orbits_proj, device=dev)
@@ -53,6 +63,37 @@ def main(argv=None):
             response.plain_adjoint(tpl, hp, hc, sky, g_out)
         torch.cuda.synchronize()
         print("%s step %d done (%d samples)" % (args.what, r, g.n_out), flush=True)
+
+
+def run_batch(args, dev):
+    import torch
+
+    from . import native, workloads
+    adj = args.what == "batch-adjoint"
+    full = workloads.config_c5(args.templates) if adj else workloads.config_c3()
+    bc = full
+    if not adj:
+        k = args.templates
+        bc = workloads.make_batch_case(full.name, [g.n_out for g in full.grids[:k]], full.dt,
+                                       full.order, full.generation, full.channels, 3,
+                                       params=full.params[:k])
+    orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
+    orb_t = orb_p if bc.orbits_tdi is bc.orbits_proj else \
+        native.Orbits.from_samples(bc.orbits_tdi, device=dev)
+    hp, hc = workloads.device_polarizations(bc, dev)
+    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    b = native.Batch(bc.layout.templates(), orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation,
+                     bc.channels, group=args.group, adjoint=adj, device=dev)
+    out = torch.empty(b.out_extent, dtype=torch.float64, device=dev)
+    data = torch.zeros_like(out) if adj else None
+    for r in range(args.reps):
+        b.response(hp, hc, sky, out=out)
+        if adj:
+            _, g_out = b.loglike(out, data, 1e-21)
+            b.adjoint(hp, hc, sky, g_out)
+        torch.cuda.synchronize()
+        print("%s step %d done (%d templates, %d samples)" % (args.what, r, len(bc.grids),
+                                                            bc.n_samples), flush=True)
 
 
 if __name__ == "__main__":

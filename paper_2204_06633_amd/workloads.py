@@ -123,3 +123,83 @@ def make_batch(n_templates, orbit_kind, n_out_list, dt, order, generation, seed,
         g.back_tdi = max(g.back_tdi, g2.back_tdi) + 4
         grids.append(g)
     return grids, np.asarray(params, dtype=np.float64), orb_p, orb_t
+
+
+@dataclasses.dataclass
+class BatchCase:
+    """A batch workload: per-template grids sharing the output start time,
+    their layout in the shared arrays, source parameters [n][8] and orbits."""
+    name: str
+    grids: list
+    layout: BatchLayout
+    params: np.ndarray
+    orbits_proj: inputs.OrbitSamples
+    orbits_tdi: inputs.OrbitSamples
+    dt: float
+    order: int
+    generation: int
+    channels: str
+
+    @property
+    def t0(self):
+        return self.grids[0].t_start
+
+    @property
+    def n_samples(self):
+        return int(sum(g.n_out for g in self.grids))
+
+
+def make_batch_case(name, n_out_list, dt, order, generation, channels, seed, params=None,
+                    orbit_kind="keplerian", tdi_orbit_kind=None):
+    grids, params, sp, st = make_batch(len(n_out_list), orbit_kind, n_out_list, dt, order,
+                                       generation, seed, tdi_orbit_kind=tdi_orbit_kind,
+                                       params=params)
+    rows = 6 if channels == "XYZAET" else 3
+    return BatchCase(name, grids, batch_layout(grids, rows), params, sp, st, dt, order,
+                     generation, channels)
+
+
+def config_c3(n_templates=512, seed=3):
+    """512 Galactic binaries of uneven durations (uniform 0.25-1 yr at
+    dt = 10 s), independent seeded parameters, flexing Keplerian orbits,
+    TDI-2 A/E/T, order 25."""
+    rng = np.random.default_rng(seed)
+    full = int(round(inputs.YEAR / 10.0))
+    n_out = np.round(rng.uniform(0.25, 1.0, n_templates) * full).astype(np.int64)
+    return make_batch_case("c3_batch%d_uneven_keplerian_tdi2" % n_templates, list(n_out), 10.0,
+                           25, 2, "AET", seed)
+
+
+def config_c5(n_walkers=256, seed=5, spread=1e-6):
+    """MCMC walkers around one Galactic binary: 1 yr at dt = 15 s each,
+    Keplerian orbits for the projection and rigid equal-arm orbits for the
+    TDI-2 delays (hybrid template), A/E/T, order 25.  Walker parameters are
+    the source's scaled by (1 + spread * N(0,1)), angles shifted by
+    spread * N(0,1)."""
+    rng = np.random.default_rng(seed)
+    base = inputs.draw_gb_params(rng)
+    params = np.repeat(base[None, :], n_walkers, 0)
+    params[:, :3] *= 1.0 + spread * rng.standard_normal((n_walkers, 3))
+    params[:, 3:] += spread * rng.standard_normal((n_walkers, 5))
+    n = int(round(inputs.YEAR / 15.0))
+    return make_batch_case("c5_walkers%d_hybrid_dt15" % n_walkers, [n] * n_walkers, 15.0, 25, 2,
+                           "AET", seed, params=params, tdi_orbit_kind="rigid")
+
+
+def device_polarizations(bc: BatchCase, device, params=None):
+    """h+ and hx of every template of a batch, generated on the device with
+    the torch waveform and laid out as bc.layout says.  Returns (hp, hc)."""
+    import torch
+
+    from . import waveform
+    lay = bc.layout
+    p = torch.as_tensor(bc.params if params is None else params, dtype=torch.float64,
+                        device=device)
+    hp = torch.empty(max(lay.n_h_total, 1), dtype=torch.float64, device=device)
+    hc = torch.empty_like(hp)
+    for k, (g, ho) in enumerate(zip(bc.grids, lay.h_offsets)):
+        t = (torch.arange(g.n_h, dtype=torch.float64, device=device) - g.out_start) * g.dt
+        a, b = waveform.gb_polarizations(p[k], t)
+        hp[ho:ho + g.n_h] = a
+        hc[ho:ho + g.n_h] = b
+    return hp, hc

@@ -168,5 +168,41 @@ def test_graph_capture_replays_match_eager(torch_cuda):
         snap = [x.clone() for x in (out, ll, ghp, ghc, gsky)]
         step()                                    # eager on the same inputs
         torch.cuda.synchronize()
-        for a, b in zip(snap, (out, ll, ghp, ghc, gsky)):
-            assert torch.allclose(a, b, rtol=1e-12, atol=0), r
+        # the forward and the likelihood are deterministic; the adjoint sums
+        # in LDS with atomics, so its rounding depends on the order in which
+        # waves arrive: compare it jointly, relative to its norm
+        assert torch.equal(snap[0], out) and torch.equal(snap[1], ll), r
+        for a, b, tol in ((snap[2], ghp, 1e-13), (snap[3], ghc, 1e-13), (snap[4], gsky, 1e-12)):
+            assert cases.rel_err(a.cpu().numpy(), b.cpu().numpy()) <= tol, r
+
+
+def test_group_and_grid_do_not_change_results(torch_cuda, tmp_path):
+    """Each template's arithmetic is the same whatever the group size and the
+    persistent grid: the outputs agree bit for bit; the autotuner returns one
+    of the candidates and caches it."""
+    torch = torch_cuda
+    from paper_2204_06633_amd import autotune, native
+    n_out_list = [1200, 300, 2500, 777, 1, 1600]
+    B = _build(torch, n_out_list, group=1, seed=17)
+    hp, hc, sky = _t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"])
+    ref = B["batch"].response(hp, hc, sky).clone()
+    gp, gt = B["orbs"]
+    tpl = B["lay"].templates()
+    t0 = B["grids"][0].t_start
+    for g in (1, 2, 4):
+        b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g)
+        for blocks in (1, 3, b.blocks, 2 * b.blocks):
+            b.set_grid(blocks)
+            out = b.response(hp, hc, sky)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (g, blocks)
+    cache = str(tmp_path / "tune.json")
+    r = autotune.tune(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky, reps=2, cache_path=cache)
+    assert r["group"] in autotune.GROUPS and r["grid_scale"] in autotune.GRID_SCALES
+    assert len(r["trials"]) == len(autotune.GROUPS) * len(autotune.GRID_SCALES)
+    assert autotune.tune(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky,
+                         cache_path=cache)["tuned_at"] == r["tuned_at"]
+    b, _ = autotune.tuned_batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky, cache_path=cache)
+    out = b.response(hp, hc, sky)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
