@@ -47,48 +47,34 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
     const int top = YT - 1 - N;
     const ParStream<YT> pa_(min(max(c0 + sa - (H - 1), 0), top)),
         pb_(min(max(c0 + 1 + sb - (H - 1), 0), top));
-#pragma unroll 1
-    for (int u = 0; u < G.nuse; ++u) {
-      const int link = G.link[u];
+    if (G.nuse == 1) {
+      const double* w[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) w[k] = ylds + (k * 6 + G.link[0]) * YT;
       double xa[M], xb[M];
-#pragma unroll
-      for (int k = 0; k < M; ++k) { xa[k] = 0.0; xb[k] = 0.0; }
-      LagrangeStream<N> A(ea), B(eb);
-      if (same) {
-#pragma unroll
-        for (int m = 0; m <= N; ++m) {
-          double v[M];
-#pragma unroll
-          for (int k = 0; k < M; ++k) v[k] = ylds[(k * 6 + link) * YT + pa_.at(m)];
-          if (m < N) {
-            A.tap(m);
-#pragma unroll
-            for (int k = 0; k < M; ++k) xa[k] = A.step(xa[k], v[k], m);
-          }
-          if (m > 0) {
-            B.tap(m - 1);
-#pragma unroll
-            for (int k = 0; k < M; ++k) xb[k] = B.step(xb[k], v[k], m - 1);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-          A.tap(m);
-          B.tap(m);
-#pragma unroll
-          for (int k = 0; k < M; ++k) {
-            xa[k] = A.step(xa[k], ylds[(k * 6 + link) * YT + pa_.at(m)], m);
-            xb[k] = B.step(xb[k], ylds[(k * 6 + link) * YT + pb_.at(m)], m);
-          }
-        }
-      }
+      stream_multi<N, YT, M>(ea, eb, same, w, pa_, pb_, xa, xb);
 #pragma unroll
       for (int k = 0; k < M; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          acc[k][0][c] = fma(G.sgn[u][c], xa[k], acc[k][0][c]);
-          acc[k][1][c] = fma(G.sgn[u][c], xb[k], acc[k][1][c]);
+          acc[k][0][c] = fma(G.sgn[0][c], xa[k], acc[k][0][c]);
+          acc[k][1][c] = fma(G.sgn[0][c], xb[k], acc[k][1][c]);
+        }
+    } else {
+      const double* w[2 * M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        w[2 * k] = ylds + (k * 6 + G.link[0]) * YT;
+        w[2 * k + 1] = ylds + (k * 6 + G.link[1]) * YT;
+      }
+      double xa[2 * M], xb[2 * M];
+      stream_multi<N, YT, 2 * M>(ea, eb, same, w, pa_, pb_, xa, xb);
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc[k][0][c] = fma(G.sgn[0][c], xa[2 * k], fma(G.sgn[1][c], xa[2 * k + 1], acc[k][0][c]));
+          acc[k][1][c] = fma(G.sgn[0][c], xb[2 * k], fma(G.sgn[1][c], xb[2 * k + 1], acc[k][1][c]));
         }
     }
   }

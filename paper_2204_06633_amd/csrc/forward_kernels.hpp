@@ -369,56 +369,35 @@ __device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int cha
   dhi = fmax(lmax, chain * lmax);
 }
 
-// One use (measured link) of a delay group for both samples of a lane, from
-// the parity-split LDS window w: sa_ starts sample a's stencil; if `same`,
-// sample b's stencil is the next window position, otherwise it starts at sb_.
-// Returns the streams' unscaled values (LagrangeStream<N>::finish scales).
-template <int N, int CAP>
-__device__ __forceinline__ void stream_pair(double ea, double eb, bool same, const double* w,
-                                            const ParStream<CAP>& sa_, const ParStream<CAP>& sb_,
-                                            double& xa, double& xb) {
+// S series (measured links, possibly of several templates) that share one
+// delay, for both samples of a lane, from parity-split LDS rows w[s]: sa_
+// starts sample a's stencil; if `same`, sample b's stencil is the next
+// window position, otherwise it starts at sb_.  One product chain per
+// sample serves all S series.  Returns the streams' unscaled values
+// (LagrangeStream<N>::finish scales).
+template <int N, int CAP, int S>
+__device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
+                                             const double* const (&w)[S],
+                                             const ParStream<CAP>& sa_, const ParStream<CAP>& sb_,
+                                             double (&xa)[S], double (&xb)[S]) {
   LagrangeStream<N> A(ea), B(eb);
-  xa = 0.0;
-  xb = 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) { xa[s] = 0.0; xb[s] = 0.0; }
   if (same) {
 #pragma unroll
     for (int k = 0; k <= N; ++k) {
-      const double v = w[sa_.at(k)];
-      if (k < N) { A.tap(k); xa = A.step(xa, v, k); }
-      if (k > 0) { B.tap(k - 1); xb = B.step(xb, v, k - 1); }
-    }
-  } else {
+      double v[S];
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      A.tap(k);
-      B.tap(k);
-      xa = A.step(xa, w[sa_.at(k)], k);
-      xb = B.step(xb, w[sb_.at(k)], k);
-    }
-  }
-}
-
-// Two uses sharing one delay (one product chain per sample, two series).
-template <int N, int CAP>
-__device__ __forceinline__ void stream_pair2(double ea, double eb, bool same, const double* w0,
-                                             const double* w1, const ParStream<CAP>& sa_,
-                                             const ParStream<CAP>& sb_, double (&xa)[2],
-                                             double (&xb)[2]) {
-  LagrangeStream<N> A(ea), B(eb);
-  xa[0] = xa[1] = xb[0] = xb[1] = 0.0;
-  if (same) {
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      const double v0 = w0[sa_.at(k)], v1 = w1[sa_.at(k)];
+      for (int s = 0; s < S; ++s) v[s] = w[s][sa_.at(k)];
       if (k < N) {
         A.tap(k);
-        xa[0] = A.step(xa[0], v0, k);
-        xa[1] = A.step(xa[1], v1, k);
+#pragma unroll
+        for (int s = 0; s < S; ++s) xa[s] = A.step(xa[s], v[s], k);
       }
       if (k > 0) {
         B.tap(k - 1);
-        xb[0] = B.step(xb[0], v0, k - 1);
-        xb[1] = B.step(xb[1], v1, k - 1);
+#pragma unroll
+        for (int s = 0; s < S; ++s) xb[s] = B.step(xb[s], v[s], k - 1);
       }
     }
   } else {
@@ -426,10 +405,11 @@ __device__ __forceinline__ void stream_pair2(double ea, double eb, bool same, co
     for (int k = 0; k < N; ++k) {
       A.tap(k);
       B.tap(k);
-      xa[0] = A.step(xa[0], w0[sa_.at(k)], k);
-      xa[1] = A.step(xa[1], w1[sa_.at(k)], k);
-      xb[0] = B.step(xb[0], w0[sb_.at(k)], k);
-      xb[1] = B.step(xb[1], w1[sb_.at(k)], k);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        xa[s] = A.step(xa[s], w[s][sa_.at(k)], k);
+        xb[s] = B.step(xb[s], w[s][sb_.at(k)], k);
+      }
     }
   }
 }
@@ -511,17 +491,18 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       const bool same = __all(sa == sb);
       const ParStream<CAP> pa_(c0 + sa - (H - 1)), pb_(c0 + 1 + sb - (H - 1));
       if (G.nuse == 1) {
-        double xa, xb;
-        stream_pair<N, CAP>(ea, eb, same, win + G.link[0] * CAP, pa_, pb_, xa, xb);
+        const double* const w[1] = {win + G.link[0] * CAP};
+        double xa[1], xb[1];
+        stream_multi<N, CAP, 1>(ea, eb, same, w, pa_, pb_, xa, xb);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          acc_a[c] = fma(G.sgn[0][c], xa, acc_a[c]);
-          acc_b[c] = fma(G.sgn[0][c], xb, acc_b[c]);
+          acc_a[c] = fma(G.sgn[0][c], xa[0], acc_a[c]);
+          acc_b[c] = fma(G.sgn[0][c], xb[0], acc_b[c]);
         }
       } else {
+        const double* const w[2] = {win + G.link[0] * CAP, win + G.link[1] * CAP};
         double xa[2], xb[2];
-        stream_pair2<N, CAP>(ea, eb, same, win + G.link[0] * CAP, win + G.link[1] * CAP, pa_,
-                             pb_, xa, xb);
+        stream_multi<N, CAP, 2>(ea, eb, same, w, pa_, pb_, xa, xb);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           acc_a[c] = fma(G.sgn[0][c], xa[0], fma(G.sgn[1][c], xa[1], acc_a[c]));
