@@ -97,8 +97,14 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
   (void)live;
 }
 
+// Minimum resident waves per SIMD for the fused kernel's register budget
+// (build-time tuning knob; 1 leaves the compiler unconstrained).
+#ifndef LR_FUSED_MIN_WAVES
+#define LR_FUSED_MIN_WAVES 1
+#endif
+
 template <int N, int GEN, int M>
-__global__ __launch_bounds__(kBlock) void fused_forward_kernel(BatchFwdArgs a) {
+__global__ __launch_bounds__(kBlock, LR_FUSED_MIN_WAVES) void fused_forward_kernel(BatchFwdArgs a) {
   constexpr int YT = kFwdTile;
   constexpr int CAPH = kFwdTile + N + kSlack;
   __shared__ double ylds[M * 6 * YT];
@@ -117,13 +123,18 @@ __global__ __launch_bounds__(kBlock) void fused_forward_kernel(BatchFwdArgs a) {
     const int64_t o0 = (int64_t)tile * a.T_out;       // output index of the tile's first output
     const int64_t i_base = o0 - a.F;                  // output index of tile element 0
 
-    // 1. link series of each template of the group into LDS
+    // 1. link series of each template of the group into LDS (one copy of the
+    // projection code, templates in a rolled loop)
     bool live[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
       const BatchTemplate T = a.tpl[grp * M + k];
       live[k] = T.index >= 0 && o0 < T.n_out;
-      if (!live[k]) continue;                         // uniform
+    }
+#pragma unroll 1
+    for (int k = 0; k < M; ++k) {
+      const BatchTemplate T = a.tpl[grp * M + k];
+      if (!(T.index >= 0 && o0 < T.n_out)) continue;  // uniform
       const int64_t n_valid = min((int64_t)a.T_out, T.n_out - o0);
       const int r_end = (int)min((int64_t)YT, a.F + n_valid + (YT - a.F - a.T_out));
       const int last = r_end - 1;
