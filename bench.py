@@ -44,9 +44,12 @@ METRIC = ("response samples/s (templates×links×time) fwd & fwd+adjoint at 1e-1
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the per-template forward kernels
+    (tdi_kernel, project_links_kernel): a recorded counter summary is used
+    only while they are unchanged."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2204_06633_amd", "csrc", "*.h*"))):
-        h.update(open(p, "rb").read())
+    for name in ("device_common.hpp", "forward_kernels.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2204_06633_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 

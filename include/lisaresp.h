@@ -236,21 +236,31 @@ int lr_batch_prepare(const lr_template *t, int64_t n, const lr_orbits *proj,
 
 /* Forward response of every template (Sec. IV.B-IV.C): hp, hc hold the
  * templates' h arrays at their offsets, sky is device [n][2] (lam, beta),
- * out receives each template's block.  Graph-capturable. */
+ * out receives each template's block (other elements untouched).  All
+ * pointers are device memory owned by the caller.  Graph-capturable.  Calls
+ * that share one lr_batch (its workspace holds the work counter) must not
+ * overlap in time.  Errors: LR_E_ARG (unprepared batch, null pointer),
+ * LR_E_HIP (launch). */
 int lr_response(const lr_batch *b, const double *hp, const double *hc, const double *sky,
                 double *out, void *stream);
 
 /* Transpose of lr_response (needs a batch prepared with adjoint != 0):
  * g_out laid out like out; g_hp, g_hc like hp, hc over [0, h_extent),
- * overwritten; g_sky device [n][2] (d/d lam, d/d beta) or NULL.
- * Graph-capturable. */
+ * overwritten; g_sky device [n][2] (d/d lam, d/d beta) or NULL (then hp, hc
+ * may be NULL too).  Graph-capturable; calls sharing one lr_batch must not
+ * overlap.  Sums use atomics, so results are reproducible to rounding.
+ * Errors: LR_E_WORKSPACE (batch prepared without adjoint), LR_E_ARG,
+ * LR_E_HIP. */
 int lr_response_adjoint(const lr_batch *b, const double *hp, const double *hc,
                         const double *sky, const double *g_out, double *g_hp, double *g_hc,
                         double *g_sky, void *stream);
 
-/* Per-template white-noise log-likelihood (as lr_loglike) of a batch
- * output: loglike device [n]; g_out (like out, or NULL) receives
- * (data - out)/sigma^2.  Graph-capturable. */
+/* Per-template white-noise log-likelihood (as lr_loglike, Sec. II.A) of a
+ * batch output: data laid out like out; loglike device [n] (0 for an empty
+ * template); g_out (like out, or NULL) receives (data - out)/sigma^2 over
+ * each template's block.  Deterministic fixed-order sums.  Graph-capturable;
+ * calls sharing one lr_batch must not overlap.  Errors: LR_E_ARG (sigma <= 0
+ * or not finite, null pointer), LR_E_HIP. */
 int lr_batch_loglike(const lr_batch *b, const double *out, const double *data, double sigma,
                      double *loglike, double *g_out, void *stream);
 
