@@ -88,13 +88,19 @@ def cpu_baseline(case, target_s=10.0):
     t0 = time.perf_counter()
     run(m)
     dt_cal = time.perf_counter() - t0
+    # the second half of the template at most; repeated if that is shorter
+    # than the target time
     m = int(min(g.n_out // 2 - g.back_tdi - 1, max(m, m * target_s / max(dt_cal, 1e-6))))
-    t0 = time.perf_counter()
-    run(m)
-    el = time.perf_counter() - t0
-    return {"value": 6.0 * m / el, "unit": "samples/s (templates×links×time)",
+    reps, el = 0, 0.0
+    while reps < 4 and (reps == 0 or el < target_s):
+        t0 = time.perf_counter()
+        run(m)
+        el += time.perf_counter() - t0
+        reps += 1
+    return {"value": 6.0 * m * reps / el, "unit": "samples/s (templates×links×time)",
             "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "%d contiguous output samples of the same 1-yr template (%.1f s)" % (m, el)}
+            "sample": "%d contiguous output samples of the same 1-yr template, run %d time(s) "
+                      "(%.1f s in total)" % (m, reps, el)}
 
 
 def _events(n):

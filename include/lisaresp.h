@@ -213,7 +213,7 @@ typedef struct {
     int64_t n_templates, n_items, n_tdi_items, n_proj_items, n_like_items;
     int64_t gy_doubles, h_extent, out_extent;
     void *ws;
-    size_t off[12];
+    size_t off[16];      /* workspace region offsets (bytes) */
 } lr_batch;
 
 /* Device workspace bytes for a batch.  With adjoint != 0 it includes the

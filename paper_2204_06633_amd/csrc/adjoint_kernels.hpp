@@ -65,85 +65,114 @@ __device__ __forceinline__ void scatter_global(double* ys, int64_t j0, int64_t n
   }
 }
 
-// One output tile (kBlock samples) of the TDI adjoint; `acc` and `red` are
-// the workgroup's LDS scratch.  The delay groups are walked by a runtime
-// loop over the constant-memory table, so one weight set is live at a time.
-template <int N, int GEN>
-__device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs& a, int64_t tile, double* acc,
+// One output tile (kBlock samples) of the TDI adjoint for M templates that
+// share the output grid and the TDI orbits (a[k].orb, t_off, dt, out_start
+// equal; a[0] the longest): the interpolation weights depend on the orbits
+// only, so each weight set serves all M templates' scatters.  live[k] says
+// whether template k has outputs in the tile (uniform).  `acc` holds M x 6
+// LDS rows of kAdjTdiCap(N); `red` is reduction scratch.  The delay groups
+// are walked by a runtime loop over the constant-memory table, so one weight
+// set is live at a time.
+template <int N, int GEN, int M>
+__device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs (&a)[M], const bool (&live)[M],
+                                                 int64_t tile, double* acc,
                                                  int (&red)[2][kBlock / 64]) {
   constexpr int H = N / 2;
   constexpr int CAP = kAdjTdiCap(N);
   constexpr int ND = TdiTab<GEN>::v.ndirect;
   const GroupTable<GEN>& GT = group_table<GEN>();
+  const TdiAdjArgs& a0 = a[0];
 
   const int tid = threadIdx.x;
   const int64_t i0 = tile * kBlock;
   const int64_t i = i0 + tid;
-  const bool active = i < a.n_out;
-  const int rel = active ? tid : (int)(a.n_out - 1 - i0);
-  const int64_t p = a.out_start + i0 + rel;
+  const bool active = i < a0.n_out;
+  const int rel = active ? tid : (int)(a0.n_out - 1 - i0);
+  const int64_t p = a0.out_start + i0 + rel;
 
   double L[6];
-  light_times(a.orb, a.t_off + (double)p * a.dt, L);
+  light_times(a0.orb, a0.t_off + (double)p * a0.dt, L);
   double dlo, dhi, e_unused;
   group_delay_bounds(L, GT.chain, dlo, dhi);
-  const int lo = min(0, split_delay(dhi, a.inv_dt, e_unused) - (H - 1));
-  const int hi = max(0, split_delay(dlo, a.inv_dt, e_unused) + H);
+  const int lo = min(0, split_delay(dhi, a0.inv_dt, e_unused) - (H - 1));
+  const int hi = max(0, split_delay(dlo, a0.inv_dt, e_unused) + H);
   int wlo, whi;
   block_range<kBlock>(rel + lo, rel + hi, red, wlo, whi);
   const int count = whi - wlo + 1;
-  const int64_t base = a.out_start + i0 + wlo;
+  const int64_t base = a0.out_start + i0 + wlo;
   const int c0 = rel - wlo;
 
-  double gch[3] = {0.0, 0.0, 0.0};
-  if (active) load_channel_grads(a.g_out, a.channels, a.n_out, i, gch);
+  double gch[M][3];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    gch[k][0] = gch[k][1] = gch[k][2] = 0.0;
+    if (live[k] && i < a[k].n_out) load_channel_grads(a[k].g_out, a[k].channels, a[k].n_out, i, gch[k]);
+  }
 
   if (count > 0 && count <= CAP) {
-    for (int k = tid; k < 6 * CAP; k += kBlock) acc[k] = 0.0;
+    for (int k = tid; k < M * 6 * CAP; k += kBlock) acc[k] = 0.0;
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
       const Direct dr = TdiTab<GEN>::v.direct[t];
-      atomicAdd(&acc[dr.link * CAP + c0], (double)dr.sign * gch[dr.chan]);
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        if (live[k]) atomicAdd(&acc[(k * 6 + dr.link) * CAP + c0], (double)dr.sign * gch[k][dr.chan]);
     }
 #pragma unroll 1
     for (int g = 0; g < GT.n; ++g) {
       const GroupRow& G = GT.row[g];
       double eps;
-      const int sh = split_delay(row_delay(G, L), a.inv_dt, eps);
+      const int sh = split_delay(row_delay(G, L), a0.inv_dt, eps);
       double w[N];
       lagrange_weights<N>(eps, w);
       const int j0 = c0 + sh - (H - 1);
 #pragma unroll 1
       for (int u = 0; u < G.nuse; ++u) {
-        const double v = G.sgn[u][0] * gch[0] + G.sgn[u][1] * gch[1] + G.sgn[u][2] * gch[2];
-        scatter_lds<N>(acc + G.link[u] * CAP + j0, w, v);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          if (!live[k]) continue;                       // uniform
+          const double v =
+              G.sgn[u][0] * gch[k][0] + G.sgn[u][1] * gch[k][1] + G.sgn[u][2] * gch[k][2];
+          scatter_lds<N>(acc + (k * 6 + G.link[u]) * CAP + j0, w, v);
+        }
       }
     }
     __syncthreads();
-    for (int k = tid; k < count; k += kBlock) {
-      const int64_t j = base + k;
-      if (j < 0 || j >= a.n_y) continue;
 #pragma unroll
-      for (int l = 0; l < 6; ++l) atomicAdd(a.g_y + (int64_t)l * a.n_y + j, acc[l * CAP + k]);
+    for (int k = 0; k < M; ++k) {
+      if (!live[k]) continue;
+      for (int e = tid; e < count; e += kBlock) {
+        const int64_t j = base + e;
+        if (j < 0 || j >= a[k].n_y) continue;
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+          atomicAdd(a[k].g_y + (int64_t)l * a[k].n_y + j, acc[(k * 6 + l) * CAP + e]);
+      }
     }
   } else {
     // stencil footprint wider than the LDS tile: scatter to global memory
 #pragma unroll
-    for (int t = 0; t < ND; ++t) {
-      const Direct dr = TdiTab<GEN>::v.direct[t];
-      if (active) atomicAdd(a.g_y + (int64_t)dr.link * a.n_y + p, (double)dr.sign * gch[dr.chan]);
-    }
+    for (int k = 0; k < M; ++k) {
+      if (!live[k] || !(i < a[k].n_out)) continue;
+      const TdiAdjArgs& ak = a[k];
+#pragma unroll
+      for (int t = 0; t < ND; ++t) {
+        const Direct dr = TdiTab<GEN>::v.direct[t];
+        atomicAdd(ak.g_y + (int64_t)dr.link * ak.n_y + p, (double)dr.sign * gch[k][dr.chan]);
+      }
 #pragma unroll 1
-    for (int g = 0; g < GT.n; ++g) {
-      const GroupRow& G = GT.row[g];
-      double eps;
-      const int sh = split_delay(row_delay(G, L), a.inv_dt, eps);
+      for (int g = 0; g < GT.n; ++g) {
+        const GroupRow& G = GT.row[g];
+        double eps;
+        const int sh = split_delay(row_delay(G, L), ak.inv_dt, eps);
 #pragma unroll 1
-      for (int u = 0; u < G.nuse; ++u) {
-        const double v = G.sgn[u][0] * gch[0] + G.sgn[u][1] * gch[1] + G.sgn[u][2] * gch[2];
-        if (active)
-          scatter_global<N>(a.g_y + (int64_t)G.link[u] * a.n_y, p + sh - (H - 1), a.n_y, eps, v);
+        for (int u = 0; u < G.nuse; ++u) {
+          const double v =
+              G.sgn[u][0] * gch[k][0] + G.sgn[u][1] * gch[k][1] + G.sgn[u][2] * gch[k][2];
+          scatter_global<N>(ak.g_y + (int64_t)G.link[u] * ak.n_y, p + sh - (H - 1), ak.n_y, eps,
+                            v);
+        }
       }
     }
   }
@@ -153,7 +182,9 @@ template <int N, int GEN>
 __global__ __launch_bounds__(kBlock) void tdi_adjoint_kernel(TdiAdjArgs a) {
   __shared__ double acc[6 * kAdjTdiCap(N)];
   __shared__ int red[2][kBlock / 64];
-  tdi_adjoint_tile<N, GEN>(a, blockIdx.x, acc, red);
+  const TdiAdjArgs x[1] = {a};
+  const bool live[1] = {true};
+  tdi_adjoint_tile<N, GEN, 1>(x, live, blockIdx.x, acc, red);
 }
 
 // ---------------------------------------------------------------------------

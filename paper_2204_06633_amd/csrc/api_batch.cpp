@@ -22,15 +22,18 @@ constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
 
 enum Region {
   R_TPL, R_ITEMS, R_COUNTER, R_ADJ_TPL, R_TDI_ITEMS, R_PROJ_ITEMS, R_SKY_PART, R_SKY_SPAN,
-  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_GY, R_COUNT
+  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_GY, R_COUNT
 };
+
+static_assert(R_COUNT <= (int)(sizeof(((lr_batch*)nullptr)->off) / sizeof(size_t)),
+              "lr_batch.off has a slot per workspace region");
 
 struct Plan {
   int F = 0, B = 0, T_out = 0;
   std::vector<lr::BatchTemplate> tpl;
   std::vector<int> items;
   std::vector<lr::BatchAdjTemplate> adj;
-  std::vector<int64_t> tdi_items, proj_items, sky_span, like_items, like_span;
+  std::vector<int64_t> tdi_items, proj_items, sky_span, like_items, like_span, pairs;
   int64_t gy_doubles = 0, h_extent = 0, out_extent = 0, max_n_out = 0;
   size_t bytes[R_COUNT] = {};
   size_t off[R_COUNT] = {};
@@ -102,10 +105,6 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
     A.t_off_h = 0.0;                      // set by prepare (needs the orbit and t0)
     P.adj[b] = A;
     P.gy_doubles += 6 * A.n_y;
-    for (int64_t tl = 0; tl < (T.n_out + kAdjTile - 1) / kAdjTile; ++tl) {
-      P.tdi_items.push_back(b);
-      P.tdi_items.push_back(tl);
-    }
     const int64_t first = (int64_t)P.proj_items.size() / 2;
     for (int64_t tl = 0; tl < (A.n_y + kAdjTile - 1) / kAdjTile; ++tl) {
       P.proj_items.push_back(b);
@@ -128,6 +127,19 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
     P.max_n_out = std::max(P.max_n_out, T.n_out);
   }
 
+  // TDI adjoint: templates paired by duration (longer first), one work item
+  // per (pair, tile) of the longer one
+  for (int64_t q = 0; q < n; q += 2) {
+    const int64_t b0 = order_idx[q], b1 = q + 1 < n ? order_idx[q + 1] : -1;
+    const int64_t pr = (int64_t)P.pairs.size() / 2;
+    P.pairs.push_back(b0);
+    P.pairs.push_back(b1);
+    for (int64_t tl = 0; tl < (t[b0].n_out + kAdjTile - 1) / kAdjTile; ++tl) {
+      P.tdi_items.push_back(pr);
+      P.tdi_items.push_back(tl);
+    }
+  }
+
   P.bytes[R_TPL] = P.tpl.size() * sizeof(lr::BatchTemplate);
   P.bytes[R_ITEMS] = P.items.size() * sizeof(int);
   P.bytes[R_COUNTER] = sizeof(int);
@@ -139,6 +151,7 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   P.bytes[R_LIKE_ITEMS] = P.like_items.size() * sizeof(int64_t);
   P.bytes[R_LIKE_PART] = P.like_items.size() / 2 * sizeof(double);
   P.bytes[R_LIKE_SPAN] = P.like_span.size() * sizeof(int64_t);
+  P.bytes[R_PAIRS] = adjoint ? P.pairs.size() * sizeof(int64_t) : 0;
   P.bytes[R_GY] = adjoint ? (size_t)P.gy_doubles * sizeof(double) : 0;
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
@@ -239,6 +252,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   put(R_SKY_SPAN, P.sky_span.data());
   put(R_LIKE_ITEMS, P.like_items.data());
   put(R_LIKE_SPAN, P.like_span.data());
+  put(R_PAIRS, P.pairs.data());
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(ws, img.data(), P.off[R_GY], hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -337,6 +351,7 @@ int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
   a.g_hp = g_hp;
   a.g_hc = g_hc;
   a.sky_part = g_sky ? at<double>(b, R_SKY_PART) : nullptr;
+  a.pairs = at<const int64_t>(b, R_PAIRS);
   if (e == hipSuccess && b->n_tdi_items > 0) {
     a.items = at<const int64_t>(b, R_TDI_ITEMS);
     e = lr::run_batch_tdi_adjoint(b->order, b->generation, a, b->n_tdi_items, s);

@@ -212,12 +212,8 @@ namespace lr {
 // Batched adjoints: one work item = (template, tile); the per-tile bodies are
 // the single-template ones.
 // ---------------------------------------------------------------------------
-template <int N, int GEN>
-__global__ __launch_bounds__(kBlock) void batch_tdi_adjoint_kernel(BatchAdjArgs a) {
-  __shared__ double acc[6 * kAdjTdiCap(N)];
-  __shared__ int red[2][kBlock / 64];
-  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
-  const BatchAdjTemplate T = a.tpl[b];
+__device__ __forceinline__ TdiAdjArgs batch_tdi_args(const BatchAdjArgs& a,
+                                                     const BatchAdjTemplate& T) {
   TdiAdjArgs x;
   x.orb = a.orb_t;
   x.g_out = a.g_out + T.out_off;
@@ -229,7 +225,22 @@ __global__ __launch_bounds__(kBlock) void batch_tdi_adjoint_kernel(BatchAdjArgs 
   x.out_start = a.F;
   x.n_out = T.n_out;
   x.g_y = a.g_y + T.gy_off;
-  tdi_adjoint_tile<N, GEN>(x, tile, acc, red);
+  return x;
+}
+
+// Work item = (pair of templates, tile): both templates' scatters reuse each
+// interpolation weight set (the TDI delays depend on the orbits only).
+template <int N, int GEN>
+__global__ __launch_bounds__(kBlock, 4) void batch_tdi_adjoint_kernel(BatchAdjArgs a) {
+  __shared__ double acc[2 * 6 * kAdjTdiCap(N)];
+  __shared__ int red[2][kBlock / 64];
+  const int64_t pr = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  const int64_t b0 = a.pairs[2 * pr], b1 = a.pairs[2 * pr + 1];
+  TdiAdjArgs x[2];
+  x[0] = batch_tdi_args(a, a.tpl[b0]);
+  x[1] = b1 >= 0 ? batch_tdi_args(a, a.tpl[b1]) : x[0];
+  const bool live[2] = {true, b1 >= 0 && tile * kBlock < x[1].n_out};
+  tdi_adjoint_tile<N, GEN, 2>(x, live, tile, acc, red);
 }
 
 // Per-template projection-adjoint arguments of work item b.

@@ -46,7 +46,8 @@ struct BatchAdjTemplate {
 struct BatchAdjArgs {
   OrbitView orb_p, orb_t;
   const BatchAdjTemplate* tpl;  // [n_templates], caller's order
-  const int64_t* items;         // [n_items][2]: template, tile
+  const int64_t* items;         // [n_items][2]: template (TDI: pair), tile
+  const int64_t* pairs;         // [n_pairs][2]: caller indices, longer first, -1 = none
   double t_off_y;               // time of link sample 0 (= output index -F) minus the TDI grid's
   double dt, inv_dt;
   int F;                        // link samples before output 0

@@ -269,7 +269,7 @@ class lr_batch(ctypes.Structure):
                 ("n_tdi_items", ctypes.c_int64), ("n_proj_items", ctypes.c_int64),
                 ("n_like_items", ctypes.c_int64), ("gy_doubles", ctypes.c_int64),
                 ("h_extent", ctypes.c_int64), ("out_extent", ctypes.c_int64),
-                ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 12)]
+                ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 16)]
 
 
 def _batch_lib():
