@@ -415,15 +415,24 @@ __device__ __forceinline__ void project_sky_tile(const ProjAdjArgs& a, int64_t t
   }
 }
 
+// Minimum resident waves per SIMD of the projection-adjoint and sky kernels
+// (build-time tuning knobs; 1 leaves the compiler unconstrained).
+#ifndef LR_PADJ_MIN_WAVES
+#define LR_PADJ_MIN_WAVES 1
+#endif
+#ifndef LR_SKY_MIN_WAVES
+#define LR_SKY_MIN_WAVES 1
+#endif
+
 template <int N>
-__global__ __launch_bounds__(kBlock) void project_adjoint_kernel(ProjAdjArgs a) {
+__global__ __launch_bounds__(kBlock, LR_PADJ_MIN_WAVES) void project_adjoint_kernel(ProjAdjArgs a) {
   __shared__ double acc[2 * kAdjProjCap(N)];
   __shared__ ProjAdjShared sh_;
   project_adjoint_tile<N>(a, blockIdx.x, acc, sh_);
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void project_sky_kernel(ProjAdjArgs a) {
+__global__ __launch_bounds__(kBlock, LR_SKY_MIN_WAVES) void project_sky_kernel(ProjAdjArgs a) {
   __shared__ double2 win[kAdjProjCap(N)];
   __shared__ ProjAdjShared sh_;
   project_sky_tile<N>(a, blockIdx.x, win, sh_, a.sky_part + 2 * blockIdx.x);

@@ -265,7 +265,7 @@ __device__ __forceinline__ ProjAdjArgs batch_proj_args(const BatchAdjArgs& a,
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjArgs a) {
+__global__ __launch_bounds__(kBlock, LR_PADJ_MIN_WAVES) void batch_project_adjoint_kernel(BatchAdjArgs a) {
   __shared__ double acc[2 * kAdjProjCap(N)];
   __shared__ ProjAdjShared sh_;
   const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kBlock) void batch_project_adjoint_kernel(BatchAdjA
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void batch_project_sky_kernel(BatchAdjArgs a) {
+__global__ __launch_bounds__(kBlock, LR_SKY_MIN_WAVES) void batch_project_sky_kernel(BatchAdjArgs a) {
   __shared__ double2 win[kAdjProjCap(N)];
   __shared__ ProjAdjShared sh_;
   const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];

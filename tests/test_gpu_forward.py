@@ -207,3 +207,42 @@ def test_tile_boundaries(torch_cuda, n_out):
     ref = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta, case.order,
                           case.generation, case.channels)
     assert cases.rel_err(got, ref) <= TOL
+
+
+def _sky_of_direction(e_r):
+    """(lam, beta) of the unit vector e_r pointing at the source."""
+    e = np.asarray(e_r, dtype=np.float64) / np.linalg.norm(e_r)
+    return math.atan2(e[1], e[0]) % (2.0 * math.pi), math.asin(max(-1.0, min(1.0, e[2])))
+
+
+def _near_arm_sky(offset):
+    """A sky position whose propagation direction k = -e_r lies within about
+    `offset` rad of arm 1->2 at the first output time, so 1 - k.n is ~offset^2/2
+    there (the response's 1/(2(1 - k.n)) factor is large but finite)."""
+    case = cases.make_case("near_arm_probe", "keplerian", 100, 10.0, 25, 2, "AET", seed=41)
+    s = case.orbits_proj
+    k0 = int(round((case.grid.t_start - s.t0) / s.dt))
+    n12 = s.x[k0, 0] - s.x[k0, 1]
+    n12 /= np.linalg.norm(n12)
+    perp = np.cross(n12, [0.0, 0.0, 1.0])
+    perp /= np.linalg.norm(perp)
+    k = n12 * math.cos(offset) + perp * math.sin(offset)
+    return _sky_of_direction(-k)
+
+
+@pytest.mark.parametrize("sky", ["north_pole", "south_pole", "lam_zero", "lam_2pi", "near_arm"])
+def test_degenerate_sky_positions(torch_cuda, sky):
+    """Sources at the ecliptic poles, at the wrap of lambda, and nearly along an
+    arm (1 - k.n ~ 5e-3): one day of TDI-2 A/E/T on Keplerian orbits."""
+    lam, beta = {"north_pole": (1.3, math.pi / 2), "south_pole": (4.0, -math.pi / 2),
+                 "lam_zero": (0.0, 0.4), "lam_2pi": (2.0 * math.pi, 0.4),
+                 "near_arm": None}[sky] or _near_arm_sky(0.1)
+    params = np.array([1e-22, 4e-3, 1e-16, 0.7, 1.0, 0.3, lam, beta])
+    case = cases.make_case("sky_" + sky, "keplerian", 8640, 10.0, 25, 2, "AET", seed=42,
+                           params=params)
+    got = _gpu_response(torch_cuda, case)
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    ref = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta,
+                          case.order, case.generation, case.channels)
+    assert np.all(np.isfinite(got))
+    assert cases.rel_err(got, ref) <= TOL
