@@ -45,11 +45,24 @@ __device__ __forceinline__ void load_channel_grads(const double* g_out, int chan
 // ---------------------------------------------------------------------------
 constexpr int kAdjTdiCap(int N) { return kBlock + N + kSlack; }
 
+// Fold a lone scatter's value into its weights (saves N multiplies per
+// single-use delay group); build-time switch for measurements.
+#ifndef LR_TDI_ADJ_FOLD
+#define LR_TDI_ADJ_FOLD 1
+#endif
+
 // Scatter v * w_m onto N consecutive LDS entries dst[0..N-1].
 template <int N>
 __device__ __forceinline__ void scatter_lds(double* dst, const double (&w)[N], double v) {
 #pragma unroll
   for (int m = 0; m < N; ++m) atomicAdd(dst + m, w[m] * v);
+}
+
+// Scatter w_m (already scaled) onto dst[0..N-1].
+template <int N>
+__device__ __forceinline__ void scatter_lds(double* dst, const double (&w)[N]) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) atomicAdd(dst + m, w[m]);
 }
 
 // Scatter v * w_m(eps) onto ys[j0 + m], indices clamped to [0, n - 1]; a
@@ -124,9 +137,18 @@ __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs (&a)[M], const
       const GroupRow& G = GT.row[g];
       double eps;
       const int sh = split_delay(row_delay(G, L), a0.inv_dt, eps);
+      const int j0 = c0 + sh - (H - 1);
+      if (LR_TDI_ADJ_FOLD && M == 1 && G.nuse == 1) {
+        // one scatter: fold its value into the weights
+        const double v =
+            G.sgn[0][0] * gch[0][0] + G.sgn[0][1] * gch[0][1] + G.sgn[0][2] * gch[0][2];
+        double w[N];
+        lagrange_weights<N>(eps, w, v);
+        scatter_lds<N>(acc + G.link[0] * CAP + j0, w);
+        continue;
+      }
       double w[N];
       lagrange_weights<N>(eps, w);
-      const int j0 = c0 + sh - (H - 1);
 #pragma unroll 1
       for (int u = 0; u < G.nuse; ++u) {
 #pragma unroll
@@ -179,7 +201,7 @@ __device__ __forceinline__ void tdi_adjoint_tile(const TdiAdjArgs (&a)[M], const
 }
 
 template <int N, int GEN>
-__global__ __launch_bounds__(kBlock) void tdi_adjoint_kernel(TdiAdjArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void tdi_adjoint_kernel(TdiAdjArgs a) {
   __shared__ double acc[6 * kAdjTdiCap(N)];
   __shared__ int red[2][kBlock / 64];
   const TdiAdjArgs x[1] = {a};

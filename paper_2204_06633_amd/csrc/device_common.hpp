@@ -175,8 +175,10 @@ constexpr LagrangeDenoms<N> make_denoms() {
   return r;
 }
 
+// scale multiplies every weight (it starts the suffix product, so a scatter
+// of scale * w_m costs no extra multiply).
 template <int N>
-__device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N]) {
+__device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N], double scale = 1.0) {
   constexpr LagrangeDenoms<N> C = make_denoms<N>();
   constexpr int H = N / 2;
   double pre = 1.0;
@@ -185,7 +187,7 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N]) {
     w[m] = pre;
     pre *= eps - (double)(m - (H - 1));
   }
-  double suf = 1.0;
+  double suf = scale;
 #pragma unroll
   for (int m = N - 1; m >= 0; --m) {
     w[m] *= suf * C.c[m];
