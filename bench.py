@@ -359,6 +359,17 @@ def main():
     log("forward + adjoint of the same template")
     ms_fa = _timed(fwd_adj, max(3, args.steps // 2), 1)
 
+    # the same template through the fused batch kernel (a batch of one)
+    log("the same template as a batch of one (fused kernel)")
+    one = native.Batch([(0, g.n_h, g.out_start, g.n_out, 0)], orb, orb, g.t_start, g.dt,
+                       case.order, case.generation, case.channels, group=1, device=dev)
+    out1 = torch.empty(one.out_extent, dtype=torch.float64, device=dev)
+    sky1 = sky.view(1, 2)
+    ms_one = _timed(lambda: one.response(hp, hc, sky1, out=out1), args.steps, 2)
+    err_one = cases.rel_err(one.output_block(out1, 0)[:, torch.from_numpy(idx).to(dev)].cpu().numpy(),
+                            ref)
+    del out1
+
     n = g.n_out
     value = 6.0 * n / (ms_step * 1e-3)
     f_tdi = costs.tdi_flops_per_sample(case.order, case.generation, case.channels) * n
@@ -404,6 +415,11 @@ def main():
                         "ms_per_step": ms_fa,
                         "step": "forward, white-noise likelihood over A/E/T with gradient, "
                                 "adjoint to h+, hx and (lam, beta)"},
+        "fused_single": {"value": 6.0 * n / (ms_one * 1e-3),
+                         "unit": "samples/s (templates×links×time)", "ms_per_step": ms_one,
+                         "step": "the headline template through lr_response (fused projection "
+                                 "+ TDI, link series kept in LDS), group 1",
+                         "parity_rel_err": err_one},
     }
     if not args.no_batch:
         del y, data, g_buf
