@@ -107,6 +107,20 @@ __device__ __forceinline__ void add_position(int p, const double (&xip)[3],
   }
 }
 
+// add_position for a position index known only at run time: the links are
+// selected by comparisons, so the accumulators stay in registers.
+__device__ __forceinline__ void add_position_rt(int p, const double (&xip)[3],
+                                                const double (&xic)[3], double hp, double hc,
+                                                double (&num)[6]) {
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const int arm = kArm[l];
+    const double v = xip[arm] * hp + xic[arm] * hc;
+    const bool emit = p == 3 + l, recv = p == kLinkRecv[l] - 1;
+    num[l] += emit ? v : (recv ? -v : 0.0);
+  }
+}
+
 // Per-sample state of the projection: what the link assembly needs.
 struct ProjSample {
   int sh[9];
@@ -205,11 +219,14 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
     }
   } else {
     // Window larger than the LDS tile (very small dt or extreme orbits):
-    // read the stencils from global memory, indices clamped.
-#pragma unroll
+    // read the stencils from global memory, indices clamped.  A rolled loop
+    // over copies of the per-sample state (which may then live in scratch):
+    // this rare path must not set the register budget of the LDS path.
+    const ProjSample Ac = A, Bc = B;
+#pragma unroll 1
     for (int p = 0; p < 9; ++p) {
-      LagrangeStream<N> sa(A.ep[p]), sb(B.ep[p]);
-      const int64_t ja = qa + A.sh[p] - (H - 1), jb = qa + 1 + B.sh[p] - (H - 1);
+      LagrangeStream<N> sa(Ac.ep[p]), sb(Bc.ep[p]);
+      const int64_t ja = qa + Ac.sh[p] - (H - 1), jb = qa + 1 + Bc.sh[p] - (H - 1);
       double pa = 0.0, ca = 0.0, pb = 0.0, cb = 0.0;
 #pragma unroll 1
       for (int m = 0; m < N; ++m) {
@@ -224,8 +241,8 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
         pb = sb.step(pb, hp[j], m);
         cb = sb.step(cb, hc[j], m);
       }
-      add_position(p, A.xip, A.xic, pa, ca, na);
-      add_position(p, B.xip, B.xic, pb, cb, nb);
+      add_position_rt(p, A.xip, A.xic, pa, ca, na);
+      add_position_rt(p, B.xip, B.xic, pb, cb, nb);
     }
   }
   // the streams' common scale folded into the link normalisation
@@ -277,94 +294,6 @@ void project_links_kernel(ProjArgs a) {
       dst[0] = ya[l];
       if (act_b) dst[1] = yb[l];
     }
-  }
-}
-
-// One link sample per lane, kBlock samples per workgroup: half the live
-// per-lane state of project_pair (more resident waves) for twice the LDS
-// reads per sample (the stencils of neighbouring samples are not shared).
-// Build-time choice: LR_PROJ_SAMPLES_PER_LANE = 1 or 2 (default).
-#ifndef LR_PROJ_SAMPLES_PER_LANE
-#define LR_PROJ_SAMPLES_PER_LANE 2
-#endif
-#ifndef LR_PROJ1_MIN_WAVES
-#define LR_PROJ1_MIN_WAVES 1
-#endif
-
-template <int N>
-__global__ __launch_bounds__(kBlock, LR_PROJ1_MIN_WAVES)
-void project_links1_kernel(ProjArgs a) {
-  constexpr int H = N / 2;
-  constexpr int CAP = kBlock + N + kSlack;
-  __shared__ double2 win[CAP];
-  __shared__ int red[2][kBlock / 64];
-  __shared__ double s_trig[2][2];
-
-  const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock;
-  const bool active = i0 + tid < a.n_y;
-  const int r = active ? tid : (int)(a.n_y - 1 - i0);
-  const int64_t q = a.y_start + i0 + r;          // h index of the link sample
-
-  const SkyTrig tr = load_sky(a.sky, s_trig);
-  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
-  ProjSample A;
-  proj_sample(a.orb, a.t_off + (double)q * a.dt, a.inv_dt, sk, A);
-  int lo = A.sh[0], hi = A.sh[0];
-#pragma unroll
-  for (int p = 1; p < 9; ++p) { lo = min(lo, A.sh[p]); hi = max(hi, A.sh[p]); }
-  int wlo, whi;
-  block_range<kBlock>(r + lo - (H - 1), r + hi + H, red, wlo, whi);
-  const int count = whi - wlo + 1;
-  const int64_t base = a.y_start + i0 + wlo;
-  const int64_t hmax = a.n_h - 1;
-
-  double num[6] = {0, 0, 0, 0, 0, 0};
-  if (count > 0 && count <= CAP) {
-    for (int k = tid; k < count; k += kBlock) {
-      int64_t j = base + k;
-      j = j < 0 ? 0 : (j > hmax ? hmax : j);
-      win[k] = make_double2(a.hp[j], a.hc[j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      LagrangeStream<N> st(A.ep[p]);
-      const int off = r + A.sh[p] - (H - 1) - wlo;
-      double vp = 0.0, vc = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double2 v = win[off + k];
-        st.tap(k);
-        vp = st.step(vp, v.x, k);
-        vc = st.step(vc, v.y, k);
-      }
-      add_position(p, A.xip, A.xic, vp, vc, num);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  } else {
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      LagrangeStream<N> st(A.ep[p]);
-      const int64_t j0 = q + A.sh[p] - (H - 1);
-      double vp = 0.0, vc = 0.0;
-#pragma unroll 1
-      for (int k = 0; k < N; ++k) {
-        int64_t j = j0 + k;
-        j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        st.tap(k);
-        vp = st.step(vp, a.hp[j], k);
-        vc = st.step(vc, a.hc[j], k);
-      }
-      add_position(p, A.xip, A.xic, vp, vc, num);
-    }
-  }
-  if (!active) return;
-#pragma unroll
-  for (int l = 0; l < 6; ++l) {
-    const int arm = kArm[l];
-    a.y[(int64_t)l * a.n_y + i0 + r] =
-        LagrangeStream<N>::finish(num[l]) / (2.0 * (1.0 - kDir[l] * A.kn[arm]));
   }
 }
 
@@ -647,13 +576,8 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
 // ---------------------------------------------------------------------------
 template <int N>
 hipError_t launch_project(const ProjArgs& a, hipStream_t s) {
-  if (LR_PROJ_SAMPLES_PER_LANE == 1) {
-    const int64_t blocks = (a.n_y + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(project_links1_kernel<N>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  } else {
-    const int64_t blocks = (a.n_y + kFwdTile - 1) / kFwdTile;
-    hipLaunchKernelGGL(project_links_kernel<N>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  }
+  const int64_t blocks = (a.n_y + kFwdTile - 1) / kFwdTile;
+  hipLaunchKernelGGL(project_links_kernel<N>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
