@@ -138,6 +138,13 @@ __device__ __forceinline__ void proj_sample(const OrbitView& orb, double tau, do
   for (int k = 0; k < 3; ++k) { s.xip[k] = g.xip[k]; s.xic[k] = g.xic[k]; s.kn[k] = g.kn[k]; }
 }
 
+// Window loads kept in flight per stream in project_pair (0: the compiler's
+// own schedule).  Build-time tuning knob (sched_group_barrier masks: 0x100
+// LDS reads, 0x002 VALU).
+#ifndef LR_PROJ_PIPE
+#define LR_PROJ_PIPE 4
+#endif
+
 // Link responses of one template at the lane's two tile samples ra and ra+1
 // (ra even).  Tile element r has h-index hq0 + r and orbit time
 // t_off + (ti0 + r) * dt.  Uses the workgroup's LDS window and reduction
@@ -188,6 +195,13 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
         // sample b's stencil is sample a's shifted by one: N + 1 loads feed both
 #pragma unroll
         for (int k = 0; k <= N; ++k) {
+          if (LR_PROJ_PIPE > 0) {
+            // at most LR_PROJ_PIPE window loads in flight: bounds the registers
+            // the scheduler spends on early loads
+            if (k == 0) __builtin_amdgcn_sched_group_barrier(0x100, LR_PROJ_PIPE, 0);
+            if (k + LR_PROJ_PIPE <= N) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+          }
           const double2 v = win[src.at(k)];
           if (k < N) {
             sa.tap(k);
@@ -204,6 +218,11 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
         const ParStream<CAP> srb(ra + 1 + B.sh[p] - (H - 1) - wlo);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
+          if (LR_PROJ_PIPE > 0) {
+            if (k == 0) __builtin_amdgcn_sched_group_barrier(0x100, 2 * LR_PROJ_PIPE, 0);
+            if (k + LR_PROJ_PIPE < N) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
+          }
           const double2 v = win[src.at(k)], w = win[srb.at(k)];
           sa.tap(k);
           sb.tap(k);
