@@ -142,7 +142,7 @@ __device__ __forceinline__ void proj_sample(const OrbitView& orb, double tau, do
 // own schedule).  Build-time tuning knob (sched_group_barrier masks: 0x100
 // LDS reads, 0x002 VALU).
 #ifndef LR_PROJ_PIPE
-#define LR_PROJ_PIPE 4
+#define LR_PROJ_PIPE 2
 #endif
 
 // Link responses of one template at the lane's two tile samples ra and ra+1
