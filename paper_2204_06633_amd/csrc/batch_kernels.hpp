@@ -45,14 +45,14 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
     // The padding bound keeps every stored output's stencil inside the tile;
     // the clamp only guards the idle lanes past a template's end.
     const int top = YT - 1 - N;
-    const ParStream<YT> pa_(min(max(c0 + sa - (H - 1), 0), top)),
-        pb_(min(max(c0 + 1 + sb - (H - 1), 0), top));
+    const ParStream<YT> pa_(min(max(c0 + sa - (H - 1), 0), top));
+    const int jb0 = min(max(c0 + 1 + sb - (H - 1), 0), top);
     if (G.nuse == 1) {
       const double* w[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) w[k] = ylds + (k * 6 + G.link[0]) * YT;
       double xa[M], xb[M];
-      stream_multi<N, YT, M>(ea, eb, same, w, pa_, pb_, xa, xb);
+      stream_multi<N, YT, M>(ea, eb, same, w, pa_, jb0, xa, xb);
 #pragma unroll
       for (int k = 0; k < M; ++k)
 #pragma unroll
@@ -68,7 +68,7 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
         w[2 * k + 1] = ylds + (k * 6 + G.link[1]) * YT;
       }
       double xa[2 * M], xb[2 * M];
-      stream_multi<N, YT, 2 * M>(ea, eb, same, w, pa_, pb_, xa, xb);
+      stream_multi<N, YT, 2 * M>(ea, eb, same, w, pa_, jb0, xa, xb);
 #pragma unroll
       for (int k = 0; k < M; ++k)
 #pragma unroll

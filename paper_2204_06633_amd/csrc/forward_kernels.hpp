@@ -83,7 +83,8 @@ __device__ __forceinline__ int par(int j) {
 template <int CAP>
 struct ParStream {
   int first, second;
-  __device__ __forceinline__ explicit ParStream(int j0) : first(par<CAP>(j0)), second(par<CAP>(j0 + 1)) {}
+  __device__ __forceinline__ explicit ParStream(int j0)
+      : first(par<CAP>(j0)), second(first + ((j0 & 1) ? 1 - (CAP + 1) / 2 : (CAP + 1) / 2)) {}
   __device__ __forceinline__ int at(int k) const { return (k & 1) ? second + (k >> 1) : first + (k >> 1); }
 };
 
@@ -408,13 +409,13 @@ __device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int cha
 // S series (measured links, possibly of several templates) that share one
 // delay, for both samples of a lane, from parity-split LDS rows w[s]: sa_
 // starts sample a's stencil; if `same`, sample b's stencil is the next
-// window position, otherwise it starts at sb_.  One product chain per
+// window position, otherwise it starts at element jb0.  One product chain per
 // sample serves all S series.  Returns the streams' unscaled values
 // (LagrangeStream<N>::finish scales).
 template <int N, int CAP, int S>
 __device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
                                              const double* const (&w)[S],
-                                             const ParStream<CAP>& sa_, const ParStream<CAP>& sb_,
+                                             const ParStream<CAP>& sa_, int jb0,
                                              double (&xa)[S], double (&xb)[S]) {
   LagrangeStream<N> A(ea), B(eb);
 #pragma unroll
@@ -437,6 +438,7 @@ __device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
       }
     }
   } else {
+    const ParStream<CAP> sb_(jb0);             // only here: most waves take `same`
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       A.tap(k);
@@ -525,11 +527,12 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
       const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
       const bool same = __all(sa == sb);
-      const ParStream<CAP> pa_(c0 + sa - (H - 1)), pb_(c0 + 1 + sb - (H - 1));
+      const ParStream<CAP> pa_(c0 + sa - (H - 1));
+      const int jb0 = c0 + 1 + sb - (H - 1);
       if (G.nuse == 1) {
         const double* const w[1] = {win + G.link[0] * CAP};
         double xa[1], xb[1];
-        stream_multi<N, CAP, 1>(ea, eb, same, w, pa_, pb_, xa, xb);
+        stream_multi<N, CAP, 1>(ea, eb, same, w, pa_, jb0, xa, xb);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           acc_a[c] = fma(G.sgn[0][c], xa[0], acc_a[c]);
@@ -538,7 +541,7 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       } else {
         const double* const w[2] = {win + G.link[0] * CAP, win + G.link[1] * CAP};
         double xa[2], xb[2];
-        stream_multi<N, CAP, 2>(ea, eb, same, w, pa_, pb_, xa, xb);
+        stream_multi<N, CAP, 2>(ea, eb, same, w, pa_, jb0, xa, xb);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           acc_a[c] = fma(G.sgn[0][c], xa[0], fma(G.sgn[1][c], xa[1], acc_a[c]));
