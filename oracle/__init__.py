@@ -5,8 +5,9 @@ benchmark's CPU-baseline leg may use it; the product path never does.  It
 shares no code with the HIP library and never imports it.
 
 Pieces and the passages of arXiv:2204.06633 they follow:
-  * orbit interpolation ("interpolated and then evaluated at each time step",
-    Sec. IV.E): not-a-knot cubic splines from scipy, evaluated in C;
+  * orbit interpolation (the coarse orbit data are interpolated once and
+    evaluated at every sample time, Sec. IV.E): not-a-knot cubic splines from
+    scipy, evaluated in C;
   * link projection y_ij (Sec. IV.B) and Michelson X1/X2 with Y, Z by cyclic
     relabelling (Sec. IV.C) in ``oracle.c``;
   * A, E, T (Sec. IV.C) and the white-noise log-likelihood -<d-h|d-h>/2 summed
