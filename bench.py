@@ -359,6 +359,36 @@ def main():
     log("forward + adjoint of the same template")
     ms_fa = _timed(fwd_adj, max(3, args.steps // 2), 1)
 
+    # the differentiation step: source parameters -> polarisations (torch)
+    # -> response -> A/E/T likelihood -> hand-written adjoint -> autograd to
+    # the eight parameters (the paper's Fig. 3 binary, data = injection +
+    # white noise sigma = 1e-21)
+    from paper_2204_06633_amd import inputs, waveform
+    log("likelihood gradient with respect to the source parameters")
+    tpl_aet = response.Template(orb, orb, g, case.order, case.generation, "AET")
+    t_w = torch.tensor(g.waveform_times(), dtype=torch.float64, device=dev)
+    theta = torch.tensor(inputs.PAPER_FIG3_BINARY, dtype=torch.float64, device=dev)
+    with torch.no_grad():
+        hp0, hc0 = waveform.gb_polarizations(theta, t_w)
+        inj, _ = response.plain_forward(tpl_aet, hp0.contiguous(), hc0.contiguous(),
+                                        theta[6:8].contiguous())
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(4)
+        data_aet = inj + 1e-21 * torch.randn(inj.shape, dtype=torch.float64, device=dev,
+                                             generator=gen)
+        del hp0, hc0, inj
+
+    def grad_step():
+        p = theta.clone().requires_grad_(True)
+        hp_, hc_ = waveform.gb_polarizations(p, t_w)
+        ll = response.loglike(response.response(tpl_aet, hp_, hc_, p[6:8]), data_aet, 1e-21)
+        ll.backward()
+        return p.grad
+
+    ms_grad = _timed(grad_step, max(3, args.steps // 2), 1)
+    grad_ok = bool(torch.isfinite(grad_step()).all())
+    del data_aet
+
     # the same template through the fused batch kernel (a batch of one)
     log("the same template as a batch of one (fused kernel)")
     one = native.Batch([(0, g.n_h, g.out_start, g.n_out, 0)], orb, orb, g.t_start, g.dt,
@@ -415,6 +445,11 @@ def main():
                         "ms_per_step": ms_fa,
                         "step": "forward, white-noise likelihood over A/E/T with gradient, "
                                 "adjoint to h+, hx and (lam, beta)"},
+        "gradient_step": {"value": 6.0 * n / (ms_grad * 1e-3),
+                          "unit": "samples/s (templates×links×time)", "ms_per_step": ms_grad,
+                          "step": "8 source parameters -> h+, hx (torch) -> response (A/E/T) -> "
+                                  "likelihood -> adjoint -> autograd to the parameters",
+                          "gradient_finite": grad_ok},
         "fused_single": {"value": 6.0 * n / (ms_one * 1e-3),
                          "unit": "samples/s (templates×links×time)", "ms_per_step": ms_one,
                          "step": "the headline template through lr_response (fused projection "
