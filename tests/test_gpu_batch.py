@@ -206,3 +206,41 @@ def test_group_and_grid_do_not_change_results(torch_cuda, tmp_path):
     out = b.response(hp, hc, sky)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("order,dt", [(1, 10.0), (31, 10.0), (25, 0.25)])
+def test_fused_forward_orders_and_small_dt(torch_cuda, order, dt):
+    """Extreme orders, and dt = 0.25 s, where the projection window of a tile
+    no longer fits the LDS window and the fused kernel reads h from global
+    memory (TDI still fits)."""
+    torch = torch_cuda
+    n_out_list = [700, 1500, 1]
+    B = _build(torch, n_out_list, order=order, group=2, dt=dt, seed=31 + order)
+    out = B["batch"].response(_t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"]))
+    torch.cuda.synchronize()
+    for k in range(len(n_out_list)):
+        got = B["batch"].output_block(out, k).cpu().numpy()
+        assert cases.rel_err(got, _oracle_out(B, k)) <= TOL, k
+
+
+def test_batch_adjoint_small_dt_against_oracle(torch_cuda):
+    """dt = 0.25 s: the adjoint footprints exceed the LDS tiles, so the paired
+    TDI adjoint and the projection adjoint scatter to global memory."""
+    torch = torch_cuda
+    n_out_list = [900, 400]
+    B = _build(torch, n_out_list, group=2, adjoint=True, seed=77, dt=0.25)
+    batch = B["batch"]
+    hp, hc, sky = _t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"])
+    rng = np.random.default_rng(3)
+    g_out = _t(torch, rng.standard_normal(batch.out_extent))
+    ghp, ghc, _ = batch.adjoint(hp, hc, sky, g_out, want_sky=False)
+    torch.cuda.synchronize()
+    op = oracle.Orbits.from_samples(B["sp"])
+    for k, n in enumerate(n_out_list):
+        g = B["grids"][k]
+        ho, oo = B["lay"].h_offsets[k], B["lay"].out_offsets[k]
+        rhp, rhc = oracle.response_adjoint(op, op, g, B["params"][k][6], B["params"][k][7], 25,
+                                           2, g_out[oo:oo + 3 * n].view(3, n).cpu().numpy(),
+                                           "AET")
+        got = np.stack([ghp[ho:ho + g.n_h].cpu().numpy(), ghc[ho:ho + g.n_h].cpu().numpy()])
+        assert cases.rel_err(got, np.stack([rhp, rhc])) <= 1e-10, k
