@@ -108,8 +108,11 @@ template <int N, int GEN, int M>
 __global__ __launch_bounds__(kBlock, LR_FUSED_MIN_WAVES) void fused_forward_kernel(BatchFwdArgs a) {
   constexpr int YT = kFwdTile;
   constexpr int CAPH = kFwdTile + N + kSlack;
-  __shared__ double ylds[M * 6 * YT];
-  __shared__ double2 hwin[CAPH];
+  // Template k's h window lives in its own link rows until its projection
+  // ends (the rows are written only after a barrier), so the window costs no
+  // LDS of its own.
+  static_assert(CAPH * sizeof(double2) <= 6 * YT * sizeof(double), "h window fits a row block");
+  __shared__ __align__(16) double ylds[M * 6 * YT];
   __shared__ int red[2][kBlock / 64];
   __shared__ double s_trig[2][2];
   __shared__ int s_item;
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(kBlock, LR_FUSED_MIN_WAVES) void fused_forward_kern
       const int last = r_end - 1;
       const bool act_a = 2 * tid <= last, act_b = 2 * tid + 1 <= last;
       const int ra = act_a ? 2 * tid : (last & ~1);
-      __syncthreads();                                // s_trig and hwin free
+      __syncthreads();                                // s_trig free
       if (tid < 2) {
         double sn, cs;
         sincos(a.sky[2 * T.index + tid], &sn, &cs);
@@ -151,8 +154,10 @@ __global__ __launch_bounds__(kBlock, LR_FUSED_MIN_WAVES) void fused_forward_kern
       __syncthreads();
       const Sky sk = sky_from_trig(s_trig[0][0], s_trig[0][1], s_trig[1][0], s_trig[1][1]);
       double ya[6], yb[6];
+      double2* hwin = reinterpret_cast<double2*>(ylds + k * 6 * YT);
       project_pair<N>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, a.hp + T.h_off,
                       a.hc + T.h_off, T.n_h, T.out_start + i_base, sk, ra, hwin, red, ya, yb);
+      __syncthreads();                                // the window is read; rows may be written
 #pragma unroll
       for (int l = 0; l < 6; ++l) {
         double* row = ylds + (k * 6 + l) * YT;
