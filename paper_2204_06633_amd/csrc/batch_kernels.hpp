@@ -98,14 +98,19 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
 }
 
 // Minimum resident waves per SIMD for the fused kernel's register budget
-// (build-time tuning knob; 1 leaves the compiler unconstrained, 2 measured
-// fastest: the LDS of a group-2 work item allows two groups per CU).
+// (build-time tuning knobs; 1 leaves the compiler unconstrained).  Measured
+// fastest: two for groups of 1 and 4, three for groups of 2 (whose 49 KB of
+// LDS let three work-groups share a CU).
 #ifndef LR_FUSED_MIN_WAVES
 #define LR_FUSED_MIN_WAVES 2
 #endif
+#ifndef LR_FUSED2_MIN_WAVES
+#define LR_FUSED2_MIN_WAVES 3
+#endif
 
 template <int N, int GEN, int M>
-__global__ __launch_bounds__(kBlock, LR_FUSED_MIN_WAVES) void fused_forward_kernel(BatchFwdArgs a) {
+__global__ __launch_bounds__(kBlock, M == 2 ? LR_FUSED2_MIN_WAVES : LR_FUSED_MIN_WAVES)
+void fused_forward_kernel(BatchFwdArgs a) {
   constexpr int YT = kFwdTile;
   constexpr int CAPH = kFwdTile + N + kSlack;
   // Template k's h window lives in its own link rows until its projection
