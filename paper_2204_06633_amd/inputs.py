@@ -297,3 +297,47 @@ def make_template_grid(orbits, order, dt, t_start, n_out, gen=2):
 def orbit_span_for(grid: TemplateGrid):
     """Absolute time range the orbits must cover for a template grid."""
     return grid.t0_h, grid.t0_h + (grid.n_h - 1) * grid.dt
+
+
+# --------------------------------------------------------------------------
+# Noise curve for the frequency-domain likelihood (Sec. II.A)
+# --------------------------------------------------------------------------
+def noise_psd_aet(f, L=L_ARM, generation=2, acc=3e-15, oms=15e-12):
+    """One-sided noise PSDs (S_AE, S_T) of the A/E and T channels, fractional
+    frequency, for equal arms.
+
+    A stand-in for the paper's tabulated design curve: test-mass acceleration
+    noise ``acc`` m s^-2 / sqrt(Hz) reddened below 0.4 mHz and whitened above
+    8 mHz, optical-metrology noise ``oms`` m / sqrt(Hz) reddened below 2 mHz,
+    propagated through the equal-arm Michelson combinations (second
+    generation: times 4 sin^2(2x)), x = 2 pi f L / c.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    s_acc = (acc ** 2 * (1.0 + (4e-4 / f) ** 2) * (1.0 + (f / 8e-3) ** 4)
+             / (2.0 * math.pi * f * C_LIGHT) ** 2)
+    s_oms = oms ** 2 * (1.0 + (2e-3 / f) ** 4) * (2.0 * math.pi * f / C_LIGHT) ** 2
+    x = 2.0 * math.pi * f * L / C_LIGHT
+    sx2 = np.sin(x) ** 2
+    s_ae = 8.0 * sx2 * (2.0 * s_acc * (3.0 + 2.0 * np.cos(x) + np.cos(2.0 * x))
+                        + s_oms * (2.0 + np.cos(x)))
+    s_t = 16.0 * s_oms * (1.0 - np.cos(x)) * sx2 + 128.0 * s_acc * sx2 * np.sin(0.5 * x) ** 4
+    if generation == 2:
+        g2 = 4.0 * np.sin(2.0 * x) ** 2
+        s_ae, s_t = s_ae * g2, s_t * g2
+    return s_ae, s_t
+
+
+def noise_weights(n_fft, dt, f_min=1e-4, f_max=2.5e-2, generation=2, L=L_ARM):
+    """Bin weights w_k = 4 df / S_n(f_k), k = 0 .. n_fft/2, for the A/E and
+    the T channel; zero outside [f_min, f_max] (the band stops below the
+    first zero of the second-generation transfer function, c / (4 L))."""
+    k = np.arange(n_fft // 2 + 1)
+    f = k / (n_fft * dt)
+    df = 1.0 / (n_fft * dt)
+    band = (f >= f_min) & (f <= f_max)
+    w_ae = np.zeros(k.shape)
+    w_t = np.zeros(k.shape)
+    s_ae, s_t = noise_psd_aet(f[band], L=L, generation=generation)
+    w_ae[band] = 4.0 * df / s_ae
+    w_t[band] = 4.0 * df / s_t
+    return w_ae, w_t
