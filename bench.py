@@ -15,6 +15,9 @@ the oracle's own throughput on a bounded sample on the host cores.
 Beside the headline it reports, in the same line:
   fwd_adjoint          the same template, forward + likelihood + adjoint
                        (gradients to h+, hx and the sky angles) per step;
+  fd_likelihood,       the noise-weighted frequency-domain likelihood of its
+  fd_fwd_adjoint       A/E/T (2^22-point transforms) alone, and in the
+                       forward + likelihood + adjoint step;
   batched_forward      512 templates of uneven durations (0.25-1 yr at
                        dt = 10 s) in one persistent fused launch, replayed
                        from a HIP graph, autotuned, against the plain
@@ -359,6 +362,30 @@ def main():
     log("forward + adjoint of the same template")
     ms_fa = _timed(fwd_adj, max(3, args.steps // 2), 1)
 
+    # the same step with the noise-weighted frequency-domain likelihood (the
+    # stand-in noise curve; data = the template itself, no noise, as in the
+    # paper's runs)
+    from paper_2204_06633_amd import inputs
+    log("forward + frequency-domain likelihood + adjoint of the same template")
+    n_fft = native.fd_length(g.n_out)
+    w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
+    plan = native.FdPlan(data, torch.tensor(w_ae, dtype=torch.float64, device=dev),
+                         torch.tensor(w_t, dtype=torch.float64, device=dev), g.dt)
+    fd_stats = torch.empty((1, 3), dtype=torch.float64, device=dev)
+
+    def fd_fwd_adj():
+        response.plain_forward(tpl, hp, hc, sky, y=y, out=out)
+        plan.loglike(out[3:], stats=fd_stats, g_h=g_buf[3:])
+        response.plain_adjoint(tpl, hp, hc, sky, g_buf)
+
+    ms_fd_fa = _timed(fd_fwd_adj, max(3, args.steps // 2), 1)
+    ms_fd = _timed(lambda: plan.loglike(out[3:], stats=fd_stats, g_h=g_buf[3:]), args.steps, 2)
+    ms_fd_stats = _timed(lambda: plan.loglike(out[3:], want_grad=False, stats=fd_stats),
+                         args.steps, 2)
+    fd_b = costs.fd_bytes(g.n_out, n_fft, 3, plan.passes, True)
+    fd_b_stats = costs.fd_bytes(g.n_out, n_fft, 3, plan.passes, False)
+    del plan
+
     # the differentiation step: source parameters -> polarisations (torch)
     # -> response -> A/E/T likelihood -> hand-written adjoint -> autograd to
     # the eight parameters (the paper's Fig. 3 binary, data = injection +
@@ -445,6 +472,17 @@ def main():
                         "ms_per_step": ms_fa,
                         "step": "forward, white-noise likelihood over A/E/T with gradient, "
                                 "adjoint to h+, hx and (lam, beta)"},
+        "fd_likelihood": {"ms": ms_fd, "ms_stats_only": ms_fd_stats, "n_fft": n_fft,
+                          "hbm_GBps": fd_b / (ms_fd * 1e-3) / 1e9,
+                          "hbm_frac": fd_b / (ms_fd * 1e-3) / costs.HBM_PEAK,
+                          "bytes": fd_b,
+                          "hbm_frac_stats_only": fd_b_stats / (ms_fd_stats * 1e-3) / costs.HBM_PEAK,
+                          "step": "lr_fd_loglike on the template's A/E/T: <d-h|d-h>, <h|h>, "
+                                  "<d|h> with the stand-in noise curve and d logL/dh"},
+        "fd_fwd_adjoint": {"value": 6.0 * n / (ms_fd_fa * 1e-3),
+                           "unit": "samples/s (templates×links×time)", "ms_per_step": ms_fd_fa,
+                           "step": "forward, frequency-domain likelihood over A/E/T with "
+                                   "gradient, adjoint to h+, hx and (lam, beta)"},
         "gradient_step": {"value": 6.0 * n / (ms_grad * 1e-3),
                           "unit": "samples/s (templates×links×time)", "ms_per_step": ms_grad,
                           "step": "8 source parameters -> h+, hx (torch) -> response (A/E/T) -> "

@@ -270,6 +270,67 @@ int lr_batch_loglike(const lr_batch *b, const double *out, const double *data, d
  * late and find the work list drained.  Errors: LR_E_ARG. */
 int lr_batch_set_grid(lr_batch *b, int blocks);
 
+/* ------------------------------------------------------------------------
+ * Frequency-domain likelihood, Sec. II.A (the noise-weighted inner product,
+ * log L = -<d-h|d-h>/2, optimal SNR sqrt(<h|h>), extraction SNR
+ * <d|h>/sqrt(<h|h>)), discretised as
+ *   <a|b> = sum_{k=0}^{N/2} w_k Re(conj(a~_k) b~_k),
+ *   a~_k  = dt sum_{j<N} a_j exp(-2 pi i k j / N),
+ * every series zero-padded to N = lr_fd_length(n) samples; w_k = 4 df /
+ * S_n(f_k) with df = 1/(N dt) is supplied by the caller (0 drops a bin).
+ * Channels: A, E (sharing the weights w_ae) and optionally T (weights w_t),
+ * each a series of n samples.  For every template h and the data d:
+ *   stats = (rr, hh, dh) = (<d-h|d-h>, <h|h>, <d|h>), summed over channels,
+ *   g_h_j = d log L / d h_j = dt sum_{k=0}^{N/2} w_k Re(r~_k exp(+2 pi i k j / N)),
+ * r = d - h.  The transforms run in FP64 on power-of-two sizes; results
+ * match an exact evaluation to FFT rounding (relative ~1e-15 log2 N of the
+ * weighted norms).
+ * ---------------------------------------------------------------------- */
+
+/* Filled by lr_fd_prepare; treat as opaque. */
+typedef struct {
+    int64_t n, n_fft, max_batch;
+    int channels, log2n, passes, q[3];
+    double dt;
+    void *ws;
+    size_t ws_bytes;
+    size_t off[6];       /* workspace region offsets (bytes) */
+} lr_fd_plan;
+
+/* Transform length for n samples: the smallest power of two >= max(n, 4096);
+ * -1 if n < 1 or n > 2^24. */
+int64_t lr_fd_length(int64_t n);
+
+/* Device workspace bytes of a plan for n samples, channels 2 (A, E) or 3
+ * (A, E, T), and up to max_batch templates per launch sequence; 0 if the
+ * arguments are invalid.  About (48 + 32 channels/2 x max_batch) bytes per
+ * transform point. */
+size_t lr_fd_workspace(int64_t n, int channels, int64_t max_batch);
+
+/* Build a plan in the caller's workspace ws (device, ws_bytes >=
+ * lr_fd_workspace): twiddle tables, the weights in transform order and the
+ * data spectrum.  data: device, channel c's n samples at data + c *
+ * data_cstride (data_cstride >= n); w_ae, w_t: device [N/2 + 1] (w_t
+ * unused, may be NULL, when channels == 2).  The inputs are read on
+ * `stream` and may be freed once it has passed this call; the plan keeps
+ * pointers into ws only.  Errors: LR_E_ARG (sizes, null pointers, overlap
+ * with ws), LR_E_UNSUPPORTED (n > 2^24), LR_E_WORKSPACE, LR_E_HIP. */
+int lr_fd_prepare(int64_t n, int channels, double dt, const double *data, int64_t data_cstride,
+                  const double *w_ae, const double *w_t, int64_t max_batch, void *ws,
+                  size_t ws_bytes, lr_fd_plan *out, void *stream);
+
+/* Statistics (and gradient) of n_templates templates: template t's channel c
+ * at h + t * t_stride + c * c_stride (c_stride >= n, t_stride >= (channels -
+ * 1) * c_stride + n); stats: device [n_templates][3] (rr, hh, dh); g_h: NULL
+ * or device, laid out like h, receives d log L / d h (every sample of every
+ * channel overwritten).  Templates are processed max_batch at a time.
+ * Deterministic (fixed-order sums).  Graph-capturable; calls sharing one plan
+ * (its workspace) must not overlap.  Errors: LR_E_ARG (unprepared plan, null
+ * pointer, strides, g_h or stats overlapping an input or the workspace),
+ * LR_E_HIP. */
+int lr_fd_loglike(const lr_fd_plan *p, int64_t n_templates, const double *h, int64_t t_stride,
+                  int64_t c_stride, double *stats, double *g_h, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,3 +57,31 @@ def projection_bytes_per_sample():
 # MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 FLOPs (FMA) x 2.4 GHz.
 FP64_VECTOR_PEAK = 256 * 4 * 16 * 2 * 2.4e9                  # 78.6 TFLOP/s
 HBM_PEAK = 8.0e12                                            # bytes/s
+
+
+def fd_bytes(n, n_fft, channels=3, passes=3, grad=True):
+    """HBM bytes per template of the frequency-domain likelihood as the
+    passes move them: the first forward pass reads the channel series and
+    writes the complex signals (A + iE, and T + i0 with T), middle passes
+    read and write them, the last forward pass also reads the data spectrum
+    and the weights, and with the gradient every inverse pass reads and
+    writes again, the last one writing the channel series.  The minimum any
+    method must move (series in, gradient out, data spectrum and weights in)
+    is ``fd_io_bytes``."""
+    sig = 2 if channels == 3 else 1
+    cplx = 16 * sig * n_fft
+    series = 8 * channels * n
+    spec = 24 * sig * n_fft                                   # data spectrum + weights
+    fwd = series + cplx + 2 * cplx * (passes - 1) + spec
+    if passes == 1:
+        fwd = series + spec
+    if not grad:
+        return fwd - (cplx if passes > 1 else 0)              # last pass writes nothing
+    if passes == 1:
+        return fwd + series
+    return fwd + 2 * cplx * (passes - 2) + cplx + series
+
+
+def fd_io_bytes(n, n_fft, channels=3, grad=True):
+    sig = 2 if channels == 3 else 1
+    return 8 * channels * n * (2 if grad else 1) + 24 * sig * n_fft

@@ -389,3 +389,88 @@ class Batch:
         """View of template k's [rows][n_out] output block."""
         _, _, _, n_out, off = self.templates[k]
         return out[off:off + self.rows * n_out].view(self.rows, n_out)
+
+
+# ---------------------------------------------------------------------------
+# Frequency-domain likelihood (lr_fd_*)
+# ---------------------------------------------------------------------------
+
+class lr_fd_plan(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_fft", ctypes.c_int64), ("max_batch", ctypes.c_int64),
+                ("channels", ctypes.c_int), ("log2n", ctypes.c_int), ("passes", ctypes.c_int),
+                ("q", ctypes.c_int * 3), ("dt", ctypes.c_double), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t), ("off", ctypes.c_size_t * 6)]
+
+
+def _fd_lib():
+    L = lib()
+    if getattr(L, "_fd_ready", False):
+        return L
+    d, i32, i64, vp = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    pp = ctypes.POINTER(lr_fd_plan)
+    L.lr_fd_length.restype = i64
+    L.lr_fd_length.argtypes = [i64]
+    L.lr_fd_workspace.restype = ctypes.c_size_t
+    L.lr_fd_workspace.argtypes = [i64, i32, i64]
+    L.lr_fd_prepare.restype = i32
+    L.lr_fd_prepare.argtypes = [i64, i32, d, vp, i64, vp, vp, i64, vp, ctypes.c_size_t, pp, vp]
+    L.lr_fd_loglike.restype = i32
+    L.lr_fd_loglike.argtypes = [pp, i64, vp, i64, i64, vp, vp, vp]
+    L._fd_ready = True
+    return L
+
+
+def fd_length(n):
+    """Transform length lr_fd_length(n) (power of two >= max(n, 4096))."""
+    m = _fd_lib().lr_fd_length(int(n))
+    if m < 0:
+        raise ValueError("no transform length for n = %d" % n)
+    return int(m)
+
+
+class FdPlan:
+    """Frequency-domain likelihood plan (lr_fd_prepare) and its workspace.
+
+    ``data``: [C][n] device series (C = 2: A, E; C = 3: A, E, T); ``w_ae``,
+    ``w_t``: device bin weights [fd_length(n) // 2 + 1] (w_t unused for C =
+    2); ``max_batch``: templates per launch sequence (sets the workspace)."""
+
+    def __init__(self, data, w_ae, w_t, dt, max_batch=1, stream=None):
+        import torch
+        if data.dim() != 2:
+            raise ValueError("data must be [channels][n]")
+        C, n = data.shape
+        L = _fd_lib()
+        nbytes = L.lr_fd_workspace(n, C, max_batch)
+        if nbytes == 0:
+            raise ValueError("invalid plan arguments (n=%d, channels=%d, max_batch=%d)"
+                             % (n, C, max_batch))
+        self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=data.device)
+        self.c = lr_fd_plan()
+        _check(L.lr_fd_prepare(n, C, float(dt), _dev(data, "data"), data.stride(0),
+                               _dev(w_ae, "w_ae"), _opt(w_t if C == 3 else None, "w_t"),
+                               int(max_batch), _dev(self.ws, "ws"), nbytes, ctypes.byref(self.c),
+                               _stream(stream)), "lr_fd_prepare")
+        self.n, self.channels, self.dt = n, C, float(dt)
+        self.n_fft, self.passes = int(self.c.n_fft), int(self.c.passes)
+        self.max_batch = int(max_batch)
+
+    def loglike(self, h, want_grad=True, stats=None, g_h=None, stream=None):
+        """(stats [B][3] = rr, hh, dh; g_h = d logL/dh or None) for h of shape
+        [B][C][n] (or [C][n], then B = 1)."""
+        import torch
+        hb = h.unsqueeze(0) if h.dim() == 2 else h
+        if hb.shape[1:] != (self.channels, self.n):
+            raise ValueError("h must be [B][%d][%d]" % (self.channels, self.n))
+        B = hb.shape[0]
+        if stats is None:
+            stats = torch.empty((B, 3), dtype=torch.float64, device=h.device)
+        if want_grad and g_h is None:
+            g_h = torch.empty_like(hb)
+        _check(_fd_lib().lr_fd_loglike(ctypes.byref(self.c), B, _dev(hb, "h"), hb.stride(0),
+                                       hb.stride(1), _dev(stats, "stats"),
+                                       _opt(g_h if want_grad else None, "g_h"), _stream(stream)),
+               "lr_fd_loglike")
+        if want_grad and h.dim() == 2:
+            g_h = g_h[0]
+        return stats, (g_h if want_grad else None)

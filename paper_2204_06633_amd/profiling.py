@@ -5,6 +5,7 @@
     python -m paper_2204_06633_amd.profiling --what copy --copy-mib 1024
     python -m paper_2204_06633_amd.profiling --what batch --templates 64
     python -m paper_2204_06633_amd.profiling --what batch-adjoint --templates 32
+    python -m paper_2204_06633_amd.profiling --what fd --templates 4
 
 ``forward`` runs the per-template forward (projection + TDI-2 XYZ+AET) on the
 1-yr, dt = 10 s, order-25 Keplerian workload; ``adjoint`` adds the adjoint
@@ -12,8 +13,10 @@ pair; ``copy`` runs one device-to-device copy of known size (the reference
 for scaling the HBM byte counters); ``batch`` runs the fused batched forward
 on the first ``--templates`` templates of the 512-template uneven batch
 (group 2); ``batch-adjoint`` runs forward, likelihood and adjoint of that
-many 1-yr, dt = 15 s walkers with hybrid orbits.  Each step prints a line so
-a profiler run shows progress.
+many 1-yr, dt = 15 s walkers with hybrid orbits; ``fd`` runs the
+frequency-domain likelihood with its gradient on ``--templates`` one-year
+A/E/T series at dt = 10 s (2^22-point transforms).  Each step prints a line
+so a profiler run shows progress.
 """
 from __future__ import annotations
 
@@ -23,7 +26,7 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["forward", "adjoint", "copy", "batch", "batch-adjoint"],
+    ap.add_argument("--what", choices=["forward", "adjoint", "copy", "batch", "batch-adjoint", "fd"],
                     default="forward")
     ap.add_argument("--templates", type=int, default=64)
     ap.add_argument("--group", type=int, default=2)
@@ -47,6 +50,8 @@ def main(argv=None):
     from . import native, response, workloads
     if args.what in ("batch", "batch-adjoint"):
         return run_batch(args, dev)
+    if args.what == "fd":
+        return run_fd(args, dev)
     case = workloads.config_c2("XYZAET")
     g = case.grid
     orb = native.Orbits.from_samples(case.orbits_proj, device=dev)
@@ -94,6 +99,23 @@ def run_batch(args, dev):
         torch.cuda.synchronize()
         print("%s step %d done (%d templates, %d samples)" % (args.what, r, len(bc.grids),
                                                             bc.n_samples), flush=True)
+
+
+def run_fd(args, dev):
+    import torch
+
+    from . import native, workloads
+    fc = workloads.fd_case(args.templates)
+    w_ae, w_t = fc.weights(native.fd_length(fc.n), dev)
+    plan = native.FdPlan(fc.data(dev), w_ae, w_t, fc.dt, max_batch=args.templates)
+    h = fc.templates(dev)
+    stats = torch.empty((args.templates, 3), dtype=torch.float64, device=dev)
+    g = torch.empty_like(h)
+    for r in range(args.reps):
+        plan.loglike(h, stats=stats, g_h=g)
+        torch.cuda.synchronize()
+        print("fd step %d done (%d templates, %d-point transforms)" % (r, args.templates,
+                                                                       plan.n_fft), flush=True)
 
 
 if __name__ == "__main__":

@@ -2,7 +2,8 @@
 
 Thin glue over the C-ABI calls: lr_project_links then lr_tdi_combine forward,
 lr_tdi_adjoint then lr_project_adjoint backward, lr_loglike for the
-white-noise likelihood.  All arithmetic runs in the HIP kernels.  The index
+white-noise likelihood and lr_fd_loglike for the noise-weighted
+frequency-domain one.  All arithmetic runs in the HIP kernels.  The index
 bookkeeping follows ``inputs.TemplateGrid``: h on [0, n_h), links on
 [y_start, y_start + n_y), output on [out_start, out_start + n_out) of the same
 uniform grid.
@@ -91,3 +92,29 @@ def response(tpl: Template, hp, hc, sky):
 
 def loglike(h, data, sigma):
     return LoglikeFn.apply(h, data, sigma)
+
+
+class FdLoglikeFn(torch.autograd.Function):
+    """log L = -<d - h|d - h>/2 of the frequency-domain likelihood
+    (lr_fd_loglike) for h [C][n] or [B][C][n]; backward returns
+    g_ll * d log L / d h from the same call."""
+
+    @staticmethod
+    def forward(ctx, h, plan):
+        h = h.contiguous()
+        want = ctx.needs_input_grad[0]
+        stats, g = plan.loglike(h, want_grad=want)
+        ctx.save_for_backward(g if want else torch.empty(0, device=h.device))
+        ll = -0.5 * stats[:, 0]
+        return ll[0] if h.dim() == 2 else ll
+
+    @staticmethod
+    def backward(ctx, g_ll):
+        (g,) = ctx.saved_tensors
+        if g.dim() == 3:
+            return g * g_ll.view(-1, 1, 1), None
+        return g * g_ll, None
+
+
+def fd_loglike(h, plan):
+    return FdLoglikeFn.apply(h, plan)

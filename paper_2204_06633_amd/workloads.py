@@ -203,3 +203,40 @@ def device_polarizations(bc: BatchCase, device, params=None):
         hp[ho:ho + g.n_h] = a
         hc[ho:ho + g.n_h] = b
     return hp, hc
+
+
+@dataclasses.dataclass
+class FdCase:
+    """Inputs of the frequency-domain likelihood: seeded A/E/T series of n
+    samples at dt standing for the data and for n_templates templates, and
+    the stand-in noise curve's bin weights."""
+    name: str
+    n: int
+    dt: float
+    n_templates: int
+    seed: int
+    f_min: float = 1e-4
+    f_max: float = 2.5e-2
+
+    def data(self, device):
+        import torch
+        g = torch.Generator(device=device).manual_seed(self.seed)
+        return torch.randn((3, self.n), dtype=torch.float64, device=device, generator=g)
+
+    def templates(self, device):
+        import torch
+        g = torch.Generator(device=device).manual_seed(self.seed + 1)
+        return torch.randn((self.n_templates, 3, self.n), dtype=torch.float64, device=device,
+                           generator=g)
+
+    def weights(self, n_fft, device):
+        import torch
+        w_ae, w_t = inputs.noise_weights(n_fft, self.dt, self.f_min, self.f_max)
+        return (torch.tensor(w_ae, dtype=torch.float64, device=device),
+                torch.tensor(w_t, dtype=torch.float64, device=device))
+
+
+def fd_case(n_templates=1, seed=11):
+    """One year of A/E/T at dt = 10 s (3,155,760 samples) per template."""
+    n = int(round(inputs.YEAR / 10.0))
+    return FdCase("fd_1yr_dt10_aet", n, 10.0, n_templates, seed)

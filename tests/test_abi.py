@@ -150,7 +150,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     compiler lays them out."""
     import subprocess
     structs = {"lr_orbits": native.lr_orbits, "lr_template": native.lr_template,
-               "lr_batch": native.lr_batch}
+               "lr_batch": native.lr_batch, "lr_fd_plan": native.lr_fd_plan}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lisaresp.h"',
              'int main(void) {']
     for name, cls in structs.items():
@@ -216,3 +216,45 @@ def test_batch_workspace_and_rejections():
     assert L.lr_batch_prepare(arr, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
                               1, 2, 0, ctypes.c_void_p(0x1000), 64, ctypes.byref(b),
                               None) == native.LR_E_WORKSPACE
+
+
+def test_fd_lengths_workspace_and_rejections():
+    L = native._fd_lib()
+    assert L.lr_fd_length(0) == -1 and L.lr_fd_length(1 + (1 << 24)) == -1
+    assert L.lr_fd_length(1) == 4096 and L.lr_fd_length(4096) == 4096
+    assert L.lr_fd_length(4097) == 8192 and L.lr_fd_length(3155760) == 1 << 22
+    assert L.lr_fd_length(1 << 24) == 1 << 24
+    assert L.lr_fd_workspace(3155760, 4, 1) == 0 and L.lr_fd_workspace(100, 3, 0) == 0
+    w2, w3 = L.lr_fd_workspace(3155760, 2, 1), L.lr_fd_workspace(3155760, 3, 1)
+    N = 1 << 22
+    # data spectrum, weights, work and partials: at least 48 + 16 signals bytes per point
+    assert w2 >= N * (48 + 16) and w3 >= N * (48 + 32) and w3 > w2
+    assert L.lr_fd_workspace(3155760, 3, 4) - w3 >= 3 * 2 * N * 16
+    plan = native.lr_fd_plan()
+    a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    ws = ctypes.c_void_p(0x10000000)
+    wsb = L.lr_fd_workspace(5000, 3, 1)
+    # bad channel count, dt, stride, null w_t with T, n too large, small workspace
+    assert L.lr_fd_prepare(5000, 4, 10.0, a, 5000, b, c, 1, ws, wsb, ctypes.byref(plan), None) == 1
+    assert L.lr_fd_prepare(5000, 3, 0.0, a, 5000, b, c, 1, ws, wsb, ctypes.byref(plan), None) == 1
+    assert L.lr_fd_prepare(5000, 3, 10.0, a, 4000, b, c, 1, ws, wsb, ctypes.byref(plan), None) == 1
+    assert L.lr_fd_prepare(5000, 3, 10.0, a, 5000, b, None, 1, ws, wsb, ctypes.byref(plan),
+                           None) == 1
+    assert L.lr_fd_prepare((1 << 24) + 1, 3, 10.0, a, 1 << 25, b, c, 1, ws, 1 << 40,
+                           ctypes.byref(plan), None) == 3
+    assert L.lr_fd_prepare(5000, 3, 10.0, a, 5000, b, c, 1, ws, wsb - 8, ctypes.byref(plan),
+                           None) == 4
+    # data inside the workspace
+    assert L.lr_fd_prepare(5000, 3, 10.0, ctypes.c_void_p(0x10000100), 5000, b, c, 1, ws, wsb,
+                           ctypes.byref(plan), None) == 1
+    # an unprepared plan is rejected, and so are bad strides and aliasing
+    assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 5000, b, c, None) == 1
+    plan.n, plan.n_fft, plan.log2n, plan.passes, plan.channels = 5000, 8192, 13, 2, 3
+    plan.max_batch, plan.ws, plan.ws_bytes = 1, 0x10000000, wsb
+    assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 4999, b, c, None) == 1
+    assert L.lr_fd_loglike(ctypes.byref(plan), 2, a, 14999, 5000, b, c, None) == 1
+    assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 5000, b, a, None) == 1
+    assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 5000, None, c, None) == 1
+    assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 5000, ctypes.c_void_p(0x10000000),
+                           c, None) == 1
+    assert L.lr_fd_loglike(ctypes.byref(plan), 0, None, 0, 0, None, None, None) == 0

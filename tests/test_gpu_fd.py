@@ -1,0 +1,219 @@
+"""GPU frequency-domain likelihood (lr_fd_loglike) against the CPU oracle.
+
+Bars (derived from FFT rounding: a radix-2^k FP64 transform of N points has
+errors of order 1e-16 log2 N relative to the weighted norms, so about 1e-14
+here; the bars leave three orders of margin):
+  rr = <d-h|d-h> and hh = <h|h>: relative 1e-11;
+  dh = <d|h>: 1e-11 sqrt(dd hh) (Cauchy-Schwarz scale; dh itself may cancel);
+  d logL / dh: 1e-11 of max |g| per element.
+Sizes cover one, two and three passes (4096, 8192 and 2^17 points), ragged
+tails, batches processed in several chunks, the one-year series (2^22) and
+the largest transform (2^24).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fd as ofd
+from paper_2204_06633_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _t(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _setup(torch, n, C, B, seed, dt=10.0, max_batch=None, band=(1e-4, 2.5e-2)):
+    from paper_2204_06633_amd import native
+    rng = np.random.default_rng(seed)
+    N = native.fd_length(n)
+    w_ae, w_t = inputs.noise_weights(N, dt, f_min=band[0], f_max=band[1])
+    d = rng.standard_normal((C, n))
+    h = rng.standard_normal((B, C, n))
+    plan = native.FdPlan(_t(torch, d), _t(torch, w_ae), _t(torch, w_t), dt,
+                         max_batch=max_batch or B)
+    return plan, N, d, h, w_ae, w_t, dt
+
+
+def _check_stats(st, ref, dd):
+    assert abs(st[0] - ref["rr"]) <= TOL * ref["rr"], (st[0], ref["rr"])
+    assert abs(st[1] - ref["hh"]) <= TOL * ref["hh"], (st[1], ref["hh"])
+    assert abs(st[2] - ref["dh"]) <= TOL * math.sqrt(dd * ref["hh"]), (st[2], ref["dh"])
+
+
+def _check_grad(g, ref):
+    err = np.max(np.abs(g - ref))
+    assert err <= TOL * np.max(np.abs(ref)), err / np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,C,B,max_batch", [(3000, 3, 2, 2), (4096, 2, 1, 1), (4097, 3, 1, 1),
+                                             (5000, 3, 3, 2), (5000, 2, 2, 2),
+                                             (70001, 3, 2, 1), (1, 3, 1, 1)])
+def test_stats_and_gradient_match_oracle(torch_cuda, n, C, B, max_batch):
+    torch = torch_cuda
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, n, C, B, seed=n + C, max_batch=max_batch)
+    if n == 1:
+        w_ae[:] = 1.0                      # a one-sample series has power at every bin
+        w_t[:] = 2.0
+        from paper_2204_06633_amd import native
+        plan = native.FdPlan(_t(torch, d), _t(torch, w_ae), _t(torch, w_t), dt, max_batch=1)
+    stats, g = plan.loglike(_t(torch, h))
+    torch.cuda.synchronize()
+    stats, g = stats.cpu().numpy(), g.cpu().numpy()
+    dd = ofd.loglike(np.zeros_like(d), d, w_ae, w_t, dt, N)["rr"]
+    print("n=%d C=%d B=%d N=%d passes=%d" % (n, C, B, N, plan.passes), flush=True)
+    for b in range(B):
+        _check_stats(stats[b], ofd.loglike(h[b], d, w_ae, w_t, dt, N), dd)
+        _check_grad(g[b], ofd.loglike_grad(h[b], d, w_ae, w_t, dt, N))
+
+
+def test_statistics_only_call_matches(torch_cuda):
+    torch = torch_cuda
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, 20000, 3, 2, seed=5)
+    hh = _t(torch, h)
+    s1, _ = plan.loglike(hh, want_grad=False)
+    s2, _ = plan.loglike(hh, want_grad=True)
+    torch.cuda.synchronize()
+    assert torch.allclose(s1, s2, rtol=1e-13, atol=0)   # same transform, same sums
+
+
+def test_template_equal_to_data_and_zero_weights(torch_cuda):
+    torch = torch_cuda
+    from paper_2204_06633_amd import native
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, 9000, 3, 1, seed=6)
+    stats, g = plan.loglike(_t(torch, d))
+    torch.cuda.synchronize()
+    # template = data: the residual vanishes (to rounding; the data spectrum
+    # and the template's come from the same transform code)
+    hh = stats[0, 1].item()
+    assert hh > 0 and 0.0 <= stats[0, 0].item() <= 1e-20 * hh
+    assert abs(stats[0, 2].item() - hh) <= 1e-13 * hh
+    g_scale = np.max(np.abs(ofd.loglike_grad(h[0], d, w_ae, w_t, dt, N)))
+    assert torch.max(torch.abs(g)).item() <= 1e-12 * g_scale
+    z = torch.zeros(N // 2 + 1, dtype=torch.float64, device="cuda")
+    plan0 = native.FdPlan(_t(torch, d), z, z, dt)
+    stats, g = plan0.loglike(_t(torch, h[0]))
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(stats).item() == 0 and torch.count_nonzero(g).item() == 0
+
+
+def test_deterministic_and_graph_replay(torch_cuda):
+    torch = torch_cuda
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, 40000, 3, 3, seed=7, max_batch=2)
+    hh = _t(torch, h)
+    s_ref, g_ref = plan.loglike(hh)
+    s_ref, g_ref = s_ref.clone(), g_ref.clone()
+    stats = torch.empty_like(s_ref)
+    g = torch.empty_like(g_ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.loglike(hh, stats=stats, g_h=g, stream=s)    # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.loglike(hh, stats=stats, g_h=g)
+    for rep in range(3):
+        stats.fill_(-1.0)
+        g.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(stats, s_ref) and torch.equal(g, g_ref), rep
+        plan.loglike(hh[:1])                             # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_autograd_function(torch_cuda):
+    torch = torch_cuda
+    from paper_2204_06633_amd import response
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, 12000, 3, 2, seed=8)
+    hh = _t(torch, h).requires_grad_(True)
+    ll = response.fd_loglike(hh, plan)
+    (ll * torch.tensor([1.0, -2.0], dtype=torch.float64, device="cuda")).sum().backward()
+    g = hh.grad.cpu().numpy()
+    for b, scale in ((0, 1.0), (1, -2.0)):
+        ref = ofd.loglike(h[b], d, w_ae, w_t, dt, N)["loglike"]
+        assert abs(ll[b].item() - ref) <= TOL * abs(ref)
+        _check_grad(g[b], scale * ofd.loglike_grad(h[b], d, w_ae, w_t, dt, N))
+
+
+def test_response_chain_sky_gradient(torch_cuda):
+    """d log L / d(h+, hx, lam, beta) through the response and the
+    frequency-domain likelihood against the oracle's chain of transposes."""
+    torch = torch_cuda
+    import oracle
+    from paper_2204_06633_amd import native, response
+    from tests import cases
+    case = cases.make_case("fdchain", "keplerian", 6000, 10.0, 25, 2, "AET", seed=31)
+    g = case.grid
+    orb = native.Orbits.from_samples(case.orbits_proj)
+    tpl = response.Template(orb, orb, g, case.order, case.generation, case.channels)
+    o = oracle.Orbits.from_samples(case.orbits_proj)
+    ref_out = oracle.response(o, o, g, case.hp, case.hc, case.lam, case.beta, case.order,
+                              case.generation, case.channels)
+    rng = np.random.default_rng(3)
+    data = ref_out * (1.0 + 0.1 * rng.standard_normal(ref_out.shape))
+    N = native.fd_length(g.n_out)
+    w_ae, w_t = inputs.noise_weights(N, g.dt)
+    plan = native.FdPlan(_t(torch, data), _t(torch, w_ae), _t(torch, w_t), g.dt)
+    hp = _t(torch, case.hp).requires_grad_(True)
+    hc = _t(torch, case.hc).requires_grad_(True)
+    sky = _t(torch, [case.lam, case.beta]).requires_grad_(True)
+    out = response.response(tpl, hp, hc, sky)
+    ll = response.fd_loglike(out, plan)
+    ll.backward()
+    # the oracle's chain at the GPU's own forward output: the forward error
+    # (~1e-11 of T's norm, R15) is amplified by the large T weights and is
+    # covered by the forward tests; this checks gradient and adjoint
+    g_out = ofd.loglike_grad(out.detach().cpu().numpy(), data, w_ae, w_t, g.dt, N)
+    rhp, rhc = oracle.response_adjoint(o, o, g, case.lam, case.beta, case.order,
+                                       case.generation, g_out, case.channels)
+    err = cases.rel_err(np.stack([hp.grad.cpu().numpy(), hc.grad.cpu().numpy()]),
+                        np.stack([rhp, rhc]))
+    print("chain: d logL/d(h+, hx) rel err %.3e" % err, flush=True)
+    assert err <= 1e-10
+    # sky gradient: central differences of the oracle's log-likelihood
+    def ll_at(lam, beta):
+        out = oracle.response(o, o, g, case.hp, case.hc, lam, beta, case.order, case.generation,
+                              case.channels)
+        return ofd.loglike(out, data, w_ae, w_t, g.dt, N)["loglike"]
+    # steps of 1e-4 rad: Richardson-extrapolated differences converge to
+    # 1e-8 there, while below 1e-5 the rounding of the T channel (amplified
+    # by its large weights) dominates
+    h_step = 1e-4
+    for k, (dl, db) in enumerate(((h_step, 0.0), (0.0, h_step))):
+        fd1 = (ll_at(case.lam + dl, case.beta + db)
+               - ll_at(case.lam - dl, case.beta - db)) / (2 * h_step)
+        fd2 = (ll_at(case.lam + 2 * dl, case.beta + 2 * db)
+               - ll_at(case.lam - 2 * dl, case.beta - 2 * db)) / (4 * h_step)
+        rich = (4 * fd1 - fd2) / 3
+        got = sky.grad[k].item()
+        assert abs(got - rich) <= 1e-6 * max(abs(rich), 1e-30), (k, got, rich)
+
+
+@pytest.mark.parametrize("n,C,B", [(3155760, 3, 2), (1 << 24, 2, 1)])
+def test_full_size(torch_cuda, n, C, B):
+    """The one-year series at dt = 10 s (2^22 points, two templates in two
+    chunks) and the largest transform (2^24 points)."""
+    torch = torch_cuda
+    plan, N, d, h, w_ae, w_t, dt = _setup(torch, n, C, B, seed=9, max_batch=1)
+    stats, g = plan.loglike(_t(torch, h))
+    torch.cuda.synchronize()
+    print("n=%d N=%d passes=%d" % (n, N, plan.passes), flush=True)
+    stats, g = stats.cpu().numpy(), g.cpu().numpy()
+    dd = ofd.loglike(np.zeros_like(d), d, w_ae, w_t, dt, N)["rr"]
+    for b in range(B):
+        _check_stats(stats[b], ofd.loglike(h[b], d, w_ae, w_t, dt, N), dd)
+        _check_grad(g[b], ofd.loglike_grad(h[b], d, w_ae, w_t, dt, N))
