@@ -27,7 +27,6 @@ namespace fd {
 constexpr int kThreads = 256;
 constexpr int kTile = 4096;                 // complex points per workgroup
 constexpr int kPer = kTile / kThreads;      // points per thread
-constexpr int kMaxLines = 128;              // lines per tile at R = 32
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
@@ -91,29 +90,116 @@ __device__ __forceinline__ void dft(double2 (&v)[RHO]) {
   }
 }
 
-// One Stockham stage of radix 2^LR over all C lines of the tile (line c at
-// lds + c * ls, R = 2^q points, sub-transforms of 2^ns_log points done).
-template <int LR, bool INV>
-__device__ __forceinline__ void stage(double2* lds, int q, int ls, int ns_log, int logN,
-                                      const double2* tlo, const double2* thi) {
-  constexpr int RHO = 1 << LR;
-  constexpr int BPT = kPer / RHO;
-  const int tid = threadIdx.x;
-  const int pl_log = q - LR;                 // butterflies per line = R / RHO
-  const int pl_mask = (1 << pl_log) - 1;
-  const int ns_mask = (1 << ns_log) - 1;
+// Stages of a line of 2^Q points: ceil(Q / 4) radix-2^b stages, larger
+// radices first (Q = 5: 8, 4; 6: 8, 8; 7: 16, 8; 8: 16, 16; 12: 16, 16, 16).
+constexpr int num_stages(int q) { return (q + 3) >> 2; }
+constexpr int stage_bits(int q, int s) {
+  int nst = num_stages(q), rem = q;
+  for (int i = 0; i < s; ++i) rem -= (rem + (nst - i) - 1) / (nst - i);
+  return (rem + (nst - s) - 1) / (nst - s);
+}
+
+// LDS layout: line c at c * line_stride, element x at x + x / 16 (one pad
+// per 16 elements, and an odd line stride in 16-byte units), so that the
+// strided stage writes and the column-wise accesses hit distinct banks.
+constexpr int line_stride(int q) { return (1 << q) + (1 << q) / 16 + 1; }
+__device__ __forceinline__ int lpad(int x) { return x + (x >> 4); }
+
+// Where a tile's elements live: element (line c, index r) of the tile is at
+// base + c * cstep + r * rstep of its signal; b0 + c is the inner index b of
+// a column line (column mode: C adjacent columns of the [A][R][B] view;
+// row mode, B = 1: C consecutive rows).
+struct Tile {
+  bool col;
+  int logA;
+  int64_t base, b0, cstep, rstep;
+};
+
+// Butterfly u of this thread in a radix-2^LR stage: line c and index j.
+// Column mode puts consecutive lines on consecutive lanes (global accesses
+// are runs of C elements), row mode consecutive j (runs of R / 2^LR).
+template <int Q, int LR>
+__device__ __forceinline__ void coords(bool col, int u, int& c, int& j) {
+  constexpr int logC = 12 - Q, PL = Q - LR;
+  const int beta = (int)threadIdx.x + kThreads * u;
+  if (col) {
+    c = beta & ((1 << logC) - 1);
+    j = beta >> logC;
+  } else {
+    j = beta & ((1 << PL) - 1);
+    c = beta >> PL;
+  }
+}
+
+template <bool IN_REAL>
+__device__ __forceinline__ double2 load_elem(const PassArgs& a, const double2* x, int64_t pos,
+                                             int64_t tpl, int kind) {
+  if (!IN_REAL) return x[pos];
+  double2 v = make_double2(0.0, 0.0);
+  if (pos < a.n) {
+    const double* h = a.h + tpl * a.t_stride + pos;
+    if (kind == 0) v = make_double2(h[0], h[a.c_stride]);
+    else v.x = h[2 * a.c_stride];
+  }
+  return v;
+}
+
+// First stage (sub-transforms of one point, no twiddle) straight from
+// global memory, output to LDS.  PRETW: the transpose of the forward
+// inter-pass twiddle, applied before an inverse line transform.
+template <int Q, int LR, bool IN_REAL, bool INV>
+__device__ __forceinline__ void first_stage(const PassArgs& a, const Tile& T, const double2* x,
+                                            int64_t tpl, int kind, bool pretw, double2* lds) {
+  constexpr int RHO = 1 << LR, BPT = kPer / RHO, PL = Q - LR, LS = line_stride(Q);
   double2 v[BPT][RHO];
-  int dst[BPT];
+  int cc[BPT], jj[BPT];
 #pragma unroll
   for (int u = 0; u < BPT; ++u) {
-    const int beta = tid + kThreads * u;
-    const int c = beta >> pl_log, j = beta & pl_mask;
-    const double2* src = lds + c * ls + j;
+    coords<Q, LR>(T.col, u, cc[u], jj[u]);
 #pragma unroll
-    for (int k = 0; k < RHO; ++k) v[u][k] = src[k << pl_log];
+    for (int k = 0; k < RHO; ++k) {
+      const int r = jj[u] + (k << PL);
+      v[u][k] = load_elem<IN_REAL>(a, x, T.base + cc[u] * T.cstep + r * T.rstep, tpl, kind);
+    }
+  }
+  if (pretw) {
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+#pragma unroll
+      for (int k = 0; k < RHO; ++k) {
+        const int r = jj[u] + (k << PL);
+        double2 w = twiddle(a.tlo, a.thi, (int)(((int64_t)r * (T.b0 + cc[u])) << T.logA));
+        w.y = -w.y;
+        v[u][k] = cmul(v[u][k], w);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    dft<RHO, INV>(v[u]);
+#pragma unroll
+    for (int k = 0; k < RHO; ++k)
+      lds[cc[u] * LS + lpad((jj[u] << LR) + k)] = v[u][bit_reverse(k, LR)];
+  }
+}
+
+// A middle Stockham stage, LDS to LDS (sub-transforms of 2^ns_log points
+// done); lanes take consecutive butterflies of a line.
+template <int Q, int LR, bool INV>
+__device__ __forceinline__ void mid_stage(double2* lds, int ns_log, int logN, const double2* tlo,
+                                          const double2* thi) {
+  constexpr int RHO = 1 << LR, BPT = kPer / RHO, PL = Q - LR, LS = line_stride(Q);
+  const int ns_mask = (1 << ns_log) - 1;
+  double2 v[BPT][RHO];
+  int cd[BPT], xd[BPT];
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int c, j;
+    coords<Q, LR>(false, u, c, j);
+#pragma unroll
+    for (int k = 0; k < RHO; ++k) v[u][k] = lds[c * LS + lpad(j + (k << PL))];
     const int m = j & ns_mask;
     if (m != 0) {
-      // exp(-2 pi i m k / (Ns RHO)), k = 1 .. RHO-1, by successive powers
       double2 w = twiddle(tlo, thi, m << (logN - ns_log - LR));
       if (INV) w.y = -w.y;
       double2 wk = w;
@@ -124,32 +210,192 @@ __device__ __forceinline__ void stage(double2* lds, int q, int ls, int ns_log, i
       }
     }
     dft<RHO, INV>(v[u]);
-    dst[u] = c * ls + (((j >> ns_log) << (ns_log + LR)) | m);
+    cd[u] = c * LS;
+    xd[u] = ((j >> ns_log) << (ns_log + LR)) | m;
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < BPT; ++u) {
 #pragma unroll
-    for (int k = 0; k < RHO; ++k) lds[dst[u] + (k << ns_log)] = v[u][bit_reverse(k, LR)];
+    for (int k = 0; k < RHO; ++k) lds[cd[u] + lpad(xd[u] + (k << ns_log))] = v[u][bit_reverse(k, LR)];
   }
   __syncthreads();
 }
 
-// DFT of every line of the tile (natural order in and out), R = 2^q with
-// 5 <= q <= 12: ceil(q / 4) stages, larger radices first.
-template <bool INV>
-__device__ __forceinline__ void line_fft(double2* lds, int q, int ls, int logN,
-                                         const double2* tlo, const double2* thi) {
-  const int nst = (q + 3) >> 2;
-  int ns_log = 0, rem = q;
-  for (int s = 0; s < nst; ++s) {
-    const int bits = (rem + (nst - s) - 1) / (nst - s);   // ceil(rem / stages left)
-    if (bits == 4) stage<4, INV>(lds, q, ls, ns_log, logN, tlo, thi);
-    else if (bits == 3) stage<3, INV>(lds, q, ls, ns_log, logN, tlo, thi);
-    else stage<2, INV>(lds, q, ls, ns_log, logN, tlo, thi);
-    ns_log += bits;
-    rem -= bits;
+// Last stage, LDS to registers: sub-transforms of R / 2^LR points done, so
+// butterfly j's twiddles are exp(-+2 pi i j k / R) and its outputs are the
+// line's elements j + k R / 2^LR in natural order: o[u * RHO + k].
+template <int Q, int LR, bool INV>
+__device__ __forceinline__ void last_stage(bool col, const double2* lds, int logN,
+                                           const double2* tlo, const double2* thi,
+                                           double2 (&o)[kPer]) {
+  constexpr int RHO = 1 << LR, BPT = kPer / RHO, PL = Q - LR, LS = line_stride(Q);
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int c, j;
+    coords<Q, LR>(col, u, c, j);
+    double2 v[RHO];
+#pragma unroll
+    for (int k = 0; k < RHO; ++k) v[k] = lds[c * LS + lpad(j + (k << PL))];
+    if (j != 0) {
+      double2 w = twiddle(tlo, thi, j << (logN - Q));
+      if (INV) w.y = -w.y;
+      double2 wk = w;
+#pragma unroll
+      for (int k = 1; k < RHO; ++k) {
+        v[k] = cmul(v[k], wk);
+        if (k + 1 < RHO) wk = cmul(wk, w);
+      }
+    }
+    dft<RHO, INV>(v);
+#pragma unroll
+    for (int k = 0; k < RHO; ++k) o[u * RHO + k] = v[bit_reverse(k, LR)];
   }
+}
+
+// Store the last stage's outputs (POSTTW: the forward inter-pass twiddle).
+template <int Q, int LR, bool OUT_REAL>
+__device__ __forceinline__ void store_out(const PassArgs& a, const Tile& T, double2* x,
+                                          int64_t tpl, int kind, bool posttw,
+                                          const double2 (&o)[kPer]) {
+  constexpr int RHO = 1 << LR, BPT = kPer / RHO, PL = Q - LR;
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int c, j;
+    coords<Q, LR>(T.col, u, c, j);
+#pragma unroll
+    for (int k = 0; k < RHO; ++k) {
+      const int r = j + (k << PL);
+      const int64_t pos = T.base + c * T.cstep + r * T.rstep;
+      double2 val = o[u * RHO + k];
+      if (posttw) val = cmul(val, twiddle(a.tlo, a.thi, (int)(((int64_t)r * (T.b0 + c)) << T.logA)));
+      if (OUT_REAL) {
+        if (pos < a.n) {
+          double* g = a.g + tpl * a.t_stride + pos;
+          if (kind == 0) { g[0] = val.x; g[a.c_stride] = val.y; }
+          else g[2 * a.c_stride] = val.x;
+        }
+      } else {
+        x[pos] = val;
+      }
+    }
+  }
+}
+
+// One pass over lines of 2^Q points.  IN_REAL: the signals are read from
+// the channel series (first forward pass); OUT_REAL: written to channel
+// series (last inverse pass); SPEC: 0 a plain pass in direction INV; 1 the
+// forward line transform and the weighted sums; 2 also the weighted
+// residual and its inverse line transform (stage order reversed, so that
+// its first stage runs on the registers the forward transform ended with).
+template <int Q, bool IN_REAL, bool OUT_REAL, int SPEC, bool INV>
+__global__ __launch_bounds__(kThreads) void fft_pass_kernel(PassArgs a) {
+  constexpr int NST = num_stages(Q);
+  constexpr int LS = line_stride(Q);
+  constexpr int logC = 12 - Q;
+  constexpr int R = 1 << Q;
+  constexpr bool DIR = INV && SPEC == 0;      // direction of the first line transform
+  constexpr int LR0 = stage_bits(Q, 0), LRL = stage_bits(Q, NST - 1);
+  __shared__ double2 lds[(kTile >> Q) * LS];
+  const int tid = threadIdx.x;
+  const int64_t N = (int64_t)1 << a.logN;
+  const int64_t tau = blockIdx.x;
+  const int64_t sig = tau >> a.tiles_log;
+  const int64_t tp = tau & (((int64_t)1 << a.tiles_log) - 1);
+
+  Tile T;
+  T.col = a.logB > 0;
+  T.logA = a.logN - Q - a.logB;
+  if (T.col) {
+    const int logTa = a.logB - logC;          // tiles per index a
+    const int64_t aa = tp >> logTa;
+    T.b0 = (tp & (((int64_t)1 << logTa) - 1)) << logC;
+    T.base = (aa << (Q + a.logB)) + T.b0;
+    T.cstep = 1;
+    T.rstep = (int64_t)1 << a.logB;
+  } else {
+    T.b0 = 0;
+    T.base = tp << 12;
+    T.cstep = R;
+    T.rstep = 1;
+  }
+  const int64_t tpl = sig / a.sig_per_tpl;
+  const int kind = (int)(sig - tpl * a.sig_per_tpl);   // 0: A + iE, 1: T
+  double2* x = a.x + sig * N;
+
+  first_stage<Q, LR0, IN_REAL, DIR>(a, T, x, tpl, kind, DIR && a.twiddle, lds);
+  __syncthreads();
+  if (NST == 3) mid_stage<Q, stage_bits(Q, 1), DIR>(lds, LR0, a.logN, a.tlo, a.thi);
+  double2 o[kPer];
+  last_stage<Q, LRL, DIR>(T.col, lds, a.logN, a.tlo, a.thi, o);
+  if (SPEC == 0) {
+    store_out<Q, LRL, OUT_REAL>(a, T, x, tpl, kind, !INV && a.twiddle, o);
+    return;
+  }
+
+  // ---- weighted sums over this tile's bins (row mode)
+  constexpr int RHO = 1 << LRL, BPT = kPer / RHO, PL = Q - LRL;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const double2* D = a.dspec + kind * N;
+  const double* W = a.wpos + kind * N;
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int c, j;
+    coords<Q, LRL>(false, u, c, j);
+#pragma unroll
+    for (int k = 0; k < RHO; ++k) {
+      const int64_t pos = T.base + c * R + j + (k << PL);
+      const double2 H = o[u * RHO + k];
+      const double2 Dv = D[pos];
+      const double w = W[pos];
+      const double2 Z = csub(Dv, H);
+      acc[0] = fma(w, fma(Z.x, Z.x, Z.y * Z.y), acc[0]);
+      acc[1] = fma(w, fma(H.x, H.x, H.y * H.y), acc[1]);
+      acc[2] = fma(w, fma(Dv.x, H.x, Dv.y * H.y), acc[2]);
+      if (SPEC == 2) o[u * RHO + k] = make_double2(w * Z.x, w * Z.y);
+    }
+  }
+  // fixed-order tree over the workgroup, in the (now free) LDS
+  double* red = reinterpret_cast<double*>(lds);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) red[i * kThreads + tid] = acc[i];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) red[i * kThreads + tid] += red[i * kThreads + tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* p = a.part + 3 * tau;
+    p[0] = red[0];
+    p[1] = red[kThreads];
+    p[2] = red[2 * kThreads];
+  }
+  if (SPEC == 1) return;
+  __syncthreads();
+
+  // ---- inverse line transform of the weighted residual: stages reversed
+  {
+    constexpr int LS_ = LS;
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      int c, j;
+      coords<Q, LRL>(false, u, c, j);
+      double2 v[RHO];
+#pragma unroll
+      for (int k = 0; k < RHO; ++k) v[k] = o[u * RHO + k];
+      dft<RHO, true>(v);
+#pragma unroll
+      for (int k = 0; k < RHO; ++k) lds[c * LS_ + lpad((j << LRL) + k)] = v[bit_reverse(k, LRL)];
+    }
+  }
+  __syncthreads();
+  if (NST == 3) mid_stage<Q, stage_bits(Q, 1), true>(lds, LRL, a.logN, a.tlo, a.thi);
+  last_stage<Q, LR0, true>(false, lds, a.logN, a.tlo, a.thi, o);
+  store_out<Q, LR0, OUT_REAL>(a, T, x, tpl, kind, false, o);
 }
 
 // Fixed-order sum of three per-thread values over the workgroup.
@@ -167,127 +413,6 @@ __device__ __forceinline__ void block_sum3(double (&v)[3], double (&red)[3][kThr
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) v[j] = red[j][0];
-}
-
-// One pass.  IN_REAL: the signals are read from the channel series (first
-// forward pass); OUT_REAL: written back to channel series (last inverse
-// pass); SPEC: 0 plain pass in direction INV, 1 forward DFT + weighted sums,
-// 2 forward DFT + weighted sums + weighted residual + inverse DFT.
-template <bool IN_REAL, bool OUT_REAL, int SPEC, bool INV>
-__global__ __launch_bounds__(kThreads) void fft_pass_kernel(PassArgs a) {
-  __shared__ double2 lds[kTile + kMaxLines];
-  __shared__ double red[3][kThreads];
-  const int tid = threadIdx.x;
-  const int q = a.q, logC = 12 - q, C = 1 << logC, R = 1 << q;
-  const int ls = R + 1;                       // one pad per line
-  const int64_t N = (int64_t)1 << a.logN;
-  const int64_t tau = blockIdx.x;
-  const int64_t sig = tau >> a.tiles_log;
-  const int64_t tp = tau & (((int64_t)1 << a.tiles_log) - 1);
-  const bool col = a.logB > 0;
-  const int logA = a.logN - q - a.logB;
-
-  int64_t base;        // element (c, r) at base + c * cstep + r * rstep
-  int64_t b0 = 0;
-  int64_t cstep, rstep;
-  if (col) {
-    const int logTa = a.logB - logC;          // tiles per index a
-    const int64_t aa = tp >> logTa;
-    b0 = (tp & (((int64_t)1 << logTa) - 1)) << logC;
-    base = (aa << (q + a.logB)) + b0;
-    cstep = 1;
-    rstep = (int64_t)1 << a.logB;
-  } else {
-    base = tp << 12;
-    cstep = R;
-    rstep = 1;
-  }
-  const int64_t tpl = sig / a.sig_per_tpl;
-  const int kind = (int)(sig - tpl * a.sig_per_tpl);   // 0: A + iE, 1: T
-  double2* x = a.x + sig * N;
-
-  // ---- load (coalesced: C consecutive elements per run)
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int e = tid + kThreads * i;
-    int c, r;
-    if (col) { r = e >> logC; c = e & (C - 1); }
-    else { c = e >> q; r = e & (R - 1); }
-    const int64_t pos = base + c * cstep + r * rstep;
-    double2 val;
-    if (IN_REAL) {
-      val = make_double2(0.0, 0.0);
-      if (pos < a.n) {
-        const double* h = a.h + tpl * a.t_stride + pos;
-        if (kind == 0) val = make_double2(h[0], h[a.c_stride]);
-        else val.x = h[2 * a.c_stride];
-      }
-    } else {
-      val = x[pos];
-    }
-    if (INV && SPEC == 0 && a.twiddle) {
-      // transpose of the forward twiddle, before the inverse DFT
-      double2 w = twiddle(a.tlo, a.thi, (int)((r * (b0 + c)) << logA));
-      w.y = -w.y;
-      val = cmul(val, w);
-    }
-    lds[c * ls + r] = val;
-  }
-  __syncthreads();
-
-  line_fft<INV && SPEC == 0>(lds, q, ls, a.logN, a.tlo, a.thi);
-
-  if (SPEC > 0) {
-    // weighted sums over this tile's bins (row mode: positions tp*4096 + e)
-    double acc[3] = {0.0, 0.0, 0.0};
-    const double2* D = a.dspec + kind * N + base;
-    const double* W = a.wpos + kind * N + base;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int e = tid + kThreads * i;
-      const int c = e >> q, r = e & (R - 1);
-      const double2 H = lds[c * ls + r];
-      const double2 Dv = D[e];
-      const double w = W[e];
-      const double2 Z = csub(Dv, H);
-      acc[0] = fma(w, fma(Z.x, Z.x, Z.y * Z.y), acc[0]);
-      acc[1] = fma(w, fma(H.x, H.x, H.y * H.y), acc[1]);
-      acc[2] = fma(w, fma(Dv.x, H.x, Dv.y * H.y), acc[2]);
-      if (SPEC == 2) lds[c * ls + r] = make_double2(w * Z.x, w * Z.y);
-    }
-    block_sum3(acc, red);
-    if (tid == 0) {
-      double* p = a.part + 3 * tau;
-      p[0] = acc[0];
-      p[1] = acc[1];
-      p[2] = acc[2];
-    }
-    if (SPEC == 1) return;
-    // block_sum3 ends with a barrier: the weighted residual is in LDS
-    line_fft<true>(lds, q, ls, a.logN, a.tlo, a.thi);
-  }
-
-  // ---- store
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int e = tid + kThreads * i;
-    int c, r;
-    if (col) { r = e >> logC; c = e & (C - 1); }
-    else { c = e >> q; r = e & (R - 1); }
-    const int64_t pos = base + c * cstep + r * rstep;
-    double2 val = lds[c * ls + r];
-    if (!INV && SPEC == 0 && a.twiddle)
-      val = cmul(val, twiddle(a.tlo, a.thi, (int)((r * (b0 + c)) << logA)));
-    if (OUT_REAL) {
-      if (pos < a.n) {
-        double* g = a.g + tpl * a.t_stride + pos;
-        if (kind == 0) { g[0] = val.x; g[a.c_stride] = val.y; }
-        else g[2 * a.c_stride] = val.x;
-      }
-    } else {
-      x[pos] = val;
-    }
-  }
 }
 
 // stats[t] = (rr, hh, dh): the partial sums of template t's signals and
@@ -354,11 +479,12 @@ __global__ void weights_kernel(double* wpos, const double* w_ae, const double* w
 
 using fd::PassArgs;
 
-static hipError_t launch_pass(const PassArgs& a, int64_t tiles, bool in_real, bool out_real,
-                              int spec, bool inv, hipStream_t s) {
-  const dim3 grid((unsigned)tiles), block(fd::kThreads);
+template <int Q>
+static void launch_q(const PassArgs& a, dim3 grid, bool in_real, bool out_real, int spec,
+                     bool inv, hipStream_t s) {
+  const dim3 block(fd::kThreads);
 #define LR_FD_LAUNCH(IR, OR, SP, IV) \
-  hipLaunchKernelGGL((fd::fft_pass_kernel<IR, OR, SP, IV>), grid, block, 0, s, a)
+  hipLaunchKernelGGL((fd::fft_pass_kernel<Q, IR, OR, SP, IV>), grid, block, 0, s, a)
   if (spec == 0 && !inv) {
     if (in_real) LR_FD_LAUNCH(true, false, 0, false);
     else LR_FD_LAUNCH(false, false, 0, false);
@@ -373,6 +499,19 @@ static hipError_t launch_pass(const PassArgs& a, int64_t tiles, bool in_real, bo
     else LR_FD_LAUNCH(false, false, 2, false);
   }
 #undef LR_FD_LAUNCH
+}
+
+static hipError_t launch_pass(const PassArgs& a, int64_t tiles, bool in_real, bool out_real,
+                              int spec, bool inv, hipStream_t s) {
+  const dim3 grid((unsigned)tiles);
+  switch (a.q) {
+    case 5: launch_q<5>(a, grid, in_real, out_real, spec, inv, s); break;
+    case 6: launch_q<6>(a, grid, in_real, out_real, spec, inv, s); break;
+    case 7: launch_q<7>(a, grid, in_real, out_real, spec, inv, s); break;
+    case 8: launch_q<8>(a, grid, in_real, out_real, spec, inv, s); break;
+    case 12: launch_q<12>(a, grid, in_real, out_real, spec, inv, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
