@@ -102,7 +102,10 @@ constexpr int stage_bits(int q, int s) {
 // LDS layout: line c at c * line_stride, element x at x + x / 16 (one pad
 // per 16 elements, and an odd line stride in 16-byte units), so that the
 // strided stage writes and the column-wise accesses hit distinct banks.
-constexpr int line_stride(int q) { return (1 << q) + (1 << q) / 16 + 1; }
+#ifndef LR_FD_LS_EXTRA
+#define LR_FD_LS_EXTRA 1
+#endif
+constexpr int line_stride(int q) { return (1 << q) + (1 << q) / 16 + LR_FD_LS_EXTRA; }
 __device__ __forceinline__ int lpad(int x) { return x + (x >> 4); }
 
 // Where a tile's elements live: element (line c, index r) of the tile is at
@@ -165,12 +168,16 @@ __device__ __forceinline__ void first_stage(const PassArgs& a, const Tile& T, co
   if (pretw) {
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
+      // conj(exp(-2 pi i r b / (R B))) for r = j + k R / RHO: w0 * step^k
+      const int64_t b = T.b0 + cc[u];
+      double2 w = twiddle(a.tlo, a.thi, (int)(((int64_t)jj[u] * b) << T.logA));
+      double2 st = twiddle(a.tlo, a.thi, (int)((b << PL) << T.logA));
+      w.y = -w.y;
+      st.y = -st.y;
 #pragma unroll
       for (int k = 0; k < RHO; ++k) {
-        const int r = jj[u] + (k << PL);
-        double2 w = twiddle(a.tlo, a.thi, (int)(((int64_t)r * (T.b0 + cc[u])) << T.logA));
-        w.y = -w.y;
         v[u][k] = cmul(v[u][k], w);
+        if (k + 1 < RHO) w = cmul(w, st);
       }
     }
   }
@@ -263,12 +270,22 @@ __device__ __forceinline__ void store_out(const PassArgs& a, const Tile& T, doub
   for (int u = 0; u < BPT; ++u) {
     int c, j;
     coords<Q, LR>(T.col, u, c, j);
+    // exp(-2 pi i r b / (R B)) for r = j + k R / RHO: w0 * step^k
+    double2 w = make_double2(1.0, 0.0), st = w;
+    if (posttw) {
+      const int64_t b = T.b0 + c;
+      w = twiddle(a.tlo, a.thi, (int)(((int64_t)j * b) << T.logA));
+      st = twiddle(a.tlo, a.thi, (int)((b << PL) << T.logA));
+    }
 #pragma unroll
     for (int k = 0; k < RHO; ++k) {
       const int r = j + (k << PL);
       const int64_t pos = T.base + c * T.cstep + r * T.rstep;
       double2 val = o[u * RHO + k];
-      if (posttw) val = cmul(val, twiddle(a.tlo, a.thi, (int)(((int64_t)r * (T.b0 + c)) << T.logA)));
+      if (posttw) {
+        val = cmul(val, w);
+        if (k + 1 < RHO) w = cmul(w, st);
+      }
       if (OUT_REAL) {
         if (pos < a.n) {
           double* g = a.g + tpl * a.t_stride + pos;
@@ -355,24 +372,29 @@ __global__ __launch_bounds__(kThreads) void fft_pass_kernel(PassArgs a) {
       if (SPEC == 2) o[u * RHO + k] = make_double2(w * Z.x, w * Z.y);
     }
   }
-  // fixed-order tree over the workgroup, in the (now free) LDS
+  // fixed-order sums: a shuffle tree within each wave, then the waves in
+  // order (the now free LDS holds the wave partials)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_down(acc[i], off);
+  }
   double* red = reinterpret_cast<double*>(lds);
   __syncthreads();
+  if ((tid & 63) == 0) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) red[i * kThreads + tid] = acc[i];
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) red[i * kThreads + tid] += red[i * kThreads + tid + w];
-    }
-    __syncthreads();
+    for (int i = 0; i < 3; ++i) red[(tid >> 6) * 3 + i] = acc[i];
   }
+  __syncthreads();
   if (tid == 0) {
     double* p = a.part + 3 * tau;
-    p[0] = red[0];
-    p[1] = red[kThreads];
-    p[2] = red[2 * kThreads];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double t = red[i];
+#pragma unroll
+      for (int w = 1; w < kThreads / 64; ++w) t += red[w * 3 + i];
+      p[i] = t;
+    }
   }
   if (SPEC == 1) return;
   __syncthreads();
