@@ -18,6 +18,9 @@ Beside the headline it reports, in the same line:
   fd_likelihood,       the noise-weighted frequency-domain likelihood of its
   fd_fwd_adjoint       A/E/T (2^22-point transforms) alone, and in the
                        forward + likelihood + adjoint step;
+  orbit_models         the paper's Fig. 3 binary through the accurate, the
+                       fitted equal-armlength and the two hybrid orbit
+                       models, scored by mismatch against the accurate data;
   batched_forward      512 templates of uneven durations (0.25-1 yr at
                        dt = 10 s) in one persistent fused launch, replayed
                        from a HIP graph, autotuned, against the plain
@@ -386,6 +389,44 @@ def main():
     fd_b_stats = costs.fd_bytes(g.n_out, n_fft, 3, plan.passes, False)
     del plan
 
+    # orbit models (Sec. V): the paper's Fig. 3 binary for a year through the
+    # accurate orbits, the fitted equal-armlength ones and the two hybrids,
+    # scored against noise-free data with the frequency-domain statistics
+    from paper_2204_06633_amd import orbitfit
+    log("orbit configurations ESA / EQ / ESAEQ / EQESA")
+    oc = workloads.orbit_config_case(g.n_out, g.dt)
+    oc_orb = {"acc": native.Orbits.from_samples(oc.accurate, device=dev),
+              "eq": native.Orbits.from_samples(oc.equal_arm, device=dev)}
+    oc_cfg = orbitfit.configurations("acc", "eq")
+    oc_names = list(oc_cfg)
+    oc_tpl = [response.Template(oc_orb[oc_cfg[k][0]], oc_orb[oc_cfg[k][1]], oc.grid, oc.order,
+                                oc.generation, "AET") for k in oc_names]
+    oc_hp = torch.tensor(oc.hp, dtype=torch.float64, device=dev)
+    oc_hc = torch.tensor(oc.hc, dtype=torch.float64, device=dev)
+    oc_sky = torch.tensor(oc.params[6:8], dtype=torch.float64, device=dev)
+    oc_h = torch.empty((4, 3, oc.grid.n_out), dtype=torch.float64, device=dev)
+    oc_y = torch.empty((6, oc.grid.n_y), dtype=torch.float64, device=dev)
+    oc_stats = torch.empty((4, 3), dtype=torch.float64, device=dev)
+    for k, tp in enumerate(oc_tpl):
+        response.plain_forward(tp, oc_hp, oc_hc, oc_sky, y=oc_y, out=oc_h[k])
+    oc_plan = native.FdPlan(oc_h[0].clone(), torch.tensor(w_ae, dtype=torch.float64, device=dev),
+                            torch.tensor(w_t, dtype=torch.float64, device=dev), g.dt, max_batch=4)
+
+    def orbit_step():
+        for k, tp in enumerate(oc_tpl):
+            response.plain_forward(tp, oc_hp, oc_hc, oc_sky, y=oc_y, out=oc_h[k])
+        oc_plan.loglike(oc_h, want_grad=False, stats=oc_stats)
+
+    ms_orb = _timed(orbit_step, max(3, args.steps // 4), 1)
+    oc_st = oc_stats.cpu().numpy()
+    oc_diag = orbitfit.overlap_statistics(oc_st, ss=oc_st[0, 1])
+    orbit_result = {"ms_per_step": ms_orb, "eq_fit_lam1_m1": list(oc.eq_params),
+                    "step": "4 templates (orbit models) forward + frequency-domain statistics "
+                            "against the accurate-orbit data, 1 yr",
+                    "mismatch": {k: float(oc_diag["mismatch"][i]) for i, k in enumerate(oc_names)},
+                    "rho_opt": {k: float(oc_diag["rho_opt"][i]) for i, k in enumerate(oc_names)}}
+    del oc_plan, oc_h, oc_y, oc_orb
+
     # the differentiation step: source parameters -> polarisations (torch)
     # -> response -> A/E/T likelihood -> hand-written adjoint -> autograd to
     # the eight parameters (the paper's Fig. 3 binary, data = injection +
@@ -483,6 +524,7 @@ def main():
                            "unit": "samples/s (templates×links×time)", "ms_per_step": ms_fd_fa,
                            "step": "forward, frequency-domain likelihood over A/E/T with "
                                    "gradient, adjoint to h+, hx and (lam, beta)"},
+        "orbit_models": orbit_result,
         "gradient_step": {"value": 6.0 * n / (ms_grad * 1e-3),
                           "unit": "samples/s (templates×links×time)", "ms_per_step": ms_grad,
                           "step": "8 source parameters -> h+, hx (torch) -> response (A/E/T) -> "

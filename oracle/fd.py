@@ -7,7 +7,9 @@ Follows Sec. II.A of arXiv:2204.06633: the inner product of two real time
 series is four times the real part of the integral over positive frequencies
 of conj(a~) b~ / S_n (Eq. for the noise-weighted inner product); the
 log-likelihood is -1/2 <d - h|d - h> summed over the A, E, T channels; the
-optimal SNR is sqrt(<h|h>) and the extraction SNR <d|h> / sqrt(<h|h>).
+optimal SNR is sqrt(<h|h>), the extraction SNR <d|h> / sqrt(<h|h>), and
+with noise-free data s the overlap is <s|h> / sqrt(<h|h><s|s>) and the
+mismatch one minus it.
 
 Discretisation (the paper states the continuous form only):
   * a~(f_k) = dt * sum_{n<N} a_n exp(-2 pi i k n / N), the series zero-padded
@@ -66,6 +68,22 @@ def loglike(h, d, w_ae, w_t, dt, n_fft):
     rho_opt = math.sqrt(hh)
     return {"rr": rr, "hh": hh, "dh": dh, "loglike": -0.5 * rr, "rho_opt": rho_opt,
             "rho_ex": dh / rho_opt if rho_opt > 0 else 0.0}
+
+
+def overlap(h, s, w_ae, w_t, dt, n_fft):
+    """Diagnostics of template h against noise-free data s (Sec. II.A):
+    optimal SNR sqrt(<h|h>), extraction SNR <s|h>/sqrt(<h|h>), overlap
+    <s|h>/sqrt(<h|h><s|s>) and mismatch 1 - overlap, inner products summed
+    over the channels."""
+    h = np.atleast_2d(np.asarray(h, dtype=np.float64))
+    s = np.atleast_2d(np.asarray(s, dtype=np.float64))
+    ws = channel_weights(w_ae, w_t, h.shape[0])
+    hh = math.fsum(inner(h[c], h[c], ws[c], dt, n_fft) for c in range(h.shape[0]))
+    ss = math.fsum(inner(s[c], s[c], ws[c], dt, n_fft) for c in range(h.shape[0]))
+    sh = math.fsum(inner(s[c], h[c], ws[c], dt, n_fft) for c in range(h.shape[0]))
+    ov = sh / math.sqrt(hh * ss)
+    return {"rho_opt": math.sqrt(hh), "rho_ex": sh / math.sqrt(hh), "overlap": ov,
+            "mismatch": 1.0 - ov}
 
 
 def loglike_grad(h, d, w_ae, w_t, dt, n_fft):

@@ -64,14 +64,17 @@ def rigid_orbits(t, L=L_ARM, a=AU, phase=0.0):
     return out
 
 
-def keplerian_orbits(t, L=L_ARM, a=AU, detune=0.01, phase=0.0):
+def keplerian_orbits(t, L=L_ARM, a=AU, detune=0.01, phase=0.0, lam1=0.0):
     """Three heliocentric Keplerian ellipses forming a flexing triangle.
 
     Eccentricity e = L / (2 sqrt(3) a); each orbit is tilted about its own
     rotated y-axis by arctan(sqrt(3) e (1 + detune)).  ``detune`` = 0.01 gives
     an armlength flex of about 1 % over a year (the ideal tilt gives about
-    0.5 %).  Kepler's equation is solved by Newton iteration in FP64.
-    Returns positions [len(t)][3][3] in metres.
+    0.5 %).  Spacecraft k = 0, 1, 2 has longitude of periastron lam1 - 2 pi
+    k / 3 and initial mean anomaly ``phase`` + 2 pi k / 3 (so ``lam1`` and
+    ``phase`` are the two free parameters of an equal-armlength
+    configuration, Sec. IV.D).  Kepler's equation is solved by Newton
+    iteration in FP64.  Returns positions [len(t)][3][3] in metres.
     """
     t = np.asarray(t, dtype=np.float64)
     om = 2.0 * math.pi / YEAR
@@ -79,8 +82,8 @@ def keplerian_orbits(t, L=L_ARM, a=AU, detune=0.01, phase=0.0):
     tilt = math.atan(math.sqrt(3.0) * e * (1.0 + detune))
     out = np.empty(t.shape + (3, 3))
     for k in range(3):
-        sig = -2.0 * math.pi * k / 3.0
-        mean = om * t + phase - sig
+        sig = lam1 - 2.0 * math.pi * k / 3.0
+        mean = om * t + phase + 2.0 * math.pi * k / 3.0
         ecc = mean.copy()
         for _ in range(50):
             step = (ecc - e * np.sin(ecc) - mean) / (1.0 - e * np.cos(ecc))
@@ -145,9 +148,10 @@ class OrbitSamples:
 def make_orbit_samples(kind, t_begin, t_end, dt_orbit=1e4, margin=3, **kw):
     """Sample an orbit family on a coarse grid that covers [t_begin, t_end].
 
-    ``kind`` is 'rigid', 'keplerian' or 'static' (static needs ``positions``
+    ``kind`` is 'rigid', 'keplerian', 'static' (static needs ``positions``
     and optionally ``ltt`` = [6] constant light times; if ``ltt`` is omitted
-    the geometric distances / c are used).
+    the geometric distances / c are used) or 'function' (``fn``: t ->
+    positions [len(t)][3][3]).
     """
     k0 = math.floor(t_begin / dt_orbit) - margin
     k1 = math.ceil(t_end / dt_orbit) + margin
@@ -157,6 +161,8 @@ def make_orbit_samples(kind, t_begin, t_end, dt_orbit=1e4, margin=3, **kw):
         fn = lambda tt: rigid_orbits(tt, **kw)
     elif kind == "keplerian":
         fn = lambda tt: keplerian_orbits(tt, **kw)
+    elif kind == "function":
+        fn = kw["fn"]
     elif kind == "static":
         pos = np.asarray(kw["positions"], dtype=np.float64)
         x = static_orbits(t, pos)

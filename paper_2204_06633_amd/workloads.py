@@ -240,3 +240,39 @@ def fd_case(n_templates=1, seed=11):
     """One year of A/E/T at dt = 10 s (3,155,760 samples) per template."""
     n = int(round(inputs.YEAR / 10.0))
     return FdCase("fd_1yr_dt10_aet", n, 10.0, n_templates, seed)
+
+
+@dataclasses.dataclass
+class OrbitConfigCase:
+    """One source seen through the orbit models of Sec. V: accurate orbits
+    (the flexing Keplerian stand-in for the ESA files) and the equal-armlength
+    configuration fitted to them, on one template grid that suits both."""
+    name: str
+    accurate: inputs.OrbitSamples
+    equal_arm: inputs.OrbitSamples
+    eq_params: tuple
+    grid: object
+    params: np.ndarray
+    hp: np.ndarray
+    hc: np.ndarray
+    order: int = 25
+    generation: int = 2
+
+
+def orbit_config_case(n_out, dt=10.0, t_start=1.0e6, params=inputs.PAPER_FIG3_BINARY, order=25,
+                      fit_years=4.0):
+    """The paper's Fig. 3 binary on n_out samples; the equal-armlength
+    parameters come from the Nelder-Mead fit over ``fit_years`` (Sec. IV.D)."""
+    from . import orbitfit
+    t_end = t_start + n_out * dt
+    acc = inputs.make_orbit_samples("keplerian", t_start, t_end)
+    t_fit = np.linspace(0.0, fit_years * inputs.YEAR, int(fit_years * 365) + 1)
+    lam1, m1, _ = orbitfit.fit_eq_orbits(t_fit, inputs.keplerian_orbits(t_fit), x0=(0.1, 0.1))
+    eq = orbitfit.eq_orbit_samples(t_start, t_end, lam1, m1)
+    pads = np.maximum(inputs.conservative_padding(acc, order, dt),
+                      inputs.conservative_padding(eq, order, dt))
+    grid = inputs.TemplateGrid(dt, t_start, n_out, *(int(v) for v in pads))
+    params = np.asarray(params, dtype=np.float64)
+    hp, hc = inputs.gb_polarizations(params, grid.waveform_times())
+    return OrbitConfigCase("orbits_%d_dt%g" % (n_out, dt), acc, eq, (lam1, m1), grid, params,
+                           hp, hc, order)
