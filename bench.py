@@ -26,7 +26,10 @@ Beside the headline it reports, in the same line:
                        from a HIP graph, autotuned, against the plain
                        per-template forward on templates of the same batch;
   batched_fwd_adjoint  256 walkers, 1 yr at dt = 15 s, hybrid orbits:
-                       forward + likelihood + adjoint in one HIP graph.
+                       forward + likelihood + adjoint in one HIP graph;
+  sampler              the tempered ensemble sampler (4 x 50 walkers, stretch
+                       move) on 1 yr at dt = 15 s, proposals scored by the
+                       batched response and frequency-domain likelihood.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--no-batch]
@@ -278,6 +281,65 @@ def bench_batched_fwd_adjoint(steps, warmup, log):
             "ms_per_step": ms, "forward_only_ms": ms_fwd, "steps": steps, "graph": True,
             "group": tuned["group"], "gradients_finite": finite,
             "parity_forward": {"rel_err": err, "templates": 2, "tolerance": 1e-11}}
+
+
+def bench_sampler(steps, log):
+    """Four temperatures of 50 walkers (Sec. II.B) on one year at dt = 15 s:
+    tempered stretch-move steps whose proposals are scored by the torch
+    waveform, lr_response and lr_fd_loglike, 100 walkers per call."""
+    import numpy as np
+    import torch
+
+    from paper_2204_06633_amd import inputs, native, sampler, workloads
+    dev = torch.device("cuda:0")
+    sc = workloads.sampler_case()
+    g = sc.grid
+    log("sampler: %s, %d proposals per half step" % (sc.name, sc.m))
+    orb = native.Orbits.from_samples(sc.orbits, device=dev)
+    batch = native.Batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order, sc.generation,
+                         "AET", group=2, device=dev)
+    t_w = torch.tensor(g.waveform_times(), dtype=torch.float64, device=dev)
+    # noise-free data: the injection through the same batch machinery
+    from paper_2204_06633_amd import waveform
+    inj = torch.tensor(sc.injection, dtype=torch.float64, device=dev)
+    one = native.Batch(sc.layout(1), orb, orb, g.t_start, g.dt, sc.order, sc.generation, "AET",
+                       group=1, device=dev)
+    hp, hc = waveform.gb_polarizations(inj[None], t_w)
+    data = torch.empty(one.out_extent, dtype=torch.float64, device=dev)
+    one.response(hp.reshape(-1).contiguous(), hc.reshape(-1).contiguous(),
+                 inj[6:8].reshape(1, 2).contiguous(), out=data)
+    n_fft = native.fd_length(g.n_out)
+    w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
+    plan = native.FdPlan(data.view(3, g.n_out), torch.tensor(w_ae, device=dev),
+                         torch.tensor(w_t, device=dev), g.dt, max_batch=sc.m)
+    del one, hp, hc
+    lo, hi = sampler.prior_box(sc.injection[0], sc.injection[1])
+    betas = [1.0, 0.25, 0.0625, 0.0]
+    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, t_w, sc.m), betas, lo, hi)
+    rng = np.random.default_rng(9)
+    th0 = sampler.to_theta(inj.cpu()).numpy()
+    scale = np.array([1e-2, 1e-7, 1e-17, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
+    x, ll, lp = ps.initial(torch.tensor(th0 + scale * rng.standard_normal((sc.T, sc.W, 8)),
+                                        device=dev))
+    gen = torch.Generator(device=dev).manual_seed(3)
+    x, ll, lp, _, _ = ps.step(x, ll, lp, sampler.draw(gen, sc.T, sc.W, device=dev))   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc_tot = torch.zeros(sc.T, dtype=torch.int64, device=dev)
+    for _ in range(steps):
+        x, ll, lp, acc, _ = ps.step(x, ll, lp, sampler.draw(gen, sc.T, sc.W, device=dev))
+        acc_tot += acc
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    evals = 2 * sc.m
+    return {"workload": sc.name, "temperatures": sc.T, "walkers_per_temperature": sc.W,
+            "time_samples": g.n_out, "ms_per_step": ms, "steps": steps,
+            "likelihood_evals_per_s": evals / (ms * 1e-3),
+            "value": evals * 6.0 * g.n_out / (ms * 1e-3),
+            "unit": "samples/s (templates×links×time)",
+            "acceptance_per_temperature": (acc_tot.float() / (steps * sc.W)).tolist(),
+            "step": "tempered stretch move over 4 x 50 walkers: torch waveform -> lr_response "
+                    "-> lr_fd_loglike (statistics) per half step, then tempering swaps"}
 
 
 def main():
@@ -542,6 +604,8 @@ def main():
         result["batched_forward"] = bench_batched_forward(max(3, args.steps // 4), 1, log)
         torch.cuda.empty_cache()
         result["batched_fwd_adjoint"] = bench_batched_fwd_adjoint(3, 1, log)
+        torch.cuda.empty_cache()
+        result["sampler"] = bench_sampler(3, log)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

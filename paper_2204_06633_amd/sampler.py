@@ -1,0 +1,186 @@
+"""Parallel-tempered ensemble sampler with the stretch move (Sec. II.B),
+driving the batched response and the frequency-domain likelihood.
+
+Per step and temperature the walkers are split into two halves; each walker
+of the active half moves along the line through a random walker of the
+other half (the affine-invariant stretch move of Goodman and Weare, 2010):
+y = x_k + z (x_j - x_k) with z drawn from g(z) ~ 1/sqrt(z) on [1/a, a], and
+is accepted with probability min(1, z^(D-1) pi(y) L(y)^beta / (pi(x_j)
+L(x_j)^beta)).  All proposals of a half step, over every temperature, are
+scored in one batched likelihood call.  Then adjacent temperatures exchange
+walkers, hottest pair first (the parallel-tempering swaps of ptemcee,
+Vousden et al. 2016): walkers of the two chains are paired by two random
+permutations and a pair swaps with probability min(1, exp((beta_i -
+beta_{i+1}) (log L_{i+1} - log L_i))).
+
+The random numbers are drawn up front (``draw``) and passed to ``step``, so
+a step is a deterministic function of its inputs.  The parameter vector is
+theta = (ln A, f0 [mHz], fdot [Hz/s], cos iota, phi0, psi, lambda, sin beta)
+with the uniform box prior of Table I.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import torch
+
+G_MSUN_C3 = 4.925490947641267e-06        # G M_sun / c^3 in seconds
+NDIM = 8
+
+
+def fdot_gw(f0, mc_solar):
+    """Eq. (fdot): fdot = 96/5 pi^(8/3) (G Mc / c^3)^(5/3) f^(11/3)."""
+    return 96.0 / 5.0 * math.pi ** (8.0 / 3.0) * (mc_solar * G_MSUN_C3) ** (5.0 / 3.0) * \
+        f0 ** (11.0 / 3.0)
+
+
+def prior_box(A_star, f0_star):
+    """Lower and upper bounds of theta (Table I)."""
+    lo = [math.log(A_star * 1e-2), 0.5, fdot_gw(f0_star, 1e-3), -1.0, 0.0, 0.0, 0.0, -1.0]
+    hi = [math.log(A_star * 1e2), 12.0, fdot_gw(f0_star, 1.0), 1.0, 2 * math.pi, math.pi,
+          2 * math.pi, 1.0]
+    return lo, hi
+
+
+def to_theta(source):
+    """Waveform parameters (A, f0, fdot, phi0, iota, psi, lam, beta) -> theta."""
+    s = torch.as_tensor(source, dtype=torch.float64)
+    return torch.stack([torch.log(s[..., 0]), s[..., 1] * 1e3, s[..., 2], torch.cos(s[..., 4]),
+                        s[..., 3], s[..., 5], s[..., 6], torch.sin(s[..., 7])], -1)
+
+
+def to_source(theta):
+    """theta -> waveform parameters (A, f0, fdot, phi0, iota, psi, lam, beta)."""
+    th = theta
+    return torch.stack([torch.exp(th[..., 0]), th[..., 1] * 1e-3, th[..., 2],
+                        th[..., 4], torch.acos(th[..., 3].clamp(-1.0, 1.0)), th[..., 5],
+                        th[..., 6], torch.asin(th[..., 7].clamp(-1.0, 1.0))], -1)
+
+
+@dataclasses.dataclass
+class StepDraws:
+    """Random numbers of one step: T temperatures, W walkers (even)."""
+    z: torch.Tensor            # [2][T][W/2] stretch factors
+    partner: torch.Tensor      # [2][T][W/2] index into the other half
+    log_u: torch.Tensor        # [2][T][W/2] log of uniform(0, 1) for acceptance
+    perm_hi: torch.Tensor      # [T-1][W] walker order of the hotter chain of pair i
+    perm_lo: torch.Tensor      # [T-1][W] walker order of the colder chain
+    log_u_swap: torch.Tensor   # [T-1][W]
+
+
+def draw(gen, T, W, a=2.0, device="cuda"):
+    """StepDraws from a torch generator (on ``device``)."""
+    h = W // 2
+    u = torch.rand((2, T, h), dtype=torch.float64, device=device, generator=gen)
+    z = ((a - 1.0) * u + 1.0) ** 2 / a
+    partner = torch.randint(0, h, (2, T, h), device=device, generator=gen)
+    log_u = torch.log(torch.rand((2, T, h), dtype=torch.float64, device=device, generator=gen))
+    perm_hi = torch.stack([torch.randperm(W, device=device, generator=gen) for _ in range(T - 1)]) \
+        if T > 1 else torch.empty((0, W), dtype=torch.int64, device=device)
+    perm_lo = torch.stack([torch.randperm(W, device=device, generator=gen) for _ in range(T - 1)]) \
+        if T > 1 else torch.empty((0, W), dtype=torch.int64, device=device)
+    log_u_swap = torch.log(torch.rand((max(T - 1, 0), W), dtype=torch.float64, device=device,
+                                      generator=gen))
+    return StepDraws(z, partner, log_u, perm_hi, perm_lo, log_u_swap)
+
+
+def log_prior(theta, lo, hi):
+    """0 inside the box, -inf outside (a uniform density up to a constant)."""
+    lo = torch.as_tensor(lo, dtype=theta.dtype, device=theta.device)
+    hi = torch.as_tensor(hi, dtype=theta.dtype, device=theta.device)
+    inside = ((theta >= lo) & (theta <= hi)).all(-1)
+    return torch.where(inside, torch.zeros_like(theta[..., 0]),
+                       torch.full_like(theta[..., 0], -math.inf))
+
+
+class PTSampler:
+    """State x [T][W][D], log L [T][W], log prior [T][W] on the device.
+
+    ``loglike(theta [M][D]) -> [M]`` scores a batch of proposals; entries
+    outside the prior are never used (they are clamped into the box before
+    the call so every template stays finite)."""
+
+    def __init__(self, loglike, betas, lo, hi, a=2.0):
+        self.loglike = loglike
+        self.betas = torch.as_tensor(betas, dtype=torch.float64)
+        self.lo, self.hi, self.a = lo, hi, a
+
+    def initial(self, x):
+        T, W, D = x.shape
+        lp = log_prior(x, self.lo, self.hi)
+        ll = self.loglike(x.reshape(T * W, D)).reshape(T, W)
+        return x.clone(), ll, lp
+
+    def step(self, x, ll, lp, d: StepDraws):
+        T, W, D = x.shape
+        h = W // 2
+        betas = self.betas.to(x.device)
+        lo = torch.as_tensor(self.lo, dtype=x.dtype, device=x.device)
+        hi = torch.as_tensor(self.hi, dtype=x.dtype, device=x.device)
+        x, ll, lp = x.clone(), ll.clone(), lp.clone()
+        n_acc = torch.zeros((T,), dtype=torch.int64, device=x.device)
+        tix = torch.arange(T, device=x.device)[:, None]
+        for half in range(2):
+            act = slice(half * h, (half + 1) * h)
+            oth = slice((1 - half) * h, (2 - half) * h)
+            xa, xo = x[:, act], x[:, oth]
+            xk = xo[tix, d.partner[half]]                       # [T][h][D]
+            z = d.z[half]
+            y = xk + z[..., None] * (xa - xk)
+            lp_y = log_prior(y, self.lo, self.hi)
+            ll_y = self.loglike(torch.minimum(torch.maximum(y, lo), hi).reshape(T * h, D))
+            ll_y = ll_y.reshape(T, h)
+            log_r = (D - 1) * torch.log(z) + betas[:, None] * (ll_y - ll[:, act]) + lp_y - \
+                lp[:, act]
+            acc = torch.isfinite(lp_y) & (d.log_u[half] < log_r)
+            x[:, act] = torch.where(acc[..., None], y, xa)
+            ll[:, act] = torch.where(acc, ll_y, ll[:, act])
+            lp[:, act] = torch.where(acc, lp_y, lp[:, act])
+            n_acc += acc.sum(-1)
+        n_swap = torch.zeros((max(T - 1, 0),), dtype=torch.int64, device=x.device)
+        for i in range(T - 1, 0, -1):                           # hottest pair first
+            hi_i, lo_i = d.perm_hi[i - 1], d.perm_lo[i - 1]
+            p_acc = (betas[i - 1] - betas[i]) * (ll[i, hi_i] - ll[i - 1, lo_i])
+            sel = d.log_u_swap[i - 1] < p_acc
+            a_hi, a_lo = hi_i[sel], lo_i[sel]
+            for arr in (x, ll, lp):
+                tmp = arr[i, a_hi].clone()
+                arr[i, a_hi] = arr[i - 1, a_lo]
+                arr[i - 1, a_lo] = tmp
+            n_swap[i - 1] = sel.sum()
+        return x, ll, lp, n_acc, n_swap
+
+
+class BatchLoglike:
+    """log L(theta) for walkers sharing one output grid: torch waveform on
+    the device -> lr_response (fused batch kernel) -> lr_fd_loglike
+    statistics, ``m`` walkers per call.  ``batch``: a native.Batch of ``m``
+    equal templates laid out back to back; ``plan``: an FdPlan on the data;
+    theta [M][8] with M a multiple of m."""
+
+    def __init__(self, batch, plan, t_waveform, m):
+        self.batch, self.plan, self.t, self.m = batch, plan, t_waveform, m
+        dev = t_waveform.device
+        n_h = t_waveform.numel()
+        self.n_out = plan.n
+        self.out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
+        self.stats = torch.empty((m, 3), dtype=torch.float64, device=dev)
+        self.n_h = n_h
+
+    def __call__(self, theta):
+        from . import waveform
+        M, m = theta.shape[0], self.m
+        if M % m:
+            raise ValueError("%d proposals for a batch of %d walkers" % (M, m))
+        out = []
+        for c in range(0, M, m):
+            src = to_source(theta[c:c + m])
+            hp, hc = waveform.gb_polarizations(src, self.t)
+            sky = src[:, 6:8].contiguous()
+            self.batch.response(hp.reshape(-1).contiguous(), hc.reshape(-1).contiguous(), sky,
+                                out=self.out)
+            h = self.out[:m * 3 * self.n_out].view(m, 3, self.n_out)
+            self.plan.loglike(h, want_grad=False, stats=self.stats)
+            out.append(-0.5 * self.stats[:, 0].clone())
+        return torch.cat(out)

@@ -276,3 +276,36 @@ def orbit_config_case(n_out, dt=10.0, t_start=1.0e6, params=inputs.PAPER_FIG3_BI
     hp, hc = inputs.gb_polarizations(params, grid.waveform_times())
     return OrbitConfigCase("orbits_%d_dt%g" % (n_out, dt), acc, eq, (lam1, m1), grid, params,
                            hp, hc, order)
+
+
+@dataclasses.dataclass
+class SamplerCase:
+    """A tempered-sampler run: ``T`` temperatures of ``W`` walkers on one
+    output grid, noise-free data from the injected source (as in Sec. V)."""
+    name: str
+    T: int
+    W: int
+    orbits: inputs.OrbitSamples
+    grid: object
+    injection: np.ndarray
+    order: int = 25
+    generation: int = 2
+
+    @property
+    def m(self):
+        return self.T * self.W // 2                     # proposals per half step
+
+    def layout(self, m):
+        g = self.grid
+        return [(k * g.n_h, g.n_h, g.out_start, g.n_out, 3 * k * g.n_out) for k in range(m)]
+
+
+def sampler_case(T=4, W=50, n_out=None, dt=15.0, t_start=1.0e6,
+                 injection=inputs.PAPER_FIG3_BINARY, order=25):
+    """The paper's sampler settings (4 temperatures of 50 walkers) on one
+    year at dt = 15 s by default, flexing Keplerian orbits."""
+    n_out = n_out or int(round(inputs.YEAR / dt))
+    orb = inputs.make_orbit_samples("keplerian", t_start, t_start + n_out * dt)
+    grid = inputs.make_template_grid(orb, order, dt, t_start, n_out, 2)
+    return SamplerCase("sampler_T%d_W%d_n%d_dt%g" % (T, W, n_out, dt), T, W, orb, grid,
+                       np.asarray(injection, dtype=np.float64), order)

@@ -1,0 +1,118 @@
+"""Host checks of the tempered ensemble sampler (Sec. II.B).
+
+The oracle's step is pinned by what the sampler must do on a target with a
+known answer: a Gaussian likelihood under a flat prior, where the chain at
+inverse temperature beta samples N(mu, Sigma / beta); a wrong acceptance rule
+(sign, missing z^(D-1) factor, swapped temperatures) changes those moments.
+The product's step (torch, run here on the CPU) must take the same
+decisions as the oracle's on the same random numbers."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sampler as osamp
+from paper_2204_06633_amd import sampler
+
+
+def _gauss(mu, sig):
+    def ll(thetas):
+        return [-0.5 * float(np.sum(((np.asarray(t) - mu) / sig) ** 2)) for t in thetas]
+    return ll
+
+
+def _np_draws(d):
+    return {k: getattr(d, k).cpu().numpy() for k in ("z", "partner", "log_u", "perm_hi",
+                                                     "perm_lo", "log_u_swap")}
+
+
+def test_stretch_factor_density():
+    # z = ((a - 1) u + 1)^2 / a has density proportional to 1/sqrt(z) on [1/a, a]:
+    # CDF F(z) = (sqrt(z) - sqrt(1/a)) / (sqrt(a) - sqrt(1/a))
+    g = torch.Generator().manual_seed(1)
+    d = sampler.draw(g, 2, 2000, a=2.0, device="cpu")
+    z = np.sort(d.z.numpy().ravel())
+    assert z.min() >= 0.5 and z.max() <= 2.0
+    F = (np.sqrt(z) - math.sqrt(0.5)) / (math.sqrt(2.0) - math.sqrt(0.5))
+    emp = (np.arange(z.size) + 0.5) / z.size
+    assert np.max(np.abs(F - emp)) < 0.02                  # Kolmogorov distance, n = 4000
+
+
+def test_oracle_samples_tempered_gaussians():
+    rng = np.random.default_rng(3)
+    T, W, D = 3, 32, 2
+    betas = [1.0, 0.5, 0.25]
+    mu, sig = np.array([0.3, -0.2]), np.array([1.0, 0.5])
+    lo, hi = [-50.0, -50.0], [50.0, 50.0]
+    ll_fn = _gauss(mu, sig)
+    x = mu + rng.standard_normal((T, W, D)) * sig
+    ll = np.array([[ll_fn([x[t, w]])[0] for w in range(W)] for t in range(T)])
+    lp = np.zeros((T, W))
+    g = torch.Generator().manual_seed(7)
+    samples = [[] for _ in range(T)]
+    for it in range(1500):
+        d = _np_draws(sampler.draw(g, T, W, device="cpu"))
+        x, ll, lp, _, _ = osamp.step(x, ll, lp, betas, d, ll_fn, lo, hi)
+        if it >= 300:
+            for t in range(T):
+                samples[t].append(x[t].copy())
+    for t, b in enumerate(betas):
+        s = np.concatenate(samples[t])
+        assert np.all(np.abs(s.mean(0) - mu) < 0.1 * sig / math.sqrt(b)), (t, s.mean(0))
+        assert np.all(np.abs(s.var(0) / (sig ** 2 / b) - 1.0) < 0.15), (t, s.var(0))
+
+
+def test_oracle_step_by_hand():
+    # one walker pair, one temperature: the proposal, acceptance and the
+    # z^(D-1) factor written out
+    x = np.array([[[0.0, 0.0], [1.0, 2.0]]])
+    ll = np.array([[0.0, 0.0]])
+    lp = np.zeros((1, 2))
+    flat = lambda thetas: [0.0] * len(thetas)
+    d = {"z": np.array([[[1.5]], [[0.6]]]), "partner": np.zeros((2, 1, 1), int),
+         "log_u": np.array([[[math.log(1.5) - 1e-9]], [[math.log(0.6) + 1e-9]]]),
+         "perm_hi": np.zeros((0, 2), int), "perm_lo": np.zeros((0, 2), int),
+         "log_u_swap": np.zeros((0, 2))}
+    x2, _, _, acc, _ = osamp.step(x, ll, lp, [1.0], d, flat, [-9, -9], [9, 9])
+    # walker 0 moves to x1 + 1.5 (x0 - x1) = (-0.5, -1); walker 1 then stays
+    # (u just above z^(D-1) = 0.6)
+    assert np.allclose(x2[0, 0], [-0.5, -1.0]) and np.allclose(x2[0, 1], [1.0, 2.0])
+    assert acc == [1]
+
+
+def test_product_step_matches_oracle():
+    rng = np.random.default_rng(11)
+    T, W, D = 4, 8, 3
+    betas = [1.0, 0.4, 0.15, 0.0]
+    mu, sig = np.array([0.1, 0.5, -0.3]), np.array([0.5, 0.3, 0.8])
+    lo, hi = [-2.0, -2.0, -2.0], [2.0, 2.0, 2.0]
+    ll_np = _gauss(mu, sig)
+
+    def ll_torch(theta):
+        return -0.5 * (((theta - torch.as_tensor(mu)) / torch.as_tensor(sig)) ** 2).sum(-1)
+
+    ps = sampler.PTSampler(ll_torch, betas, lo, hi)
+    x0 = torch.as_tensor(mu + 0.5 * rng.standard_normal((T, W, D)) * sig)
+    x, ll, lp = ps.initial(x0)
+    xo, llo, lpo = x.numpy().copy(), ll.numpy().copy(), lp.numpy().copy()
+    g = torch.Generator().manual_seed(5)
+    for _ in range(20):
+        d = sampler.draw(g, T, W, device="cpu")
+        x, ll, lp, acc, sw = ps.step(x, ll, lp, d)
+        xo, llo, lpo, acc_o, sw_o = osamp.step(xo, llo, lpo, betas, _np_draws(d), ll_np, lo, hi)
+        assert acc.tolist() == acc_o and sw.tolist() == sw_o
+        assert np.allclose(x.numpy(), xo, rtol=0, atol=1e-12)
+        assert np.allclose(ll.numpy(), llo, rtol=1e-12, atol=1e-12)
+
+
+def test_prior_box_and_parameter_maps():
+    lo, hi = sampler.prior_box(1e-22, 10e-3)
+    assert math.isclose(math.exp(lo[0]), 1e-24) and math.isclose(math.exp(hi[0]), 1e-20)
+    # eq. (fdot) at 10 mHz: 1.4e-14 Hz/s lies between the chirp-mass bounds
+    assert lo[2] < 1.4e-14 < hi[2]
+    src = torch.tensor([1e-22, 10e-3, 1.4e-14, 4.58, 1.11, 0.45, 5.23, 1.23], dtype=torch.float64)
+    th = sampler.to_theta(src)
+    assert torch.allclose(sampler.to_source(th), src, rtol=1e-14, atol=0)
+    assert float(sampler.log_prior(th, lo, hi)) == 0.0
+    assert float(sampler.log_prior(th + torch.tensor([0, 20.0, 0, 0, 0, 0, 0, 0]), lo, hi)) == -math.inf
