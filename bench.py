@@ -285,8 +285,9 @@ def bench_batched_fwd_adjoint(steps, warmup, log):
 
 def bench_sampler(steps, log):
     """Four temperatures of 50 walkers (Sec. II.B) on one year at dt = 15 s:
-    tempered stretch-move steps whose proposals are scored by the torch
-    waveform, lr_response and lr_fd_loglike, 100 walkers per call."""
+    tempered stretch-move steps whose proposals are scored by
+    lr_gb_polarizations, lr_response and lr_fd_loglike, 100 walkers per
+    call."""
     import numpy as np
     import torch
 
@@ -315,7 +316,8 @@ def bench_sampler(steps, log):
     del one, hp, hc
     lo, hi = sampler.prior_box(sc.injection[0], sc.injection[1])
     betas = [1.0, 0.25, 0.0625, 0.0]
-    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, t_w, sc.m), betas, lo, hi)
+    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, -g.out_start, g.n_h, g.dt, sc.m),
+                           betas, lo, hi)
     rng = np.random.default_rng(9)
     th0 = sampler.to_theta(inj.cpu()).numpy()
     scale = np.array([1e-2, 1e-7, 1e-17, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
@@ -338,7 +340,7 @@ def bench_sampler(steps, log):
             "value": evals * 6.0 * g.n_out / (ms * 1e-3),
             "unit": "samples/s (templates×links×time)",
             "acceptance_per_temperature": (acc_tot.float() / (steps * sc.W)).tolist(),
-            "step": "tempered stretch move over 4 x 50 walkers: torch waveform -> lr_response "
+            "step": "tempered stretch move over 4 x 50 walkers: lr_gb_polarizations -> lr_response "
                     "-> lr_fd_loglike (statistics) per half step, then tempering swaps"}
 
 
@@ -517,6 +519,18 @@ def main():
 
     ms_grad = _timed(grad_step, max(3, args.steps // 2), 1)
     grad_ok = bool(torch.isfinite(grad_step()).all())
+
+    def grad_step_hip():
+        # the same with the polarisations and their adjoint in the HIP library
+        p = theta.clone().requires_grad_(True)
+        hp_, hc_ = response.gb_polarizations(p[None], -g.out_start, g.n_h, g.dt)
+        ll = response.loglike(response.response(tpl_aet, hp_[0], hc_[0], p[6:8]), data_aet, 1e-21)
+        ll.backward()
+        return p.grad
+
+    ms_grad_hip = _timed(grad_step_hip, max(3, args.steps // 2), 1)
+    g_t, g_h = grad_step(), grad_step_hip()
+    grad_agree = float(((g_h - g_t).abs() / g_t.abs().clamp_min(1e-300)).max())
     del data_aet
 
     # the same template through the fused batch kernel (a batch of one)
@@ -591,7 +605,9 @@ def main():
                           "unit": "samples/s (templates×links×time)", "ms_per_step": ms_grad,
                           "step": "8 source parameters -> h+, hx (torch) -> response (A/E/T) -> "
                                   "likelihood -> adjoint -> autograd to the parameters",
-                          "gradient_finite": grad_ok},
+                          "gradient_finite": grad_ok,
+                          "ms_per_step_hip_waveform": ms_grad_hip,
+                          "hip_vs_torch_waveform_rel_diff": grad_agree},
         "fused_single": {"value": 6.0 * n / (ms_one * 1e-3),
                          "unit": "samples/s (templates×links×time)", "ms_per_step": ms_one,
                          "step": "the headline template through lr_response (fused projection "

@@ -331,6 +331,41 @@ int lr_fd_prepare(int64_t n, int channels, double dt, const double *data, int64_
 int lr_fd_loglike(const lr_fd_plan *p, int64_t n_templates, const double *h, int64_t t_stride,
                   int64_t c_stride, double *stats, double *g_h, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Galactic-binary polarisations, Sec. III, for n templates on one time grid:
+ *   Phi(t) = 2 pi (f0 t + fdot t^2/2 + fddot t^3/6) + phi0,
+ *   fddot = 11 fdot^2 / (3 f0),
+ *   a+ = -(1 + cos^2 iota) A cos Phi,   ax = -2 cos(iota) A sin Phi,
+ *   h+ = cos(2 psi) a+ - sin(2 psi) ax, hx = sin(2 psi) a+ + cos(2 psi) ax,
+ * at t_j = (k0 + j) dt, j = 0 .. n_h - 1 (t = 0 at the template's first
+ * output sample: k0 = -out_start).  The phase is evaluated in cycles with
+ * the product f0 t split exactly and whole cycles removed, so its rounding
+ * stays ~1e-15 rad over years.  params: device [n][8] = (A, f0, fdot,
+ * phi0, iota, psi, lambda, beta) (lambda, beta unused here); f0 <= 0 gives
+ * non-finite output, not an error (the values are not read on the host).
+ * ---------------------------------------------------------------------- */
+
+/* hp, hc: device, template t's samples at hp + t * h_stride (h_stride >=
+ * n_h), overwritten.  Graph-capturable.  Errors: LR_E_ARG (sizes, dt,
+ * overlap), LR_E_UNSUPPORTED (n > 65535), LR_E_HIP. */
+int lr_gb_polarizations(const double *params, int64_t n, int64_t k0, int64_t n_h, double dt,
+                        double *hp, double *hc, int64_t h_stride, void *stream);
+
+/* Device workspace bytes of lr_gb_polarizations_adjoint. */
+size_t lr_gb_adjoint_workspace(int64_t n, int64_t n_h);
+
+/* g_params[t][k] = sum_j (g_hp[t][j] dh+/dparam_k + g_hc[t][j] dhx/dparam_k)
+ * (the transpose of the linearised lr_gb_polarizations; fddot's dependence
+ * on f0 and fdot included; the lambda and beta entries are 0).  g_hp, g_hc
+ * laid out like hp, hc; g_params device [n][8], overwritten.  Sums are
+ * per-block partials reduced in a fixed order (deterministic).
+ * Graph-capturable.  Errors: LR_E_ARG, LR_E_UNSUPPORTED, LR_E_WORKSPACE,
+ * LR_E_HIP. */
+int lr_gb_polarizations_adjoint(const double *params, int64_t n, int64_t k0, int64_t n_h,
+                                double dt, const double *g_hp, const double *g_hc,
+                                int64_t h_stride, double *g_params, void *work,
+                                size_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -474,3 +474,73 @@ class FdPlan:
         if want_grad and h.dim() == 2:
             g_h = g_h[0]
         return stats, (g_h if want_grad else None)
+
+
+# ---------------------------------------------------------------------------
+# Galactic-binary polarisations (lr_gb_*)
+# ---------------------------------------------------------------------------
+
+def _gb_lib():
+    L = lib()
+    if getattr(L, "_gb_ready", False):
+        return L
+    d, i64, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
+    L.lr_gb_polarizations.restype = ctypes.c_int
+    L.lr_gb_polarizations.argtypes = [vp, i64, i64, i64, d, vp, vp, i64, vp]
+    L.lr_gb_adjoint_workspace.restype = ctypes.c_size_t
+    L.lr_gb_adjoint_workspace.argtypes = [i64, i64]
+    L.lr_gb_polarizations_adjoint.restype = ctypes.c_int
+    L.lr_gb_polarizations_adjoint.argtypes = [vp, i64, i64, i64, d, vp, vp, i64, vp, vp,
+                                              ctypes.c_size_t, vp]
+    L._gb_ready = True
+    return L
+
+
+def _dev_rows(t, name):
+    """Pointer of a float64 CUDA tensor [n][m] whose rows are contiguous (any
+    row stride)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError("%s must be [n][m] with contiguous rows" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def gb_polarizations(params, k0, n_h, dt, hp=None, hc=None, stream=None):
+    """(h+, hx) [n][n_h] for params [n][8] on t_j = (k0 + j) dt
+    (lr_gb_polarizations)."""
+    import torch
+    n = params.shape[0]
+    if hp is None:
+        hp = torch.empty((n, n_h), dtype=torch.float64, device=params.device)
+    if hc is None:
+        hc = torch.empty((n, n_h), dtype=torch.float64, device=params.device)
+    if hp.stride(0) != hc.stride(0):
+        raise ValueError("hp and hc must share one row stride")
+    _check(_gb_lib().lr_gb_polarizations(_dev(params, "params"), n, int(k0), int(n_h), float(dt),
+                                         _dev_rows(hp, "hp"), _dev_rows(hc, "hc"),
+                                         max(hp.stride(0), int(n_h)), _stream(stream)),
+           "lr_gb_polarizations")
+    return hp, hc
+
+
+def gb_polarizations_adjoint(params, k0, dt, g_hp, g_hc, g_params=None, work=None, stream=None):
+    """d/dparams of sum(g_hp h+ + g_hc hx), [n][8] (lr_gb_polarizations_adjoint)."""
+    import torch
+    n, n_h = g_hp.shape
+    L = _gb_lib()
+    if g_params is None:
+        g_params = torch.empty((n, 8), dtype=torch.float64, device=params.device)
+    nb = L.lr_gb_adjoint_workspace(n, n_h)
+    if work is None:
+        work = torch.empty((nb + 7) // 8, dtype=torch.float64, device=params.device)
+    if g_hp.stride(0) != g_hc.stride(0):
+        raise ValueError("g_hp and g_hc must share one row stride")
+    _check(L.lr_gb_polarizations_adjoint(_dev(params, "params"), n, int(k0), int(n_h), float(dt),
+                                         _dev_rows(g_hp, "g_hp"), _dev_rows(g_hc, "g_hc"),
+                                         max(g_hp.stride(0), int(n_h)),
+                                         _dev(g_params, "g_params"), _dev(work, "work"),
+                                         work.numel() * 8, _stream(stream)),
+           "lr_gb_polarizations_adjoint")
+    return g_params

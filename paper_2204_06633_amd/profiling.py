@@ -6,6 +6,7 @@
     python -m paper_2204_06633_amd.profiling --what batch --templates 64
     python -m paper_2204_06633_amd.profiling --what batch-adjoint --templates 32
     python -m paper_2204_06633_amd.profiling --what fd --templates 4
+    python -m paper_2204_06633_amd.profiling --what sampler --reps 2
 
 ``forward`` runs the per-template forward (projection + TDI-2 XYZ+AET) on the
 1-yr, dt = 10 s, order-25 Keplerian workload; ``adjoint`` adds the adjoint
@@ -15,8 +16,9 @@ on the first ``--templates`` templates of the 512-template uneven batch
 (group 2); ``batch-adjoint`` runs forward, likelihood and adjoint of that
 many 1-yr, dt = 15 s walkers with hybrid orbits; ``fd`` runs the
 frequency-domain likelihood with its gradient on ``--templates`` one-year
-A/E/T series at dt = 10 s (2^22-point transforms).  Each step prints a line
-so a profiler run shows progress.
+A/E/T series at dt = 10 s (2^22-point transforms); ``sampler`` runs
+tempered stretch-move steps of 4 x 50 walkers on one year at dt = 15 s.
+Each step prints a line so a profiler run shows progress.
 """
 from __future__ import annotations
 
@@ -26,7 +28,8 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["forward", "adjoint", "copy", "batch", "batch-adjoint", "fd"],
+    ap.add_argument("--what", choices=["forward", "adjoint", "copy", "batch", "batch-adjoint", "fd",
+                             "sampler"],
                     default="forward")
     ap.add_argument("--templates", type=int, default=64)
     ap.add_argument("--group", type=int, default=2)
@@ -52,6 +55,11 @@ def main(argv=None):
         return run_batch(args, dev)
     if args.what == "fd":
         return run_fd(args, dev)
+    if args.what == "sampler":
+        import bench
+        r = bench.bench_sampler(args.reps, lambda msg: print(msg, flush=True))
+        print("sampler: %.1f ms per step" % r["ms_per_step"], flush=True)
+        return
     case = workloads.config_c2("XYZAET")
     g = case.grid
     orb = native.Orbits.from_samples(case.orbits_proj, device=dev)

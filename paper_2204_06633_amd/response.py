@@ -118,3 +118,31 @@ class FdLoglikeFn(torch.autograd.Function):
 
 def fd_loglike(h, plan):
     return FdLoglikeFn.apply(h, plan)
+
+
+class GbPolarizationsFn(torch.autograd.Function):
+    """(h+, hx) [n][n_h] of Galactic binaries (lr_gb_polarizations) for
+    params [n][8] on t_j = (k0 + j) dt; backward: lr_gb_polarizations_adjoint."""
+
+    @staticmethod
+    def forward(ctx, params, k0, n_h, dt):
+        params = params.contiguous()
+        hp, hc = native.gb_polarizations(params, k0, n_h, dt)
+        ctx.save_for_backward(params)
+        ctx.k0, ctx.dt = k0, dt
+        return hp, hc
+
+    @staticmethod
+    def backward(ctx, g_hp, g_hc):
+        (params,) = ctx.saved_tensors
+        if g_hp is None:
+            g_hp = torch.zeros_like(g_hc)
+        if g_hc is None:
+            g_hc = torch.zeros_like(g_hp)
+        g = native.gb_polarizations_adjoint(params, ctx.k0, ctx.dt, g_hp.contiguous(),
+                                            g_hc.contiguous())
+        return g, None, None, None
+
+
+def gb_polarizations(params, k0, n_h, dt):
+    return GbPolarizationsFn.apply(params, k0, n_h, dt)

@@ -7,7 +7,8 @@ other half (the affine-invariant stretch move of Goodman and Weare, 2010):
 y = x_k + z (x_j - x_k) with z drawn from g(z) ~ 1/sqrt(z) on [1/a, a], and
 is accepted with probability min(1, z^(D-1) pi(y) L(y)^beta / (pi(x_j)
 L(x_j)^beta)).  All proposals of a half step, over every temperature, are
-scored in one batched likelihood call.  Then adjacent temperatures exchange
+scored in one batched likelihood call (polarisations, response and
+likelihood all in the HIP library).  Then adjacent temperatures exchange
 walkers, hottest pair first (the parallel-tempering swaps of ptemcee,
 Vousden et al. 2016): walkers of the two chains are paired by two random
 permutations and a pair swaps with probability min(1, exp((beta_i -
@@ -153,32 +154,32 @@ class PTSampler:
 
 
 class BatchLoglike:
-    """log L(theta) for walkers sharing one output grid: torch waveform on
-    the device -> lr_response (fused batch kernel) -> lr_fd_loglike
-    statistics, ``m`` walkers per call.  ``batch``: a native.Batch of ``m``
-    equal templates laid out back to back; ``plan``: an FdPlan on the data;
+    """log L(theta) for walkers sharing one output grid: lr_gb_polarizations
+    -> lr_response (fused batch kernel) -> lr_fd_loglike statistics, ``m``
+    walkers per call.  ``batch``: a native.Batch of ``m`` equal templates
+    laid out back to back, each with n_h h-samples at waveform times
+    (k0 + j) dt (k0 = -out_start); ``plan``: an FdPlan on the data;
     theta [M][8] with M a multiple of m."""
 
-    def __init__(self, batch, plan, t_waveform, m):
-        self.batch, self.plan, self.t, self.m = batch, plan, t_waveform, m
-        dev = t_waveform.device
-        n_h = t_waveform.numel()
+    def __init__(self, batch, plan, k0, n_h, dt, m, device="cuda"):
+        self.batch, self.plan, self.m = batch, plan, m
+        self.k0, self.n_h, self.dt = int(k0), int(n_h), float(dt)
         self.n_out = plan.n
-        self.out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
-        self.stats = torch.empty((m, 3), dtype=torch.float64, device=dev)
-        self.n_h = n_h
+        self.out = torch.empty(batch.out_extent, dtype=torch.float64, device=device)
+        self.stats = torch.empty((m, 3), dtype=torch.float64, device=device)
+        self.hp = torch.empty((m, self.n_h), dtype=torch.float64, device=device)
+        self.hc = torch.empty_like(self.hp)
 
     def __call__(self, theta):
-        from . import waveform
+        from . import native
         M, m = theta.shape[0], self.m
         if M % m:
             raise ValueError("%d proposals for a batch of %d walkers" % (M, m))
         out = []
         for c in range(0, M, m):
-            src = to_source(theta[c:c + m])
-            hp, hc = waveform.gb_polarizations(src, self.t)
-            sky = src[:, 6:8].contiguous()
-            self.batch.response(hp.reshape(-1).contiguous(), hc.reshape(-1).contiguous(), sky,
+            src = to_source(theta[c:c + m]).contiguous()
+            native.gb_polarizations(src, self.k0, self.n_h, self.dt, hp=self.hp, hc=self.hc)
+            self.batch.response(self.hp.view(-1), self.hc.view(-1), src[:, 6:8].contiguous(),
                                 out=self.out)
             h = self.out[:m * 3 * self.n_out].view(m, 3, self.n_out)
             self.plan.loglike(h, want_grad=False, stats=self.stats)

@@ -258,3 +258,24 @@ def test_fd_lengths_workspace_and_rejections():
     assert L.lr_fd_loglike(ctypes.byref(plan), 1, a, 15000, 5000, ctypes.c_void_p(0x10000000),
                            c, None) == 1
     assert L.lr_fd_loglike(ctypes.byref(plan), 0, None, 0, 0, None, None, None) == 0
+
+
+def test_gb_rejections_before_launch():
+    L = native._gb_lib()
+    p, hp, hc = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x400000)
+    assert L.lr_gb_polarizations(p, 2, 0, 100, 10.0, hp, hc, 99, None) == 1      # stride < n_h
+    assert L.lr_gb_polarizations(p, 2, 0, 100, 0.0, hp, hc, 100, None) == 1      # dt
+    assert L.lr_gb_polarizations(p, -1, 0, 100, 10.0, hp, hc, 100, None) == 1
+    assert L.lr_gb_polarizations(p, 70000, 0, 100, 10.0, hp, hc, 100, None) == 3
+    assert L.lr_gb_polarizations(p, 2, 0, 100, 10.0, hp, ctypes.c_void_p(0x200100), 100,
+                                 None) == 1                                      # hp / hc overlap
+    assert L.lr_gb_polarizations(p, 2, 0, 100, 10.0, None, hc, 100, None) == 1
+    assert L.lr_gb_polarizations(p, 0, 0, 100, 10.0, None, None, 100, None) == 0  # nothing to do
+    nb = L.lr_gb_adjoint_workspace(2, 3000)
+    assert nb >= 2 * 3 * 7 * 8
+    w = ctypes.c_void_p(0x800000)
+    g = ctypes.c_void_p(0x600000)
+    assert L.lr_gb_polarizations_adjoint(p, 2, 0, 3000, 10.0, hp, hc, 3000, g, w, nb - 8,
+                                         None) == 4
+    assert L.lr_gb_polarizations_adjoint(p, 2, 0, 3000, 10.0, hp, hc, 3000, p, w, nb,
+                                         None) == 1                              # g aliases params

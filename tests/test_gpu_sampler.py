@@ -57,8 +57,8 @@ def test_sampler_steps_match_oracle(torch_cuda):
                          "AET", group=2, device=dev)
     plan = native.FdPlan(torch.tensor(data, device=dev), torch.tensor(w_ae, device=dev),
                          torch.tensor(w_t, device=dev), g.dt, max_batch=sc.m)
-    t_gpu = torch.tensor(t_w, dtype=torch.float64, device=dev)
-    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, t_gpu, sc.m), betas, lo, hi)
+    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, -g.out_start, g.n_h, g.dt, sc.m),
+                           betas, lo, hi)
     rng = np.random.default_rng(2)
     th0 = sampler.to_theta(torch.tensor(inj)).numpy()
     scale = np.array([1e-2, 1e-6, 1e-16, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
