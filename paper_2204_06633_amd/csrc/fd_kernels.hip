@@ -316,7 +316,20 @@ __global__ __launch_bounds__(kThreads) void fft_pass_kernel(PassArgs a) {
   __shared__ double2 lds[(kTile >> Q) * LS];
   const int tid = threadIdx.x;
   const int64_t N = (int64_t)1 << a.logN;
-  const int64_t tau = blockIdx.x;
+  // Tile tau = signal * tiles per signal + tile position.  The last forward
+  // pass reads the data spectrum and weights at the tile's positions, the
+  // same for every template: work-groups go to the 8 XCDs (separate L2s) in
+  // turn, so each XCD takes a contiguous run of work indices ordered
+  // (position, kind, template), and consecutive groups on one XCD share the
+  // spectrum and weights through its L2.
+  int64_t tau = blockIdx.x;
+  if (SPEC > 0 && a.n_tpl > 1 && (gridDim.x & 7) == 0) {
+    const int64_t per = gridDim.x >> 3;
+    const int64_t w = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t t = w % a.n_tpl, rest = w / a.n_tpl;
+    const int64_t kd = rest % a.sig_per_tpl, pos = rest / a.sig_per_tpl;
+    tau = ((t * a.sig_per_tpl + kd) << a.tiles_log) + pos;
+  }
   const int64_t sig = tau >> a.tiles_log;
   const int64_t tp = tau & (((int64_t)1 << a.tiles_log) - 1);
 
@@ -598,6 +611,7 @@ hipError_t run_fd_loglike(const FdGeometry& g, const FdBuffers& b, int64_t n_tpl
   a.dspec = b.dspec;
   a.wpos = b.wpos;
   a.part = b.part;
+  a.n_tpl = n_tpl;
   const int P = g.passes;
   const int spec = g_h ? 2 : 1;
   hipError_t e;

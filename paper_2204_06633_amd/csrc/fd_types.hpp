@@ -26,6 +26,7 @@ struct FdBuffers {
 namespace fd {
 struct PassArgs {
   int logN, q, logB, tiles_log, twiddle, sig_per_tpl;
+  int64_t n_tpl;        // templates in the launch (the last pass orders its tiles by it)
   double2* x;
   const double2* tlo;
   const double2* thi;
