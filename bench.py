@@ -297,8 +297,15 @@ def bench_sampler(steps, log):
     g = sc.grid
     log("sampler: %s, %d proposals per half step" % (sc.name, sc.m))
     orb = native.Orbits.from_samples(sc.orbits, device=dev)
-    batch = native.Batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order, sc.generation,
-                         "AET", group=2, device=dev)
+    # group and grid tuned on the walkers' batch (all slots at the injection)
+    from paper_2204_06633_amd import autotune
+    src_all = torch.tensor(sc.injection, dtype=torch.float64, device=dev).repeat(sc.m, 1)
+    hp_t, hc_t = native.gb_polarizations(src_all, -g.out_start, g.n_h, g.dt)
+    batch, tuned = autotune.tuned_batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order,
+                                        sc.generation, "AET", hp_t.view(-1), hc_t.view(-1),
+                                        src_all[:, 6:8].contiguous())
+    del hp_t, hc_t
+    log("sampler: tuned group %d, grid x%.1f" % (tuned["group"], tuned["grid_scale"]))
     t_w = torch.tensor(g.waveform_times(), dtype=torch.float64, device=dev)
     # noise-free data: the injection through the same batch machinery
     from paper_2204_06633_amd import waveform
@@ -335,6 +342,7 @@ def bench_sampler(steps, log):
     ms = (time.perf_counter() - t0) / steps * 1e3
     evals = 2 * sc.m
     return {"workload": sc.name, "temperatures": sc.T, "walkers_per_temperature": sc.W,
+            "group": tuned["group"], "grid_scale": tuned["grid_scale"],
             "time_samples": g.n_out, "ms_per_step": ms, "steps": steps,
             "likelihood_evals_per_s": evals / (ms * 1e-3),
             "value": evals * 6.0 * g.n_out / (ms * 1e-3),
