@@ -105,15 +105,33 @@ class PTSampler:
     def __init__(self, loglike, betas, lo, hi, a=2.0):
         self.loglike = loglike
         self.betas = torch.as_tensor(betas, dtype=torch.float64)
+        if self.betas.dim() != 1 or len(self.betas) < 1:
+            raise ValueError("betas must be a non-empty list")
+        if not bool((self.betas[:-1] >= self.betas[1:]).all()) or float(self.betas[0]) > 1.0 \
+                or float(self.betas[-1]) < 0.0:
+            raise ValueError("betas must fall from at most 1 to at least 0")
+        if len(lo) != len(hi) or any(l >= h for l, h in zip(lo, hi)):
+            raise ValueError("prior box: lo < hi in every dimension")
         self.lo, self.hi, self.a = lo, hi, a
 
+    def _check(self, x):
+        T, W, D = x.shape
+        if T != len(self.betas):
+            raise ValueError("%d temperatures in the state, %d betas" % (T, len(self.betas)))
+        if W < 4 or W % 2:
+            raise ValueError("walkers per temperature must be even and at least 4, got %d" % W)
+        if D != len(self.lo):
+            raise ValueError("%d parameters in the state, %d in the prior box" % (D, len(self.lo)))
+
     def initial(self, x):
+        self._check(x)
         T, W, D = x.shape
         lp = log_prior(x, self.lo, self.hi)
         ll = self.loglike(x.reshape(T * W, D)).reshape(T, W)
         return x.clone(), ll, lp
 
     def step(self, x, ll, lp, d: StepDraws):
+        self._check(x)
         T, W, D = x.shape
         h = W // 2
         betas = self.betas.to(x.device)

@@ -116,3 +116,16 @@ def test_prior_box_and_parameter_maps():
     assert torch.allclose(sampler.to_source(th), src, rtol=1e-14, atol=0)
     assert float(sampler.log_prior(th, lo, hi)) == 0.0
     assert float(sampler.log_prior(th + torch.tensor([0, 20.0, 0, 0, 0, 0, 0, 0]), lo, hi)) == -math.inf
+
+
+def test_sampler_argument_checks():
+    ll = lambda th: -0.5 * (th ** 2).sum(-1)
+    with pytest.raises(ValueError):
+        sampler.PTSampler(ll, [0.5, 1.0], [-1.0], [1.0])           # betas must fall
+    with pytest.raises(ValueError):
+        sampler.PTSampler(ll, [1.0], [1.0], [-1.0])                 # empty box
+    ps = sampler.PTSampler(ll, [1.0, 0.5], [-1.0], [1.0])
+    with pytest.raises(ValueError):
+        ps.initial(torch.zeros((2, 5, 1), dtype=torch.float64))     # odd walker count
+    with pytest.raises(ValueError):
+        ps.initial(torch.zeros((3, 4, 1), dtype=torch.float64))     # 3 temperatures, 2 betas
