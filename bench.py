@@ -288,61 +288,24 @@ def bench_sampler(steps, log):
     tempered stretch-move steps whose proposals are scored by
     lr_gb_polarizations, lr_response and lr_fd_loglike, 100 walkers per
     call."""
-    import numpy as np
     import torch
 
-    from paper_2204_06633_amd import inputs, native, sampler, workloads
-    dev = torch.device("cuda:0")
+    from paper_2204_06633_amd import sampler, workloads
     sc = workloads.sampler_case()
-    g = sc.grid
-    log("sampler: %s, %d proposals per half step" % (sc.name, sc.m))
-    orb = native.Orbits.from_samples(sc.orbits, device=dev)
-    # group and grid tuned on the walkers' batch (all slots at the injection)
-    from paper_2204_06633_amd import autotune
-    src_all = torch.tensor(sc.injection, dtype=torch.float64, device=dev).repeat(sc.m, 1)
-    hp_t, hc_t = native.gb_polarizations(src_all, -g.out_start, g.n_h, g.dt)
-    batch, tuned = autotune.tuned_batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order,
-                                        sc.generation, "AET", hp_t.view(-1), hc_t.view(-1),
-                                        src_all[:, 6:8].contiguous())
-    del hp_t, hc_t
-    log("sampler: tuned group %d, grid x%.1f" % (tuned["group"], tuned["grid_scale"]))
-    t_w = torch.tensor(g.waveform_times(), dtype=torch.float64, device=dev)
-    # noise-free data: the injection through the same batch machinery
-    from paper_2204_06633_amd import waveform
-    inj = torch.tensor(sc.injection, dtype=torch.float64, device=dev)
-    one = native.Batch(sc.layout(1), orb, orb, g.t_start, g.dt, sc.order, sc.generation, "AET",
-                       group=1, device=dev)
-    hp, hc = waveform.gb_polarizations(inj[None], t_w)
-    data = torch.empty(one.out_extent, dtype=torch.float64, device=dev)
-    one.response(hp.reshape(-1).contiguous(), hc.reshape(-1).contiguous(),
-                 inj[6:8].reshape(1, 2).contiguous(), out=data)
-    n_fft = native.fd_length(g.n_out)
-    w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
-    plan = native.FdPlan(data.view(3, g.n_out), torch.tensor(w_ae, device=dev),
-                         torch.tensor(w_t, device=dev), g.dt, max_batch=sc.m)
-    del one, hp, hc
-    lo, hi = sampler.prior_box(sc.injection[0], sc.injection[1])
-    betas = [1.0, 0.25, 0.0625, 0.0]
-    ps = sampler.PTSampler(sampler.BatchLoglike(batch, plan, -g.out_start, g.n_h, g.dt, sc.m),
-                           betas, lo, hi)
-    rng = np.random.default_rng(9)
-    th0 = sampler.to_theta(inj.cpu()).numpy()
-    scale = np.array([1e-2, 1e-7, 1e-17, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
-    x, ll, lp = ps.initial(torch.tensor(th0 + scale * rng.standard_normal((sc.T, sc.W, 8)),
-                                        device=dev))
-    gen = torch.Generator(device=dev).manual_seed(3)
-    x, ll, lp, _, _ = ps.step(x, ll, lp, sampler.draw(gen, sc.T, sc.W, device=dev))   # warm-up
+    run = sampler.setup_run(sc, device="cuda:0", log=log)
+    run.step()                                                         # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    acc_tot = torch.zeros(sc.T, dtype=torch.int64, device=dev)
+    acc_tot = torch.zeros(sc.T, dtype=torch.int64, device="cuda:0")
     for _ in range(steps):
-        x, ll, lp, acc, _ = ps.step(x, ll, lp, sampler.draw(gen, sc.T, sc.W, device=dev))
+        acc, _ = run.step()
         acc_tot += acc
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     evals = 2 * sc.m
+    g = sc.grid
     return {"workload": sc.name, "temperatures": sc.T, "walkers_per_temperature": sc.W,
-            "group": tuned["group"], "grid_scale": tuned["grid_scale"],
+            "group": run.tuned["group"], "grid_scale": run.tuned["grid_scale"],
             "time_samples": g.n_out, "ms_per_step": ms, "steps": steps,
             "likelihood_evals_per_s": evals / (ms * 1e-3),
             "value": evals * 6.0 * g.n_out / (ms * 1e-3),

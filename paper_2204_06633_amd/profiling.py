@@ -56,9 +56,17 @@ def main(argv=None):
     if args.what == "fd":
         return run_fd(args, dev)
     if args.what == "sampler":
-        import bench
-        r = bench.bench_sampler(args.reps, lambda msg: print(msg, flush=True))
-        print("sampler: %.1f ms per step" % r["ms_per_step"], flush=True)
+        import time as _time
+
+        from . import sampler
+        run = sampler.setup_run(workloads.sampler_case(), device=dev,
+                                log=lambda msg: print(msg, flush=True))
+        for r in range(args.reps + 1):
+            t0 = _time.perf_counter()
+            run.step()
+            torch.cuda.synchronize()
+            print("sampler step %d: %.1f ms per step" % (r, (_time.perf_counter() - t0) * 1e3),
+                  flush=True)
         return
     case = workloads.config_c2("XYZAET")
     g = case.grid

@@ -203,3 +203,68 @@ class BatchLoglike:
             self.plan.loglike(h, want_grad=False, stats=self.stats)
             out.append(-0.5 * self.stats[:, 0].clone())
         return torch.cat(out)
+
+
+@dataclasses.dataclass
+class PTRun:
+    """A ready tempered run on the device: sampler, state and random source."""
+    case: object
+    sampler: PTSampler
+    x: torch.Tensor
+    ll: torch.Tensor
+    lp: torch.Tensor
+    gen: torch.Generator
+    tuned: dict
+
+    def step(self):
+        d = draw(self.gen, self.case.T, self.case.W, device=self.x.device)
+        self.x, self.ll, self.lp, acc, sw = self.sampler.step(self.x, self.ll, self.lp, d)
+        return acc, sw
+
+
+def setup_run(sc, device="cuda", betas=(1.0, 0.25, 0.0625, 0.0), seed=9, tune=True, log=None):
+    """Everything a tempered run on a ``workloads.SamplerCase`` needs: the
+    orbits on the device, a batch of T W / 2 walkers (group and grid tuned on
+    the batch when ``tune``), noise-free data from the injection, the
+    frequency-domain plan with the stand-in noise curve, the Table I prior
+    box around the injection, and walkers started in a small ball around it
+    (the initial likelihoods evaluated)."""
+    import numpy as np
+
+    from . import autotune, inputs, native
+    dev = torch.device(device)
+    g = sc.grid
+    orb = native.Orbits.from_samples(sc.orbits, device=dev)
+    src_all = torch.tensor(sc.injection, dtype=torch.float64, device=dev).repeat(sc.m, 1)
+    hp, hc = native.gb_polarizations(src_all, -g.out_start, g.n_h, g.dt)
+    if tune:
+        batch, tuned = autotune.tuned_batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt,
+                                            sc.order, sc.generation, "AET", hp.view(-1),
+                                            hc.view(-1), src_all[:, 6:8].contiguous())
+    else:
+        batch = native.Batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order,
+                             sc.generation, "AET", group=2, device=dev)
+        tuned = {"group": 2, "grid_scale": 1.0}
+    if log:
+        log("sampler: %s, %d proposals per half step, group %d, grid x%.1f"
+            % (sc.name, sc.m, tuned["group"], tuned["grid_scale"]))
+    # noise-free data: the injection through the same batch machinery
+    one = native.Batch(sc.layout(1), orb, orb, g.t_start, g.dt, sc.order, sc.generation, "AET",
+                       group=1, device=dev)
+    data = torch.empty(one.out_extent, dtype=torch.float64, device=dev)
+    one.response(hp[0].contiguous(), hc[0].contiguous(), src_all[:1, 6:8].contiguous(), out=data)
+    del hp, hc, one
+    n_fft = native.fd_length(g.n_out)
+    w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
+    plan = native.FdPlan(data.view(3, g.n_out), torch.tensor(w_ae, device=dev),
+                         torch.tensor(w_t, device=dev), g.dt, max_batch=sc.m)
+    lo, hi = prior_box(sc.injection[0], sc.injection[1])
+    ps = PTSampler(BatchLoglike(batch, plan, -g.out_start, g.n_h, g.dt, sc.m, device=dev),
+                   list(betas), lo, hi)
+    rng = np.random.default_rng(seed)
+    th0 = to_theta(torch.tensor(sc.injection)).numpy()
+    scale = np.array([1e-2, 1e-7, 1e-17, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
+    x, ll, lp = ps.initial(torch.tensor(th0 + scale * rng.standard_normal((sc.T, sc.W, 8)),
+                                        device=dev))
+    gen = torch.Generator(device=dev).manual_seed(seed + 1)
+    return PTRun(sc, ps, x, ll, lp, gen, tuned)
