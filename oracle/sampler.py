@@ -20,7 +20,6 @@ from __future__ import annotations
 
 import math
 
-import numpy as np
 
 
 def log_prior_box(theta, lo, hi):

@@ -1,7 +1,6 @@
 """The cost model's TDI shape (terms, delay groups, links per delay) against
 the oracle's term lists, and the bench's traffic-record bookkeeping."""
 import json
-import os
 from collections import Counter
 
 import pytest

@@ -6,7 +6,6 @@ Bars: identical accept and swap decisions (every decision's margin
 |log u - log r| is checked to exceed 1e-6, so rounding cannot flip one);
 log-likelihoods relative 1e-9; positions relative 1e-13 (the same
 arithmetic on both sides, up to fused multiply-adds)."""
-import math
 
 import numpy as np
 import pytest
