@@ -164,7 +164,7 @@ def bench_batched_forward(steps, warmup, log):
 
     from paper_2204_06633_amd import autotune, costs, native, response, workloads
     dev = torch.device("cuda:0")
-    bc = workloads.config_c3()
+    bc = workloads.uneven_batch_case()
     log("batched forward: %s, %d templates, %d samples" % (bc.name, len(bc.grids), bc.n_samples))
     orb = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     hp, hc = workloads.device_polarizations(bc, dev)
@@ -226,7 +226,7 @@ def bench_batched_fwd_adjoint(steps, warmup, log):
 
     from paper_2204_06633_amd import autotune, costs, native, workloads
     dev = torch.device("cuda:0")
-    bc = workloads.config_c5()
+    bc = workloads.walker_batch_case()
     log("batched fwd+adjoint: %s, %d walkers, %d samples" % (bc.name, len(bc.grids),
                                                             bc.n_samples))
     orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
@@ -336,7 +336,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    case = workloads.config_c2("XYZAET")
+    case = workloads.year_case("XYZAET")
     g = case.grid
     print("bench: workload %s, n_out=%d, n_h=%d" % (case.name, g.n_out, g.n_h), file=sys.stderr,
           flush=True)
@@ -520,7 +520,7 @@ def main():
     f_proj = costs.projection_flops_per_sample(case.order) * g.n_y
     b_tdi = costs.tdi_bytes_per_sample(case.channels) * n
     b_proj = costs.projection_bytes_per_sample() * g.n_y
-    traffic = recorded_traffic("tdi", "c2")
+    traffic = recorded_traffic("tdi", "1yr")
     result = {
         "metric": METRIC,
         "value": value,

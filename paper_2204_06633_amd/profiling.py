@@ -70,7 +70,7 @@ def main(argv=None):
             print("sampler step %d: %.1f ms per step" % (r, (_time.perf_counter() - t0) * 1e3),
                   flush=True)
         return
-    case = workloads.config_c2("XYZAET")
+    case = workloads.year_case("XYZAET")
     g = case.grid
     orb = native.Orbits.from_samples(case.orbits_proj, device=dev)
     tpl = response.Template(orb, orb, g, case.order, case.generation, case.channels)
@@ -93,7 +93,7 @@ def run_batch(args, dev):
 
     from . import native, workloads
     adj = args.what == "batch-adjoint"
-    full = workloads.config_c5(args.templates) if adj else workloads.config_c3()
+    full = workloads.walker_batch_case(args.templates) if adj else workloads.uneven_batch_case()
     bc = full
     if not adj:
         k = args.templates

@@ -57,13 +57,13 @@ def make_case(name, orbit_kind, n_out, dt, order, generation, channels, seed, t_
 # The benchmark configurations (single template): a day of a monochromatic
 # source on rigid equal-arm orbits with TDI-1, and a year of a chirping
 # source on flexing Keplerian orbits with TDI-2.
-def config_c1():
-    return make_case("c1_day_rigid_tdi1", "rigid", 8640, 10.0, 25, 1, "XYZ", seed=1,
+def day_case():
+    return make_case("day8640_rigid_tdi1", "rigid", 8640, 10.0, 25, 1, "XYZ", seed=1,
                      monochromatic=True)
 
 
-def config_c2(channels="XYZAET"):
-    return make_case("c2_year_keplerian_tdi2", "keplerian", int(round(inputs.YEAR / 10.0)), 10.0,
+def year_case(channels="XYZAET"):
+    return make_case("year_keplerian_tdi2", "keplerian", int(round(inputs.YEAR / 10.0)), 10.0,
                      25, 2, channels, seed=2)
 
 
@@ -159,18 +159,18 @@ def make_batch_case(name, n_out_list, dt, order, generation, channels, seed, par
                      generation, channels)
 
 
-def config_c3(n_templates=512, seed=3):
+def uneven_batch_case(n_templates=512, seed=3):
     """512 Galactic binaries of uneven durations (uniform 0.25-1 yr at
     dt = 10 s), independent seeded parameters, flexing Keplerian orbits,
     TDI-2 A/E/T, order 25."""
     rng = np.random.default_rng(seed)
     full = int(round(inputs.YEAR / 10.0))
     n_out = np.round(rng.uniform(0.25, 1.0, n_templates) * full).astype(np.int64)
-    return make_batch_case("c3_batch%d_uneven_keplerian_tdi2" % n_templates, list(n_out), 10.0,
+    return make_batch_case("batch%d_uneven_keplerian_tdi2" % n_templates, list(n_out), 10.0,
                            25, 2, "AET", seed)
 
 
-def config_c5(n_walkers=256, seed=5, spread=1e-6):
+def walker_batch_case(n_walkers=256, seed=5, spread=1e-6):
     """MCMC walkers around one Galactic binary: 1 yr at dt = 15 s each,
     Keplerian orbits for the projection and rigid equal-arm orbits for the
     TDI-2 delays (hybrid template), A/E/T, order 25.  Walker parameters are
@@ -182,7 +182,7 @@ def config_c5(n_walkers=256, seed=5, spread=1e-6):
     params[:, :3] *= 1.0 + spread * rng.standard_normal((n_walkers, 3))
     params[:, 3:] += spread * rng.standard_normal((n_walkers, 5))
     n = int(round(inputs.YEAR / 15.0))
-    return make_batch_case("c5_walkers%d_hybrid_dt15" % n_walkers, [n] * n_walkers, 15.0, 25, 2,
+    return make_batch_case("walkers%d_hybrid_dt15" % n_walkers, [n] * n_walkers, 15.0, 25, 2,
                            "AET", seed, params=params, tdi_orbit_kind="rigid")
 
 

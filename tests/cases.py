@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2204_06633_amd.workloads import Case, config_c1, config_c2, make_case  # noqa: F401
+from paper_2204_06633_amd.workloads import Case, day_case, make_case, year_case  # noqa: F401
 
 
 def sample_indices(n, k, seed, edge=8):

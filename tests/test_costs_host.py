@@ -32,11 +32,11 @@ def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.recorded_traffic("tdi", "c2") is None               # no record
+    assert bench.recorded_traffic("tdi", "1yr") is None               # no record
     rec = {"bytes_per_launch": 123.0, "source_hash": "not-the-sources"}
-    (prof / "traffic_tdi_c2.json").write_text(json.dumps(rec))
+    (prof / "traffic_tdi_1yr.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "the-sources")
-    assert bench.recorded_traffic("tdi", "c2") is None               # stale record
+    assert bench.recorded_traffic("tdi", "1yr") is None               # stale record
     rec["source_hash"] = "the-sources"
-    (prof / "traffic_tdi_c2.json").write_text(json.dumps(rec))
-    assert bench.recorded_traffic("tdi", "c2") == 123.0
+    (prof / "traffic_tdi_1yr.json").write_text(json.dumps(rec))
+    assert bench.recorded_traffic("tdi", "1yr") == 123.0

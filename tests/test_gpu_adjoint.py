@@ -112,7 +112,7 @@ def test_dot_product_full_year(torch_cuda):
     """<R h, g> = <h, R^T g> at the full 1-yr size (any-size property)."""
     from paper_2204_06633_amd import response
     torch = torch_cuda
-    case = cases.config_c2("XYZAET")
+    case = cases.year_case("XYZAET")
     tpl = _template(case)
     hp, hc = _t(torch, case.hp), _t(torch, case.hc)
     sky = _t(torch, [case.lam, case.beta])
@@ -163,7 +163,7 @@ SIGMA = 1e-21
 
 def _likelihood_case(n_out, dt=10.0):
     params = np.array(inputs.PAPER_FIG3_BINARY, dtype=np.float64)
-    case = cases.make_case("c4", "keplerian", n_out, dt, 25, 2, "AET", seed=4, params=params)
+    case = cases.make_case("likelihood_keplerian", "keplerian", n_out, dt, 25, 2, "AET", seed=4, params=params)
     orb = oracle.Orbits.from_samples(case.orbits_proj)
     inj = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta, 25, 2, "AET")
     noise = np.random.default_rng(40).standard_normal(inj.shape) * SIGMA
@@ -239,7 +239,7 @@ def test_loglike_gradient_full_year_self_consistent(torch_cuda):
     torch = torch_cuda
     n_out = int(round(inputs.YEAR / 10.0))
     params = np.array(inputs.PAPER_FIG3_BINARY, dtype=np.float64)
-    case = cases.make_case("c4_year", "keplerian", n_out, 10.0, 25, 2, "AET", seed=4,
+    case = cases.make_case("likelihood_year", "keplerian", n_out, 10.0, 25, 2, "AET", seed=4,
                            params=params)
     tpl = _template(case)
     t = _t(torch, case.grid.waveform_times())

@@ -94,9 +94,9 @@ def _gpu_response(torch, case):
     return out.cpu().numpy()
 
 
-def test_response_c1_full(torch_cuda):
+def test_response_day_full(torch_cuda):
     """One day of a monochromatic source, rigid equal-arm orbits, TDI-1 XYZ."""
-    case = cases.config_c1()
+    case = cases.day_case()
     got = _gpu_response(torch_cuda, case)
     orb = oracle.Orbits.from_samples(case.orbits_proj)
     ref = oracle.response(orb, orb, case.grid, case.hp, case.hc, case.lam, case.beta,
@@ -104,11 +104,11 @@ def test_response_c1_full(torch_cuda):
     assert cases.rel_err(got, ref) <= TOL
 
 
-def test_response_c2_sampled(torch_cuda):
+def test_response_year_sampled(torch_cuda):
     """One year at 10 s of a chirping source on flexing Keplerian orbits,
     TDI-2 X/Y/Z and A/E/T, compared on sampled outputs (the oracle computes
     each sampled output on its own)."""
-    case = cases.config_c2("XYZAET")
+    case = cases.year_case("XYZAET")
     got = _gpu_response(torch_cuda, case)
     idx = cases.sample_indices(case.grid.n_out, 400, seed=22)
     orb = oracle.Orbits.from_samples(case.orbits_proj)

@@ -24,7 +24,7 @@ def test_uneven_batch_512_sampled(torch_cuda):
     torch = torch_cuda
     from paper_2204_06633_amd import autotune, native
     dev = torch.device("cuda:0")
-    bc = workloads.config_c3()
+    bc = workloads.uneven_batch_case()
     orb = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     hp, hc = workloads.device_polarizations(bc, dev)
     sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
@@ -41,7 +41,7 @@ def test_uneven_batch_512_sampled(torch_cuda):
     for k in picks:
         g = bc.grids[k]
         ho = bc.layout.h_offsets[k]
-        case = workloads.Case("c3_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
+        case = workloads.Case("uneven_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
                               hp[ho:ho + g.n_h].cpu().numpy(), hc[ho:ho + g.n_h].cpu().numpy(),
                               bc.order, bc.generation, bc.channels)
         idx = cases.sample_indices(g.n_out, 40, seed=k, edge=3)
@@ -56,7 +56,7 @@ def test_walkers_256_dot_product(torch_cuda):
     torch = torch_cuda
     from paper_2204_06633_amd import native
     dev = torch.device("cuda:0")
-    bc = workloads.config_c5()
+    bc = workloads.walker_batch_case()
     orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     orb_t = native.Orbits.from_samples(bc.orbits_tdi, device=dev)
     sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()

@@ -317,7 +317,7 @@ def test_source_along_an_arm_is_regular():
 # ---------------------------------------------------------------------------
 # P4: monochromatic source, closed form of the whole response.
 #   * static equal-arm constellation, any sky;
-#   * rigid rotating constellation for the projection (C1 orbits), equal
+#   * rigid rotating constellation for the projection (the one-day rigid case), equal
 #     constant delays for TDI (the hybrid template of Sec. V).
 # y_ij(t) is evaluated analytically from exact orbits and h, and X1, X2 from
 # the equal-arm factorisations; the oracle must match to rounding.
