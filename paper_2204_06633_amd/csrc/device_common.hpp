@@ -195,32 +195,98 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N], dou
   }
 }
 
-// Streaming Lagrange interpolation, without materialising the weights:
-//   I = sum_m c_m P_m S_m f_m,  P_m = prod_{j<m}(eps - x_j), S_m = prod_{j>m}(eps - x_j),
-// evaluated by the recurrence T_k = T_{k-1} (eps - x_k) + c_k P_k f_k (so that
-// T_{N-1} = I) with P_{k+1} = P_k (eps - x_k).  Per tap: 3 FP64 ops shared by
-// all series on the stencil (c_k P_k with c_k from an SGPR, the product
-// update, and eps - x_k by an inline-constant subtraction) plus 2 per series,
-// and O(1) registers.  Usage per tap k = 0, 1, ...: tap(k), then for every
-// series x = step(x, f_k, k); the interpolant is finish(x).
+// Streaming Lagrange interpolation, without materialising the weights.
+// With d_k = eps - x_k the interpolant is I = sum_j c_j f_j prod_{i != j} d_i.
+// Rescaled factors nu_k = s_k d_k, s_k = K / c_k, turn every weight into a
+// pure product: prod_{i != j} nu_i = (K^(N-1) prod_i 1/c_i) c_j prod_{i != j} d_i.
+// So with R_0 = 1, R_{k+1} = R_k nu_k and the recurrence
+//   T_0 = f_0,   T_k = T_{k-1} nu_k + R_k f_k,
+// T_{N-1} = I / kScale, kScale = K prod_i (c_i / K).  K is a power of two
+// near the geometric mean of the |1/c_i|, which keeps every partial product
+// within ~1e+-20 for N <= 32.
+template <int N>
+struct LagrangeScaled {
+  double s[N];      // s_k = K / c_k = K prod_{j != k} (x_k - x_j)
+  double scale;     // kScale
+};
+
+template <int N>
+constexpr LagrangeScaled<N> make_scaled() {
+  LagrangeScaled<N> r{};
+  double p[N] = {};
+  int esum = 0;
+  for (int m = 0; m < N; ++m) {
+    p[m] = 1.0;
+    for (int j = 0; j < N; ++j)
+      if (j != m) p[m] *= (double)(m - j);
+    double v = p[m] < 0.0 ? -p[m] : p[m];
+    while (v >= 2.0) { v *= 0.5; ++esum; }
+  }
+  const int e = (esum + N / 2) / N;
+  double K = 1.0;
+  for (int i = 0; i < e; ++i) K *= 0.5;
+  double scale = K;
+  for (int m = 0; m < N; ++m) {
+    r.s[m] = K * p[m];
+    scale /= r.s[m];
+  }
+  r.scale = scale;
+  return r;
+}
+
+// One sample.  Per tap: 3 FP64 ops shared by all series on the stencil (the
+// product update, eps - x_k by an inline-constant subtraction, nu_k with s_k
+// from an SGPR) plus 2 per series, in O(1) registers.  Usage per tap
+// k = 0, 1, ...: tap(k), then for every series x = step(x, f_k, k); the
+// interpolant is finish(x).
 template <int N>
 struct LagrangeStream {
-  static constexpr double kScale = 1.0;   // finish() multiplier
-  double d, P, c;
+  static constexpr double kScale = make_scaled<N>().scale;   // finish() multiplier
+  double d, R, nu;
   __device__ __forceinline__ explicit LagrangeStream(double eps)
-      : d(eps + (double)(N / 2 - 1)), P(1.0), c(0.0) {}
+      : d(eps + (double)(N / 2 - 1)), R(1.0), nu(0.0) {}
   __device__ __forceinline__ void tap(int k) {
-    constexpr LagrangeDenoms<N> C = make_denoms<N>();
+    constexpr LagrangeScaled<N> S = make_scaled<N>();
     if (k > 0) {
-      P *= d;
+      R *= nu;
       d -= 1.0;
     }
-    c = C.c[k] * P;
+    nu = S.s[k] * d;
   }
   __device__ __forceinline__ double step(double x, double f, int k) const {
-    return k == 0 ? c * f : fma(c, f, x * d);
+    return k == 0 ? f : fma(R, f, x * nu);
   }
   __device__ __forceinline__ static double finish(double x) { return x * kScale; }
+};
+
+// Two samples a and b of one lane, stepped through the same tap index k
+// (their stencils may start at different window positions).  Sample b's
+// factor comes from sample a's by one FMA, nu_b = nu_a + s_k (eps_b - eps_a),
+// whose only scalar operand is s_k; a VOP3 reads at most one, so computing
+// s_k (eps_b - x_k) afresh would cost a subtraction and a multiply.  Per tap
+// the pair shares 5 FP64 ops (6 for two LagrangeStreams) plus 2 per series.
+// Same scale as LagrangeStream: finish() with LagrangeStream<N>::finish.
+template <int N>
+struct LagrangePair {
+  double d, de, Ra, Rb, na, nb;
+  __device__ __forceinline__ LagrangePair(double ea, double eb)
+      : d(ea + (double)(N / 2 - 1)), de(eb - ea), Ra(1.0), Rb(1.0), na(0.0), nb(0.0) {}
+  __device__ __forceinline__ void tap(int k) {
+    constexpr LagrangeScaled<N> S = make_scaled<N>();
+    if (k > 0) {
+      Ra *= na;
+      Rb *= nb;
+      d -= 1.0;
+    }
+    na = S.s[k] * d;
+    nb = fma(de, S.s[k], na);
+  }
+  __device__ __forceinline__ double step_a(double x, double f, int k) const {
+    return k == 0 ? f : fma(Ra, f, x * na);
+  }
+  __device__ __forceinline__ double step_b(double x, double f, int k) const {
+    return k == 0 ? f : fma(Rb, f, x * nb);
+  }
 };
 
 // LagrangeStream with the derivative with respect to eps carried along:

@@ -189,13 +189,14 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
-      LagrangeStream<N> sa(A.ep[p]), sb(B.ep[p]);
+      LagrangePair<N> st(A.ep[p], B.ep[p]);
       const ParStream<CAP> src(ra + A.sh[p] - (H - 1) - wlo);
       double pa = 0.0, ca = 0.0, pb = 0.0, cb = 0.0;
       if (__all(A.sh[p] == B.sh[p])) {
         // sample b's stencil is sample a's shifted by one: N + 1 loads feed both
+        double2 cur = win[src.at(0)];
 #pragma unroll
-        for (int k = 0; k <= N; ++k) {
+        for (int k = 0; k < N; ++k) {
           if (LR_PROJ_PIPE > 0) {
             // at most LR_PROJ_PIPE window loads in flight: bounds the registers
             // the scheduler spends on early loads
@@ -203,17 +204,13 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
             if (k + LR_PROJ_PIPE <= N) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
           }
-          const double2 v = win[src.at(k)];
-          if (k < N) {
-            sa.tap(k);
-            pa = sa.step(pa, v.x, k);
-            ca = sa.step(ca, v.y, k);
-          }
-          if (k > 0) {
-            sb.tap(k - 1);
-            pb = sb.step(pb, v.x, k - 1);
-            cb = sb.step(cb, v.y, k - 1);
-          }
+          const double2 nxt = win[src.at(k + 1)];
+          st.tap(k);
+          pa = st.step_a(pa, cur.x, k);
+          ca = st.step_a(ca, cur.y, k);
+          pb = st.step_b(pb, nxt.x, k);
+          cb = st.step_b(cb, nxt.y, k);
+          cur = nxt;
         }
       } else {
         const ParStream<CAP> srb(ra + 1 + B.sh[p] - (H - 1) - wlo);
@@ -225,12 +222,11 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
             __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);
           }
           const double2 v = win[src.at(k)], w = win[srb.at(k)];
-          sa.tap(k);
-          sb.tap(k);
-          pa = sa.step(pa, v.x, k);
-          ca = sa.step(ca, v.y, k);
-          pb = sb.step(pb, w.x, k);
-          cb = sb.step(cb, w.y, k);
+          st.tap(k);
+          pa = st.step_a(pa, v.x, k);
+          ca = st.step_a(ca, v.y, k);
+          pb = st.step_b(pb, w.x, k);
+          cb = st.step_b(cb, w.y, k);
         }
       }
       add_position(p, A.xip, A.xic, pa, ca, na);
@@ -245,21 +241,20 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
     const ProjSample Ac = A, Bc = B;
 #pragma unroll 1
     for (int p = 0; p < 9; ++p) {
-      LagrangeStream<N> sa(Ac.ep[p]), sb(Bc.ep[p]);
+      LagrangePair<N> st(Ac.ep[p], Bc.ep[p]);
       const int64_t ja = qa + Ac.sh[p] - (H - 1), jb = qa + 1 + Bc.sh[p] - (H - 1);
       double pa = 0.0, ca = 0.0, pb = 0.0, cb = 0.0;
 #pragma unroll 1
       for (int m = 0; m < N; ++m) {
         int64_t j = ja + m;
         j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        sa.tap(m);
-        pa = sa.step(pa, hp[j], m);
-        ca = sa.step(ca, hc[j], m);
-        j = jb + m;
-        j = j < 0 ? 0 : (j > hmax ? hmax : j);
-        sb.tap(m);
-        pb = sb.step(pb, hp[j], m);
-        cb = sb.step(cb, hc[j], m);
+        int64_t jj = jb + m;
+        jj = jj < 0 ? 0 : (jj > hmax ? hmax : jj);
+        st.tap(m);
+        pa = st.step_a(pa, hp[j], m);
+        ca = st.step_a(ca, hc[j], m);
+        pb = st.step_b(pb, hp[jj], m);
+        cb = st.step_b(cb, hc[jj], m);
       }
       add_position_rt(p, A.xip, A.xic, pa, ca, na);
       add_position_rt(p, B.xip, B.xic, pb, cb, nb);
@@ -409,44 +404,43 @@ __device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int cha
 // S series (measured links, possibly of several templates) that share one
 // delay, for both samples of a lane, from parity-split LDS rows w[s]: sa_
 // starts sample a's stencil; if `same`, sample b's stencil is the next
-// window position, otherwise it starts at element jb0.  One product chain per
-// sample serves all S series.  Returns the streams' unscaled values
+// window position, otherwise it starts at element jb0.  One LagrangePair
+// serves all S series of both samples.  Returns the streams' unscaled values
 // (LagrangeStream<N>::finish scales).
 template <int N, int CAP, int S>
 __device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
                                              const double* const (&w)[S],
                                              const ParStream<CAP>& sa_, int jb0,
                                              double (&xa)[S], double (&xb)[S]) {
-  LagrangeStream<N> A(ea), B(eb);
+  LagrangePair<N> P(ea, eb);
 #pragma unroll
   for (int s = 0; s < S; ++s) { xa[s] = 0.0; xb[s] = 0.0; }
   if (same) {
+    double cur[S];
 #pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      double v[S];
+    for (int s = 0; s < S; ++s) cur[s] = w[s][sa_.at(0)];
 #pragma unroll
-      for (int s = 0; s < S; ++s) v[s] = w[s][sa_.at(k)];
-      if (k < N) {
-        A.tap(k);
+    for (int k = 0; k < N; ++k) {
+      double nxt[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) xa[s] = A.step(xa[s], v[s], k);
-      }
-      if (k > 0) {
-        B.tap(k - 1);
+      for (int s = 0; s < S; ++s) nxt[s] = w[s][sa_.at(k + 1)];
+      P.tap(k);
 #pragma unroll
-        for (int s = 0; s < S; ++s) xb[s] = B.step(xb[s], v[s], k - 1);
+      for (int s = 0; s < S; ++s) {
+        xa[s] = P.step_a(xa[s], cur[s], k);
+        xb[s] = P.step_b(xb[s], nxt[s], k);
+        cur[s] = nxt[s];
       }
     }
   } else {
     const ParStream<CAP> sb_(jb0);             // only here: most waves take `same`
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      A.tap(k);
-      B.tap(k);
+      P.tap(k);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        xa[s] = A.step(xa[s], w[s][sa_.at(k)], k);
-        xb[s] = B.step(xb[s], w[s][sb_.at(k)], k);
+        xa[s] = P.step_a(xa[s], w[s][sa_.at(k)], k);
+        xb[s] = P.step_b(xb[s], w[s][sb_.at(k)], k);
       }
     }
   }
