@@ -341,11 +341,18 @@ struct TdiTab {
 
 // Delay groups as a run-time table in constant memory: the kernels loop over
 // groups without unrolling, so only one group's state is live at a time.
+// Rows are ordered by channel: for channel c, rows [first[c], comb[c]) have
+// one use, rows [comb[c], first[c + 1]) two uses of that same channel (their
+// two link series are combined before the interpolation); rows [first[3], n)
+// feed two different channels.  The general fields (nuse, link, sgn) describe
+// every row, for kernels that loop over all rows alike.
 struct GroupRow {
   double cnt[6];       // light-time multiplicities of the group's delay
   int nuse;            // 1 or 2 delayed terms share the delay
   int link[2];         // measured link of each use
   double sgn[2][3];    // signed X, Y, Z selector of each use
+  double sign;         // one-channel rows: sign of use 0
+  double ratio;        // two uses of one channel: sign of use 1 / sign of use 0
 };
 
 template <int GEN>
@@ -353,22 +360,47 @@ struct GroupTable {
   GroupRow row[3 * TdiTable<GEN>::kTermsPerChan];
   int n;
   int chain;           // longest chain of link delays (3 or 7)
+  int first[4];        // see above
+  int comb[3];
 };
 
 template <int GEN>
 constexpr GroupTable<GEN> make_group_table() {
   constexpr TdiTable<GEN> t = make_tdi_table<GEN>();
   GroupTable<GEN> r{};
-  r.n = t.ngroup;
+  r.n = 0;
   r.chain = GEN == 1 ? 3 : 7;
-  for (int g = 0; g < t.ngroup; ++g) {
-    for (int l = 0; l < 6; ++l) r.row[g].cnt[l] = (double)t.group[g].cnt[l];
-    r.row[g].nuse = t.group[g].nuse;
+  auto add = [&r, &t](int g) {
+    GroupRow& row = r.row[r.n++];
+    for (int l = 0; l < 6; ++l) row.cnt[l] = (double)t.group[g].cnt[l];
+    row.nuse = t.group[g].nuse;
     for (int k = 0; k < t.group[g].nuse; ++k) {
-      r.row[g].link[k] = t.group[g].use[k].link;
+      row.link[k] = t.group[g].use[k].link;
       for (int c = 0; c < 3; ++c)
-        r.row[g].sgn[k][c] = t.group[g].use[k].chan == c ? (double)t.group[g].use[k].sign : 0.0;
+        row.sgn[k][c] = t.group[g].use[k].chan == c ? (double)t.group[g].use[k].sign : 0.0;
     }
+    row.sign = (double)t.group[g].use[0].sign;
+    row.ratio = t.group[g].nuse == 2
+                    ? (double)(t.group[g].use[1].sign * t.group[g].use[0].sign) : 0.0;
+  };
+  auto one_chan = [&t](int g, int c) {
+    for (int k = 0; k < t.group[g].nuse; ++k)
+      if (t.group[g].use[k].chan != c) return false;
+    return true;
+  };
+  for (int c = 0; c < 3; ++c) {
+    r.first[c] = r.n;
+    for (int g = 0; g < t.ngroup; ++g)
+      if (t.group[g].nuse == 1 && one_chan(g, c)) add(g);
+    r.comb[c] = r.n;
+    for (int g = 0; g < t.ngroup; ++g)
+      if (t.group[g].nuse == 2 && one_chan(g, c)) add(g);
+  }
+  r.first[3] = r.n;
+  for (int g = 0; g < t.ngroup; ++g) {
+    bool single = false;
+    for (int c = 0; c < 3; ++c) single = single || (t.group[g].nuse <= 2 && one_chan(g, c));
+    if (!single) add(g);
   }
   return r;
 }
@@ -401,29 +433,28 @@ __device__ __forceinline__ void group_delay_bounds(const double (&L)[6], int cha
   dhi = fmax(lmax, chain * lmax);
 }
 
-// S series (measured links, possibly of several templates) that share one
-// delay, for both samples of a lane, from parity-split LDS rows w[s]: sa_
-// starts sample a's stencil; if `same`, sample b's stencil is the next
-// window position, otherwise it starts at element jb0.  One LagrangePair
-// serves all S series of both samples.  Returns the streams' unscaled values
+// S series that share one delay, for both samples of a lane: load(s, i)
+// returns series s at window element i (a parity-split LDS position).  sa_
+// starts sample a's stencil; if `same`, sample b's stencil is the next window
+// position, otherwise it starts at element jb0.  One LagrangePair serves all
+// S series of both samples.  Returns the streams' unscaled values
 // (LagrangeStream<N>::finish scales).
-template <int N, int CAP, int S>
-__device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
-                                             const double* const (&w)[S],
-                                             const ParStream<CAP>& sa_, int jb0,
-                                             double (&xa)[S], double (&xb)[S]) {
+template <int N, int CAP, int S, class Load>
+__device__ __forceinline__ void stream_series(double ea, double eb, bool same, const Load& load,
+                                              const ParStream<CAP>& sa_, int jb0,
+                                              double (&xa)[S], double (&xb)[S]) {
   LagrangePair<N> P(ea, eb);
 #pragma unroll
   for (int s = 0; s < S; ++s) { xa[s] = 0.0; xb[s] = 0.0; }
   if (same) {
     double cur[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) cur[s] = w[s][sa_.at(0)];
+    for (int s = 0; s < S; ++s) cur[s] = load(s, sa_.at(0));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double nxt[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) nxt[s] = w[s][sa_.at(k + 1)];
+      for (int s = 0; s < S; ++s) nxt[s] = load(s, sa_.at(k + 1));
       P.tap(k);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -439,11 +470,22 @@ __device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
       P.tap(k);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        xa[s] = P.step_a(xa[s], w[s][sa_.at(k)], k);
-        xb[s] = P.step_b(xb[s], w[s][sb_.at(k)], k);
+        xa[s] = P.step_a(xa[s], load(s, sa_.at(k)), k);
+        xb[s] = P.step_b(xb[s], load(s, sb_.at(k)), k);
       }
     }
   }
+}
+
+// S series from parity-split LDS rows w[s] (measured links, possibly of
+// several templates).
+template <int N, int CAP, int S>
+__device__ __forceinline__ void stream_multi(double ea, double eb, bool same,
+                                             const double* const (&w)[S],
+                                             const ParStream<CAP>& sa_, int jb0,
+                                             double (&xa)[S], double (&xb)[S]) {
+  stream_series<N, CAP, S>(ea, eb, same, [&w](int s, int i) { return w[s][i]; }, sa_, jb0, xa,
+                           xb);
 }
 
 // Global-memory version for one sample (clamped indices).
@@ -514,8 +556,48 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       for (int l = 0; l < 6; ++l) win[l * CAP + par<CAP>(k)] = a.y[(int64_t)l * a.n_y + j];
     }
     __syncthreads();
+    // rows that feed one channel c: a one-link group adds one stream to
+    // acc[c]; a two-link group of one channel interpolates the signed sum of
+    // its two link series (the same delay, so the same weights)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll 1
-    for (int g = 0; g < GT.n; ++g) {
+      for (int g = GT.first[c]; g < GT.comb[c]; ++g) {
+        const GroupRow& G = GT.row[g];
+        double ea, eb;
+        const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
+        const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
+        const bool same = __all(sa == sb);
+        const ParStream<CAP> pa_(c0 + sa - (H - 1));
+        const double* const w0 = win + G.link[0] * CAP;
+        double xa[1], xb[1];
+        stream_series<N, CAP, 1>(ea, eb, same, [w0](int, int i) { return w0[i]; }, pa_,
+                                 c0 + 1 + sb - (H - 1), xa, xb);
+        acc_a[c] = fma(G.sign, xa[0], acc_a[c]);
+        acc_b[c] = fma(G.sign, xb[0], acc_b[c]);
+      }
+#pragma unroll 1
+      for (int g = GT.comb[c]; g < GT.first[c + 1]; ++g) {
+        const GroupRow& G = GT.row[g];
+        double ea, eb;
+        const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
+        const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
+        const bool same = __all(sa == sb);
+        const ParStream<CAP> pa_(c0 + sa - (H - 1));
+        const double* const w0 = win + G.link[0] * CAP;
+        const double* const w1 = win + G.link[1] * CAP;
+        const double q = G.ratio;
+        double xa[1], xb[1];
+        stream_series<N, CAP, 1>(ea, eb, same,
+                                 [w0, w1, q](int, int i) { return fma(q, w1[i], w0[i]); }, pa_,
+                                 c0 + 1 + sb - (H - 1), xa, xb);
+        acc_a[c] = fma(G.sign, xa[0], acc_a[c]);
+        acc_b[c] = fma(G.sign, xb[0], acc_b[c]);
+      }
+    }
+    // two-link groups whose uses feed different channels
+#pragma unroll 1
+    for (int g = GT.first[3]; g < GT.n; ++g) {
       const GroupRow& G = GT.row[g];
       double ea, eb;
       const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
@@ -523,24 +605,13 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       const bool same = __all(sa == sb);
       const ParStream<CAP> pa_(c0 + sa - (H - 1));
       const int jb0 = c0 + 1 + sb - (H - 1);
-      if (G.nuse == 1) {
-        const double* const w[1] = {win + G.link[0] * CAP};
-        double xa[1], xb[1];
-        stream_multi<N, CAP, 1>(ea, eb, same, w, pa_, jb0, xa, xb);
+      const double* const w[2] = {win + G.link[0] * CAP, win + G.link[1] * CAP};
+      double xa[2], xb[2];
+      stream_multi<N, CAP, 2>(ea, eb, same, w, pa_, jb0, xa, xb);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc_a[c] = fma(G.sgn[0][c], xa[0], acc_a[c]);
-          acc_b[c] = fma(G.sgn[0][c], xb[0], acc_b[c]);
-        }
-      } else {
-        const double* const w[2] = {win + G.link[0] * CAP, win + G.link[1] * CAP};
-        double xa[2], xb[2];
-        stream_multi<N, CAP, 2>(ea, eb, same, w, pa_, jb0, xa, xb);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc_a[c] = fma(G.sgn[0][c], xa[0], fma(G.sgn[1][c], xa[1], acc_a[c]));
-          acc_b[c] = fma(G.sgn[0][c], xb[0], fma(G.sgn[1][c], xb[1], acc_b[c]));
-        }
+      for (int c = 0; c < 3; ++c) {
+        acc_a[c] = fma(G.sgn[0][c], xa[0], fma(G.sgn[1][c], xa[1], acc_a[c]));
+        acc_b[c] = fma(G.sgn[0][c], xb[0], fma(G.sgn[1][c], xb[1], acc_b[c]));
       }
     }
   } else {
