@@ -35,48 +35,89 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[k][s][c] = 0.0;
-#pragma unroll 1
-  for (int g = 0; g < GT.n; ++g) {
-    const GroupRow& G = GT.row[g];
-    double ea, eb;
+  // The padding bound keeps every stored output's stencil inside the tile;
+  // the clamp only guards the idle lanes past a template's end.
+  const int top = YT - 1 - N;
+  auto stencil = [&](const GroupRow& G, double& ea, double& eb, bool& same, int& ja, int& jb) {
     const int sa = split_delay(row_delay(G, La), a.inv_dt, ea);
     const int sb = split_delay(row_delay(G, Lb), a.inv_dt, eb);
-    const bool same = __all(sa == sb);
-    // The padding bound keeps every stored output's stencil inside the tile;
-    // the clamp only guards the idle lanes past a template's end.
-    const int top = YT - 1 - N;
-    const ParStream<YT> pa_(min(max(c0 + sa - (H - 1), 0), top));
-    const int jb0 = min(max(c0 + 1 + sb - (H - 1), 0), top);
-    if (G.nuse == 1) {
+    same = __all(sa == sb);
+    ja = min(max(c0 + sa - (H - 1), 0), top);
+    jb = min(max(c0 + 1 + sb - (H - 1), 0), top);
+  };
+  // rows that feed one channel c (see GroupTable): one FMA per template and
+  // sample; a two-link group of one channel interpolates the signed sum of
+  // its link series
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll 1
+    for (int g = GT.first[c]; g < GT.comb[c]; ++g) {
+      const GroupRow& G = GT.row[g];
+      double ea, eb;
+      bool same;
+      int ja, jb;
+      stencil(G, ea, eb, same, ja, jb);
       const double* w[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) w[k] = ylds + (k * 6 + G.link[0]) * YT;
       double xa[M], xb[M];
-      stream_multi<N, YT, M>(ea, eb, same, w, pa_, jb0, xa, xb);
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc[k][0][c] = fma(G.sgn[0][c], xa[k], acc[k][0][c]);
-          acc[k][1][c] = fma(G.sgn[0][c], xb[k], acc[k][1][c]);
-        }
-    } else {
-      const double* w[2 * M];
+      stream_series<N, YT, M>(ea, eb, same, [&w](int s, int i) { return w[s][i]; },
+                              ParStream<YT>(ja), jb, xa, xb);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        w[2 * k] = ylds + (k * 6 + G.link[0]) * YT;
-        w[2 * k + 1] = ylds + (k * 6 + G.link[1]) * YT;
+        acc[k][0][c] = fma(G.sign, xa[k], acc[k][0][c]);
+        acc[k][1][c] = fma(G.sign, xb[k], acc[k][1][c]);
       }
-      double xa[2 * M], xb[2 * M];
-      stream_multi<N, YT, 2 * M>(ea, eb, same, w, pa_, jb0, xa, xb);
-#pragma unroll
-      for (int k = 0; k < M; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc[k][0][c] = fma(G.sgn[0][c], xa[2 * k], fma(G.sgn[1][c], xa[2 * k + 1], acc[k][0][c]));
-          acc[k][1][c] = fma(G.sgn[0][c], xb[2 * k], fma(G.sgn[1][c], xb[2 * k + 1], acc[k][1][c]));
-        }
     }
+#pragma unroll 1
+    for (int g = GT.comb[c]; g < GT.first[c + 1]; ++g) {
+      const GroupRow& G = GT.row[g];
+      double ea, eb;
+      bool same;
+      int ja, jb;
+      stencil(G, ea, eb, same, ja, jb);
+      const double* w0[M];
+      const double* w1[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        w0[k] = ylds + (k * 6 + G.link[0]) * YT;
+        w1[k] = ylds + (k * 6 + G.link[1]) * YT;
+      }
+      const double q = G.ratio;
+      double xa[M], xb[M];
+      stream_series<N, YT, M>(ea, eb, same,
+                              [&w0, &w1, q](int s, int i) { return fma(q, w1[s][i], w0[s][i]); },
+                              ParStream<YT>(ja), jb, xa, xb);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        acc[k][0][c] = fma(G.sign, xa[k], acc[k][0][c]);
+        acc[k][1][c] = fma(G.sign, xb[k], acc[k][1][c]);
+      }
+    }
+  }
+  // two-link groups whose uses feed different channels
+#pragma unroll 1
+  for (int g = GT.first[3]; g < GT.n; ++g) {
+    const GroupRow& G = GT.row[g];
+    double ea, eb;
+    bool same;
+    int ja, jb;
+    stencil(G, ea, eb, same, ja, jb);
+    const double* w[2 * M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      w[2 * k] = ylds + (k * 6 + G.link[0]) * YT;
+      w[2 * k + 1] = ylds + (k * 6 + G.link[1]) * YT;
+    }
+    double xa[2 * M], xb[2 * M];
+    stream_multi<N, YT, 2 * M>(ea, eb, same, w, ParStream<YT>(ja), jb, xa, xb);
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[k][0][c] = fma(G.sgn[0][c], xa[2 * k], fma(G.sgn[1][c], xa[2 * k + 1], acc[k][0][c]));
+        acc[k][1][c] = fma(G.sgn[0][c], xb[2 * k], fma(G.sgn[1][c], xb[2 * k + 1], acc[k][1][c]));
+      }
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {
