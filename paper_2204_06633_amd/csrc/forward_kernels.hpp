@@ -635,6 +635,12 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
     }
   }
 
+  // the sample indices again from the lane's tile row: an opaque copy keeps
+  // the compiler from holding the 64-bit indices in registers through the
+  // group loops (they spilled at the four-wave budget)
+  int rl = ra;
+  asm volatile("" : "+v"(rl));
+  const int64_t pl = a.out_start + i0 + rl;
 #pragma unroll
   for (int t = 0; t < ND; ++t) {
     const Direct dr = TdiTab<GEN>::v.direct[t];
@@ -643,8 +649,8 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
       dir_b[dr.chan] += (double)dr.sign * win[dr.link * CAP + par<CAP>(c0 + 1)];
     } else {
       const double* ys = a.y + (int64_t)dr.link * a.n_y;
-      dir_a[dr.chan] += (double)dr.sign * ys[pa];
-      dir_b[dr.chan] += (double)dr.sign * ys[min(pa + 1, ymax)];
+      dir_a[dr.chan] += (double)dr.sign * ys[pl];
+      dir_b[dr.chan] += (double)dr.sign * ys[min(pl + 1, ymax)];
     }
   }
 #pragma unroll
@@ -653,7 +659,7 @@ __global__ __launch_bounds__(kBlock, LR_TDI_MIN_WAVES) void tdi_kernel(TdiArgs a
     acc_b[c] = fma(LagrangeStream<N>::kScale, acc_b[c], dir_b[c]);
   }
   if (!act_a) return;
-  const int64_t i = i0 + ra;
+  const int64_t i = i0 + rl;
   store_channels(acc_a, a.channels, a.out, a.n_out, i);
   if (act_b) store_channels(acc_b, a.channels, a.out, a.n_out, i + 1);
 }
