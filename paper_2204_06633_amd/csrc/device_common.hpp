@@ -202,8 +202,8 @@ __device__ __forceinline__ void lagrange_weights(double eps, double (&w)[N], dou
 // So with R_0 = 1, R_{k+1} = R_k nu_k and the recurrence
 //   T_0 = f_0,   T_k = T_{k-1} nu_k + R_k f_k,
 // T_{N-1} = I / kScale, kScale = K prod_i (c_i / K).  K is a power of two
-// near the geometric mean of the |1/c_i|, which keeps every partial product
-// within ~1e+-20 for N <= 32.
+// near the geometric mean of the |c_i|, so that every |s_k| is of order one
+// and every partial product stays within ~1e+-20 for N <= 32.
 template <int N>
 struct LagrangeScaled {
   double s[N];      // s_k = K / c_k = K prod_{j != k} (x_k - x_j)
