@@ -68,6 +68,7 @@ def lib():
         L.orc_project_adjoint.argtypes = [d, i64, pd, d, d, i64, d, d, i32, pi64, i64, pd, pd, pd]
         L.orc_project_adjoint.restype = i32
         L.orc_max_threads.restype = i32
+        L.orc_set_threads.argtypes = [i32]
         L.orc_sky_basis.argtypes = [d, d, pd, pd, pd]
         _lib = L
     return _lib
@@ -79,6 +80,12 @@ def _p(a, ct=ctypes.c_double):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (for timing at 1 thread and at
+    all cores)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

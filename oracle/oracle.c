@@ -341,6 +341,18 @@ int orc_max_threads(void)
 #endif
 }
 
+/* Thread count of the OpenMP loops (timing runs at one thread and at all
+   cores). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* Sky basis (k, u, v) of Sec. IV.A, exposed for the pin tests. */
 void orc_sky_basis(double lam, double beta, double *k, double *u, double *v)
 {

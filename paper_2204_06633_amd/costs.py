@@ -85,3 +85,68 @@ def fd_bytes(n, n_fft, channels=3, passes=3, grad=True):
 def fd_io_bytes(n, n_fft, channels=3, grad=True):
     sig = 2 if channels == 3 else 1
     return 8 * channels * n * (2 if grad else 1) + 24 * sig * n_fft
+
+
+# ---------------------------------------------------------------------------
+# FP64 lane-operation model (every FP64 operation one lane-op, an FMA too)
+# against the vector issue peak: 256 CUs x 64 lanes x 2.4 GHz.  Per (template,
+# sample), N = order + 1 taps:
+#   Lagrange weights of one retarded position   5N (prefix and suffix products)
+#   one interpolated series                     N  (one multiply-add per tap)
+#   projection geometry and orbit evaluation    200 + 120
+# so the projection costs 9 * 5N + 9 * 2N + 320 per link sample (nine
+# positions, h+ and hx share the weights), TDI 5N per delay group (shared by
+# the templates of a work item, which share the orbits) plus N per delayed
+# term, and the sky gradient 9 * 15N (weights and their derivatives) + 9 * 4N
+# (value and derivative of h+ and hx) + 420 per link sample.  The adjoints
+# scatter with the same weights as their forwards and cost the same.
+# ---------------------------------------------------------------------------
+LANE_OPS_PEAK = 256 * 64 * 2.4e9                              # 3.93e13 FP64 lane-ops/s
+
+
+def lane_ops_projection(order):
+    n = order + 1
+    return 9 * 5 * n + 9 * 2 * n + 200 + 120
+
+
+def lane_ops_tdi(order, generation, share=1):
+    n = order + 1
+    s = TDI_SHAPE[generation]
+    return s["groups"] * 5 * n / share + s["delayed"] * n
+
+
+def lane_ops_sky(order):
+    n = order + 1
+    return 9 * 15 * n + 9 * 4 * n + 420
+
+
+def lane_ops_fused_forward(grids, order, generation, share):
+    """Algorithmic lane-ops of one fused batched forward: the projection of
+    every link sample a template's outputs need (n_y = n_out + TDI padding)
+    and TDI with each weight set shared by ``share`` templates."""
+    return sum(lane_ops_projection(order) * g.n_y +
+               lane_ops_tdi(order, generation, share) * g.n_out for g in grids if g.n_out > 0)
+
+
+def lane_ops_fwd_adjoint(grids, order, generation, share_fwd, share_adj, sky=True):
+    """Forward (as above) plus the TDI adjoint (weights shared by
+    ``share_adj`` templates), the projection adjoint and the sky gradient."""
+    f = lane_ops_fused_forward(grids, order, generation, share_fwd)
+    a = sum(lane_ops_tdi(order, generation, share_adj) * g.n_out +
+            (lane_ops_projection(order) + (lane_ops_sky(order) if sky else 0)) * g.n_y
+            for g in grids if g.n_out > 0)
+    return f + a
+
+
+def batch_bytes(grids, rows=3):
+    """Algorithmic HBM bytes of a batched forward: read h+ and hx over each
+    template's h range, write its channels."""
+    return sum(16.0 * g.n_h + 8.0 * rows * g.n_out for g in grids if g.n_out > 0)
+
+
+def fwd_adjoint_step_bytes(grids, rows=3):
+    """Algorithmic HBM bytes of forward + likelihood + adjoint: the forward
+    reads h+, hx and writes the channels; the likelihood reads them and the
+    data and writes their gradient; the adjoint reads that gradient and
+    h+, hx (for the sky gradient) and writes the gradients of h+ and hx."""
+    return sum(48.0 * g.n_h + 8.0 * rows * 5 * g.n_out for g in grids if g.n_out > 0)

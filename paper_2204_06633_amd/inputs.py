@@ -347,3 +347,12 @@ def noise_weights(n_fft, dt, f_min=1e-4, f_max=2.5e-2, generation=2, L=L_ARM):
     w_ae[band] = 4.0 * df / s_ae
     w_t[band] = 4.0 * df / s_t
     return w_ae, w_t
+
+
+def sample_indices(n, k, seed, edge=8):
+    """``k`` seeded random indices of [0, n) plus the first and last ``edge``
+    (sorted, unique): the output samples that a sampled comparison reads."""
+    rng = np.random.default_rng(seed)
+    mid = rng.choice(n, size=min(k, n), replace=False)
+    idx = np.unique(np.concatenate([np.arange(min(edge, n)), np.arange(max(n - edge, 0), n), mid]))
+    return idx.astype(np.int64)

@@ -102,6 +102,33 @@ def _dev(t, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _size(t, name, shape=None, numel=None, min_numel=None):
+    """Check a tensor argument's extent against what the kernels will touch
+    (before any pointer is handed to the library): exact ``shape``, exact
+    ``numel`` or at least ``min_numel`` elements.  Raises ValueError."""
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
+    if shape is not None and tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError("%s has shape %s, the call needs %s" % (name, tuple(t.shape),
+                                                                  tuple(int(v) for v in shape)))
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError("%s has %d elements, the call needs %d" % (name, t.numel(), int(numel)))
+    if min_numel is not None and t.numel() < int(min_numel):
+        raise ValueError("%s has %d elements, the call needs at least %d"
+                         % (name, t.numel(), int(min_numel)))
+
+
+def _same_device(*named):
+    """All given tensors (None skipped) on one device."""
+    devs = {(n, t.device) for n, t in named if t is not None}
+    if len({d for _, d in devs}) > 1:
+        raise ValueError("arguments on different devices: %s"
+                         % ", ".join("%s on %s" % (n, d) for n, d in sorted(devs, key=str)))
+
+
 # ---------------------------------------------------------------------------
 # Orbits
 # ---------------------------------------------------------------------------
@@ -164,6 +191,10 @@ def project_links(orb: Orbits, t0_h, dt, hp, hc, sky, order, y_start, n_y, y=Non
     import torch
     if y is None:
         y = torch.empty((6, n_y), dtype=torch.float64, device=hp.device)
+    _size(hc, "hc", numel=hp.numel())
+    _size(sky, "sky", numel=2)
+    _size(y, "y", shape=(6, n_y))
+    _same_device(("hp", hp), ("hc", hc), ("sky", sky), ("y", y))
     _check(lib().lr_project_links(orb.ref, float(t0_h), float(dt), hp.numel(), _dev(hp, "hp"),
                                   _dev(hc, "hc"), _dev(sky, "sky"), int(order), int(y_start),
                                   int(n_y), _dev(y, "y"), _stream(stream)), "lr_project_links")
@@ -175,9 +206,13 @@ def tdi_combine(orb: Orbits, t0_y, dt, y, generation, order, channels, out_start
     """TDI channels out[3 or 6][n_out] at y-indices out_start .. out_start +
     n_out - 1 (lr_tdi_combine).  ``channels`` is "XYZ", "AET" or "XYZAET"."""
     import torch
+    rows = 6 if channels == "XYZAET" else 3
     if out is None:
-        rows = 6 if channels == "XYZAET" else 3
         out = torch.empty((rows, n_out), dtype=torch.float64, device=y.device)
+    if y.dim() != 2 or y.shape[0] != 6:
+        raise ValueError("y must be [6][n_y], got shape %s" % (tuple(y.shape),))
+    _size(out, "out", shape=(rows, n_out))
+    _same_device(("y", y), ("out", out))
     n_y = y.shape[-1]
     _check(lib().lr_tdi_combine(orb.ref, float(t0_y), float(dt), n_y, _dev(y, "y"),
                                 int(generation), int(order), CHANNELS[channels], int(out_start),
@@ -195,6 +230,12 @@ def tdi_adjoint(orb: Orbits, t0_y, dt, n_y, generation, order, channels, out_sta
     import torch
     if g_y is None:
         g_y = torch.empty((6, n_y), dtype=torch.float64, device=g_out.device)
+    rows = 6 if channels == "XYZAET" else 3
+    if g_out.dim() != 2 or g_out.shape[0] != rows:
+        raise ValueError("g_out must be [%d][n_out] for %s, got shape %s"
+                         % (rows, channels, tuple(g_out.shape)))
+    _size(g_y, "g_y", shape=(6, n_y))
+    _same_device(("g_out", g_out), ("g_y", g_y))
     n_out = g_out.shape[-1]
     _check(lib().lr_tdi_adjoint(orb.ref, float(t0_y), float(dt), int(n_y), int(generation),
                                 int(order), CHANNELS[channels], int(out_start), int(n_out),
@@ -209,7 +250,14 @@ def project_adjoint(orb: Orbits, t0_h, dt, n_h, hp, hc, sky, order, y_start, g_y
     (lr_project_adjoint); g_sky is None unless ``want_sky``."""
     import torch
     dev = g_y.device
+    if g_y.dim() != 2 or g_y.shape[0] != 6:
+        raise ValueError("g_y must be [6][n_y], got shape %s" % (tuple(g_y.shape),))
     n_y = g_y.shape[-1]
+    _size(hp, "hp", numel=n_h)
+    _size(hc, "hc", numel=n_h)
+    _size(sky, "sky", numel=2)
+    _size(g_hp, "g_hp", numel=n_h)
+    _size(g_hc, "g_hc", numel=n_h)
     if g_hp is None:
         g_hp = torch.empty(n_h, dtype=torch.float64, device=dev)
     if g_hc is None:
@@ -223,6 +271,9 @@ def project_adjoint(orb: Orbits, t0_h, dt, n_h, hp, hc, sky, order, y_start, g_y
             work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
     else:
         g_sky = None
+    _size(g_sky, "g_sky", numel=2)
+    _same_device(("g_y", g_y), ("hp", hp), ("hc", hc), ("sky", sky), ("g_hp", g_hp),
+                 ("g_hc", g_hc), ("g_sky", g_sky), ("work", work if want_sky else None))
     _check(lib().lr_project_adjoint(orb.ref, float(t0_h), float(dt), int(n_h), _opt(hp, "hp"),
                                     _opt(hc, "hc"), _dev(sky, "sky"), int(order), int(y_start),
                                     int(n_y), _dev(g_y, "g_y"), _dev(g_hp, "g_hp"),
@@ -244,6 +295,13 @@ def loglike(h, data, sigma, want_grad=True, out=None, g_h=None, work=None, strea
     nbytes = lib().lr_loglike_workspace()
     if work is None:
         work = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    _size(data, "data", numel=h.numel())
+    _size(out, "loglike", min_numel=1)
+    if want_grad:
+        _size(g_h, "g_h", numel=h.numel())
+    _size(work, "work", min_numel=(nbytes + 7) // 8)
+    _same_device(("h", h), ("data", data), ("loglike", out), ("g_h", g_h if want_grad else None),
+                 ("work", work))
     _check(lib().lr_loglike(_dev(h, "h"), _dev(data, "data"), h.numel(), float(sigma),
                             _dev(out, "loglike"), _opt(g_h if want_grad else None, "g_h"),
                             _dev(work, "work"), work.numel() * 8, _stream(stream)), "lr_loglike")
@@ -330,6 +388,12 @@ class Batch:
     def n(self):
         return len(self.templates)
 
+    def _check_inputs(self, hp, hc, sky):
+        """h+ / hx cover every template's h range; sky holds n (lam, beta)."""
+        _size(hp, "hp", min_numel=self.h_extent)
+        _size(hc, "hc", min_numel=self.h_extent)
+        _size(sky, "sky", min_numel=2 * self.n)
+
     @property
     def blocks(self):
         """Work-groups of the persistent forward launch."""
@@ -351,6 +415,9 @@ class Batch:
         import torch
         if out is None:
             out = torch.empty(max(self.out_extent, 1), dtype=torch.float64, device=hp.device)
+        self._check_inputs(hp, hc, sky)
+        _size(out, "out", min_numel=self.out_extent)
+        _same_device(("hp", hp), ("hc", hc), ("sky", sky), ("out", out))
         _check(_batch_lib().lr_response(ctypes.byref(self.c), _dev(hp, "hp"), _dev(hc, "hc"),
                                         _dev(sky, "sky"), _dev(out, "out"), _stream(stream)),
                "lr_response")
@@ -366,6 +433,16 @@ class Batch:
             g_hc = torch.empty(max(self.h_extent, 1), dtype=torch.float64, device=dev)
         if want_sky and g_sky is None:
             g_sky = torch.empty((max(self.n, 1), 2), dtype=torch.float64, device=dev)
+        if want_sky and (hp is None or hc is None):
+            raise ValueError("the sky gradient needs hp and hc")
+        self._check_inputs(hp, hc, sky)
+        _size(g_out, "g_out", min_numel=self.out_extent)
+        _size(g_hp, "g_hp", min_numel=self.h_extent)
+        _size(g_hc, "g_hc", min_numel=self.h_extent)
+        if want_sky:
+            _size(g_sky, "g_sky", min_numel=2 * self.n)
+        _same_device(("hp", hp), ("hc", hc), ("sky", sky), ("g_out", g_out), ("g_hp", g_hp),
+                     ("g_hc", g_hc), ("g_sky", g_sky if want_sky else None))
         _check(_batch_lib().lr_response_adjoint(
             ctypes.byref(self.c), _opt(hp, "hp"), _opt(hc, "hc"), _dev(sky, "sky"),
             _dev(g_out, "g_out"), _dev(g_hp, "g_hp"), _dev(g_hc, "g_hc"),
@@ -379,6 +456,13 @@ class Batch:
             ll = torch.empty(max(self.n, 1), dtype=torch.float64, device=dev)
         if want_grad and g_out is None:
             g_out = torch.zeros_like(out)
+        _size(out, "out", min_numel=self.out_extent)
+        _size(data, "data", min_numel=self.out_extent)
+        _size(ll, "loglike", min_numel=self.n)
+        if want_grad:
+            _size(g_out, "g_out", min_numel=self.out_extent)
+        _same_device(("out", out), ("data", data), ("loglike", ll),
+                     ("g_out", g_out if want_grad else None))
         _check(_batch_lib().lr_batch_loglike(
             ctypes.byref(self.c), _dev(out, "out"), _dev(data, "data"), float(sigma),
             _dev(ll, "loglike"), _opt(g_out if want_grad else None, "g_out"), _stream(stream)),
@@ -441,6 +525,15 @@ class FdPlan:
             raise ValueError("data must be [channels][n]")
         C, n = data.shape
         L = _fd_lib()
+        if C not in (2, 3):
+            raise ValueError("data must hold 2 (A, E) or 3 (A, E, T) channels")
+        n_bins = fd_length(n) // 2 + 1
+        _size(w_ae, "w_ae", numel=n_bins)
+        if C == 3:
+            if w_t is None:
+                raise ValueError("w_t is needed for three channels")
+            _size(w_t, "w_t", numel=n_bins)
+        _same_device(("data", data), ("w_ae", w_ae), ("w_t", w_t if C == 3 else None))
         nbytes = L.lr_fd_workspace(n, C, max_batch)
         if nbytes == 0:
             raise ValueError("invalid plan arguments (n=%d, channels=%d, max_batch=%d)"
@@ -467,6 +560,15 @@ class FdPlan:
             stats = torch.empty((B, 3), dtype=torch.float64, device=h.device)
         if want_grad and g_h is None:
             g_h = torch.empty_like(hb)
+        _size(stats, "stats", shape=(B, 3))
+        if want_grad:
+            if g_h.dim() == 2:
+                g_h = g_h.unsqueeze(0)
+            _size(g_h, "g_h", shape=tuple(hb.shape))
+            if g_h.stride() != hb.stride():
+                raise ValueError("g_h must be laid out like h")
+        _same_device(("h", h), ("stats", stats), ("g_h", g_h if want_grad else None),
+                     ("workspace", self.ws))
         _check(_fd_lib().lr_fd_loglike(ctypes.byref(self.c), B, _dev(hb, "h"), hb.stride(0),
                                        hb.stride(1), _dev(stats, "stats"),
                                        _opt(g_h if want_grad else None, "g_h"), _stream(stream)),
@@ -511,6 +613,8 @@ def gb_polarizations(params, k0, n_h, dt, hp=None, hc=None, stream=None):
     """(h+, hx) [n][n_h] for params [n][8] on t_j = (k0 + j) dt
     (lr_gb_polarizations)."""
     import torch
+    if params.dim() != 2 or params.shape[1] != 8:
+        raise ValueError("params must be [n][8], got shape %s" % (tuple(params.shape),))
     n = params.shape[0]
     if hp is None:
         hp = torch.empty((n, n_h), dtype=torch.float64, device=params.device)
@@ -518,6 +622,11 @@ def gb_polarizations(params, k0, n_h, dt, hp=None, hc=None, stream=None):
         hc = torch.empty((n, n_h), dtype=torch.float64, device=params.device)
     if hp.stride(0) != hc.stride(0):
         raise ValueError("hp and hc must share one row stride")
+    for name, t in (("hp", hp), ("hc", hc)):
+        if t.dim() != 2 or t.shape[0] != n or t.shape[1] < n_h:
+            raise ValueError("%s must be [%d][>= %d], got shape %s" % (name, n, n_h,
+                                                                     tuple(t.shape)))
+    _same_device(("params", params), ("hp", hp), ("hc", hc))
     _check(_gb_lib().lr_gb_polarizations(_dev(params, "params"), n, int(k0), int(n_h), float(dt),
                                          _dev_rows(hp, "hp"), _dev_rows(hc, "hc"),
                                          max(hp.stride(0), int(n_h)), _stream(stream)),
@@ -528,15 +637,22 @@ def gb_polarizations(params, k0, n_h, dt, hp=None, hc=None, stream=None):
 def gb_polarizations_adjoint(params, k0, dt, g_hp, g_hc, g_params=None, work=None, stream=None):
     """d/dparams of sum(g_hp h+ + g_hc hx), [n][8] (lr_gb_polarizations_adjoint)."""
     import torch
+    if g_hp.dim() != 2 or g_hc.shape != g_hp.shape:
+        raise ValueError("g_hp and g_hc must be [n][n_h] of one shape")
     n, n_h = g_hp.shape
+    _size(params, "params", shape=(n, 8))
     L = _gb_lib()
     if g_params is None:
         g_params = torch.empty((n, 8), dtype=torch.float64, device=params.device)
+    _size(g_params, "g_params", shape=(n, 8))
     nb = L.lr_gb_adjoint_workspace(n, n_h)
     if work is None:
         work = torch.empty((nb + 7) // 8, dtype=torch.float64, device=params.device)
+    _size(work, "work", min_numel=(nb + 7) // 8)
     if g_hp.stride(0) != g_hc.stride(0):
         raise ValueError("g_hp and g_hc must share one row stride")
+    _same_device(("params", params), ("g_hp", g_hp), ("g_hc", g_hc), ("g_params", g_params),
+                 ("work", work))
     _check(L.lr_gb_polarizations_adjoint(_dev(params, "params"), n, int(k0), int(n_h), float(dt),
                                          _dev_rows(g_hp, "g_hp"), _dev_rows(g_hc, "g_hc"),
                                          max(g_hp.stride(0), int(n_h)),

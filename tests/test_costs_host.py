@@ -32,11 +32,23 @@ def test_recorded_traffic_needs_matching_sources(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.recorded_traffic("tdi", "1yr") is None               # no record
+    srcs = ("forward_kernels.hpp",)
+    assert bench.recorded_traffic("tdi_1yr", srcs) is None            # no record
     rec = {"bytes_per_launch": 123.0, "source_hash": "not-the-sources"}
     (prof / "traffic_tdi_1yr.json").write_text(json.dumps(rec))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "the-sources")
-    assert bench.recorded_traffic("tdi", "1yr") is None               # stale record
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda names: "the-sources")
+    assert bench.recorded_traffic("tdi_1yr", srcs) is None            # stale record
     rec["source_hash"] = "the-sources"
     (prof / "traffic_tdi_1yr.json").write_text(json.dumps(rec))
-    assert bench.recorded_traffic("tdi", "1yr") == 123.0
+    assert bench.recorded_traffic("tdi_1yr", srcs) == 123.0
+
+
+def test_lane_op_model_matches_the_stated_counts():
+    """The FP64 lane-op model: projection 9 x 5N + 9 x 2N + 320, TDI-2 36 x 5N
+    + 42 N (weights shared by `share` templates), sky 9 x 19 N + 420."""
+    assert costs.lane_ops_projection(25) == 9 * 130 + 9 * 52 + 320 == 1958
+    assert costs.lane_ops_tdi(25, 2) == 36 * 130 + 42 * 26 == 5772
+    assert costs.lane_ops_tdi(25, 2, share=2) == 36 * 65 + 42 * 26
+    assert costs.lane_ops_tdi(25, 1) == 15 * 130 + 18 * 26
+    assert costs.lane_ops_sky(25) == 9 * 19 * 26 + 420
+    assert costs.LANE_OPS_PEAK == pytest.approx(3.93216e13)

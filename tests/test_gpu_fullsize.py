@@ -47,7 +47,7 @@ def test_uneven_batch_512_sampled(torch_cuda):
         idx = cases.sample_indices(g.n_out, 40, seed=k, edge=3)
         ref = cases.oracle_sampled_response(op, op, case, idx)
         got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
-        assert cases.rel_err(got, ref) <= 1e-11, k
+        cases.check(got, ref, 1e-11, str(k))
 
 
 def test_walkers_256_dot_product(torch_cuda):
@@ -78,3 +78,84 @@ def test_walkers_256_dot_product(torch_cuda):
                     torch.dot(ghc[ho:ho + nh], vc[ho:ho + nh]))
         scale = float(torch.linalg.norm(g[off:off + 3 * n]) * torch.linalg.norm(out[off:off + 3 * n]))
         assert abs(lhs - rhs) <= 1e-12 * scale, (k, lhs, rhs)
+
+
+def _fd_richardson(f, x0, step):
+    d1 = (f(x0 + step) - f(x0 - step)) / (2 * step)
+    d2 = (f(x0 + step / 2) - f(x0 - step / 2)) / step
+    return (4 * d2 - d1) / 3
+
+
+def test_walkers_256_against_oracle(torch_cuda):
+    """The 256-walker forward + adjoint workload at its own shape (1 yr at
+    dt = 15 s, order 25, Keplerian projection with rigid equal-arm TDI
+    orbits, TDI-2 A/E/T), all walkers in one autotuned fused launch:
+      * forward: sampled outputs of four walkers against the oracle;
+      * adjoint: a channel gradient that is zero except at those sampled
+        outputs, against the oracle's TDI scatter at exactly those outputs
+        followed by its projection scatter; every other walker's gradient
+        must be exactly zero;
+      * sky gradient of the same walkers against central differences of
+        the oracle's <g, response(lam, beta)> at the sampled outputs."""
+    torch = torch_cuda
+    from paper_2204_06633_amd import autotune, native
+    dev = torch.device("cuda:0")
+    bc = workloads.walker_batch_case()
+    orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
+    orb_t = native.Orbits.from_samples(bc.orbits_tdi, device=dev)
+    hp, hc = workloads.device_polarizations(bc, dev)
+    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    tpl = bc.layout.templates()
+    tuned = autotune.tune(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                          hp, hc, sky, use_cache=False, reps=1, max_templates=16)
+    batch = native.Batch(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                         group=tuned["group"], adjoint=True, device=dev)
+    batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
+    out = batch.response(hp, hc, sky)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    op = oracle.Orbits.from_samples(bc.orbits_proj)
+    ot = oracle.Orbits.from_samples(bc.orbits_tdi)
+    picks = (0, 1, 127, 255)
+    rng = np.random.default_rng(55)
+    g_out = torch.zeros_like(out)
+    sel = {}
+    for k in picks:
+        g = bc.grids[k]
+        ho, off = bc.layout.h_offsets[k], bc.layout.out_offsets[k]
+        case = workloads.Case("walker_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
+                              hp[ho:ho + g.n_h].cpu().numpy(), hc[ho:ho + g.n_h].cpu().numpy(),
+                              bc.order, bc.generation, bc.channels)
+        idx = cases.sample_indices(g.n_out, 150, seed=500 + k, edge=3)
+        ref = cases.sampled_response(op, ot, case, idx)
+        got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
+        cases.check(got, ref, 1e-11, "forward walker %d" % k)
+        gs = rng.standard_normal((3, idx.size))
+        blk = g_out[off:off + 3 * g.n_out].view(3, g.n_out)
+        blk[:, torch.from_numpy(idx).to(dev)] = torch.tensor(gs, dtype=torch.float64, device=dev)
+        sel[k] = (case, idx, gs)
+    ghp, ghc, gsky = batch.adjoint(hp, hc, sky, g_out)
+    torch.cuda.synchronize()
+    mask = torch.ones(batch.h_extent, dtype=torch.bool, device=dev)
+    gsky_np = gsky.cpu().numpy()
+    for k, (case, idx, gs) in sel.items():
+        g = case.grid
+        ho = bc.layout.h_offsets[k]
+        mask[ho:ho + g.n_h] = False
+        rhp, rhc = cases.sampled_adjoint(op, ot, case, idx, gs)
+        got = np.stack([ghp[ho:ho + g.n_h].cpu().numpy(), ghc[ho:ho + g.n_h].cpu().numpy()])
+        cases.check(got, np.stack([rhp, rhc]), 1e-10, "adjoint walker %d" % k)
+
+        def J(lam, beta, case=case, idx=idx, gs=gs):
+            c = workloads.Case(case.name, case.orbits_proj, case.orbits_tdi, case.grid,
+                               np.concatenate([case.params[:6], [lam, beta]]), case.hp, case.hc,
+                               case.order, case.generation, case.channels)
+            return float(np.sum(cases.sampled_response(op, ot, c, idx) * gs))
+
+        fd_lam = _fd_richardson(lambda x: J(x, case.beta), case.lam, 1e-4)
+        fd_beta = _fd_richardson(lambda x: J(case.lam, x), case.beta, 1e-4)
+        assert abs(gsky_np[k, 0] - fd_lam) <= 1e-6 * abs(fd_lam), (k, gsky_np[k, 0], fd_lam)
+        assert abs(gsky_np[k, 1] - fd_beta) <= 1e-6 * abs(fd_beta), (k, gsky_np[k, 1], fd_beta)
+    rest = [k for k in range(batch.n) if k not in sel]
+    assert float(ghp[mask].abs().max()) == 0.0 and float(ghc[mask].abs().max()) == 0.0
+    assert np.all(gsky_np[rest] == 0.0)

@@ -129,3 +129,35 @@ def test_sampler_argument_checks():
         ps.initial(torch.zeros((2, 5, 1), dtype=torch.float64))     # odd walker count
     with pytest.raises(ValueError):
         ps.initial(torch.zeros((3, 4, 1), dtype=torch.float64))     # 3 temperatures, 2 betas
+
+
+# Hand-computed cases of the Table I sampling coordinates
+# (ln A, f0 in mHz, fdot, cos iota, phi0, psi, lambda, sin beta) and the
+# waveform parameters (A, f0 in Hz, fdot, phi0, iota, psi, lambda, beta) they
+# stand for.  Exact special values (ln 1 = 0, ln 2, acos 0 = pi/2, acos(-1) =
+# pi, asin(-1/2) = -pi/6, ...) and a distinct value in every slot, so a
+# swapped, dropped or wrongly converted coordinate fails.
+_THETA_SOURCE = [
+    ([0.0, 3.0, 1e-16, 0.0, 1.25, 0.5, 2.0, 1.0],
+     [1.0, 3e-3, 1e-16, 1.25, math.pi / 2, 0.5, 2.0, math.pi / 2]),
+    ([math.log(2.0), 0.5, -1e-17, 1.0, 0.0, 3.0, 6.0, -0.5],
+     [2.0, 5e-4, -1e-17, 0.0, 0.0, 3.0, 6.0, -math.pi / 6]),
+    ([-math.log(10.0) * 22, 12.0, 2e-15, -1.0, 6.25, 0.125, 0.75, -1.0],
+     [1e-22, 1.2e-2, 2e-15, 6.25, math.pi, 0.125, 0.75, -math.pi / 2]),
+    ([1.0, 10.0, 1.4e-14, 0.5, 4.58, 0.45, 5.23, math.sqrt(3.0) / 2],
+     [math.e, 1e-2, 1.4e-14, 4.58, math.pi / 3, 0.45, 5.23, math.pi / 3]),
+]
+
+
+@pytest.mark.parametrize("theta,source", _THETA_SOURCE)
+def test_theta_to_source_hand_values(theta, source):
+    got = osamp.theta_to_source(theta)
+    assert len(got) == 8
+    for g, s in zip(got, source):
+        assert math.isclose(g, s, rel_tol=1e-14, abs_tol=1e-300), (got, source)
+    # the product's maps agree with the same hand values
+    th = torch.tensor(theta, dtype=torch.float64)
+    assert torch.allclose(sampler.to_source(th), torch.tensor(source, dtype=torch.float64),
+                          rtol=1e-14, atol=0)
+    assert torch.allclose(sampler.to_theta(torch.tensor(source, dtype=torch.float64)), th,
+                          rtol=1e-13, atol=1e-15)
