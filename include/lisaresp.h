@@ -145,8 +145,13 @@ int lr_tdi_combine(const lr_orbits *orb, double t0_y, double dt, int64_t n_y, co
  * Adjoints.  Not in the paper; they are the exact transposes of the linear
  * maps above (derived from Sec. IV.B-IV.C and the interpolation of
  * Sec. IV.E), so that a likelihood gradient can flow from the TDI channels
- * back to h+, hx and the sky angles.  Gradients are accumulated with FP64
- * atomics: results are reproducible to rounding, not bit for bit.
+ * back to h+, hx and the sky angles.  Each wave of 128 sources sums its
+ * scatters in a register carry in a fixed order, the waves of a tile are
+ * summed in a fixed order, and every output element receives at most two
+ * tile sums (added onto zero, which commutes): results are bitwise
+ * reproducible.  Exception: when dt is so small against the light times that
+ * a wave's footprint does not fit LDS (about dt < L/50), LDS and global
+ * atomics take over and results are reproducible to rounding only.
  * ---------------------------------------------------------------------- */
 
 /* g_y = T^T g_out: transpose of lr_tdi_combine with the same arguments.
@@ -211,6 +216,7 @@ typedef struct {
     int order, generation, channels, group;
     int front, tile_out, blocks, adjoint;
     int64_t n_templates, n_items, n_tdi_items, n_proj_items, n_like_items;
+    int64_t n_tdi_citems, n_padj_citems;
     int64_t gy_doubles, h_extent, out_extent;
     void *ws;
     size_t off[16];      /* workspace region offsets (bytes) */
@@ -248,7 +254,10 @@ int lr_response(const lr_batch *b, const double *hp, const double *hc, const dou
  * g_out laid out like out; g_hp, g_hc like hp, hc over [0, h_extent),
  * overwritten; g_sky device [n][2] (d/d lam, d/d beta) or NULL (then hp, hc
  * may be NULL too).  Graph-capturable; calls sharing one lr_batch must not
- * overlap.  Sums use atomics, so results are reproducible to rounding.
+ * overlap.  Results are bitwise reproducible unless dt is so small (below
+ * about a fiftieth of the light time) that the scatter footprints do not fit
+ * LDS; then atomics reorder the sums and results are reproducible to
+ * rounding.
  * Errors: LR_E_WORKSPACE (batch prepared without adjoint), LR_E_ARG,
  * LR_E_HIP. */
 int lr_response_adjoint(const lr_batch *b, const double *hp, const double *hc,

@@ -7,13 +7,24 @@
 //   project_sky_kernel      g_y, h+, hx -> partial gradients with respect to
 //                           the ecliptic sky angles lam, beta
 //
-// Scatter strategy: a workgroup owns a tile of samples, accumulates its
-// contributions to its stencil footprint in LDS with FP64 LDS atomics, then adds the footprint to the zero-filled global
-// gradient with FP64 global atomics.  Neighbouring footprints overlap by
-// about one stencil, so a global entry receives at most two tile sums; with a
-// zero-filled destination the result does not depend on their order.
+// Scatter strategy (carry kernels, the default): a workgroup owns 512
+// consecutive sources, each wave 128 of them.  Per delay set a wave sums its
+// sources' scatters in a register carry (carry.hpp), in a fixed order, and
+// adds the result to its own LDS rows; at the end of the tile the four
+// waves' rows are summed in wave order and added to the zero-filled global
+// gradient with one FP64 atomic per entry.  Neighbouring tiles' footprints
+// overlap by about one stencil and never three deep, so every global entry
+// receives at most two additions onto zero, and IEEE addition being
+// commutative, the result is bitwise reproducible.
+//
+// When a wave's footprint does not fit the LDS rows (sampling intervals far
+// below the light times, or orbits whose positions do not match their light
+// times) the atomic kernels take over: LDS atomics inside the tile, then the
+// same global additions; their sums depend on the order in which lanes
+// arrive, so those results are reproducible to rounding only.
 #pragma once
 
+#include "carry.hpp"
 #include "forward_kernels.hpp"
 
 namespace lr {
@@ -44,6 +55,15 @@ __device__ __forceinline__ void load_channel_grads(const double* g_out, int chan
 // TDI adjoint
 // ---------------------------------------------------------------------------
 constexpr int kAdjTdiCap(int N) { return kBlock + N + kSlack; }
+
+// Minimum resident waves per SIMD of the carry kernels (register budget;
+// build-time tuning knobs).
+#ifndef LR_TDI_CARRY_MIN_WAVES
+#define LR_TDI_CARRY_MIN_WAVES 2
+#endif
+#ifndef LR_PADJ_CARRY_MIN_WAVES
+#define LR_PADJ_CARRY_MIN_WAVES 2
+#endif
 
 // Fold a lone scatter's value into its weights (saves N multiplies per
 // single-use delay group); build-time switch for measurements.
@@ -207,6 +227,254 @@ __global__ __launch_bounds__(kBlock, 4) void tdi_adjoint_kernel(TdiAdjArgs a) {
   const TdiAdjArgs x[1] = {a};
   const bool live[1] = {true};
   tdi_adjoint_tile<N, GEN, 1>(x, live, blockIdx.x, acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// TDI adjoint, carry form
+// ---------------------------------------------------------------------------
+constexpr int kCarryTile = 4 * kCarrySlots;   // sources per workgroup (4 waves)
+
+struct CarryShared {
+  int lo[kBlock / 64];    // per wave: relative index of its row element 0
+  int rl[kBlock / 64];    // per wave: row length in use (0: wave took the global path)
+};
+
+// Doubles of dynamic LDS of a carry tile: per wave R rows of rl_cap plus
+// NP parked sums per carry of N - 1.
+__host__ __device__ constexpr size_t carry_lds_doubles(int rows, int rl_cap, int ncarry, int N) {
+  return (size_t)(kBlock / 64) * ((size_t)rows * rl_cap + (size_t)ncarry * (N - 1));
+}
+
+// Sum of the waves' rows in wave order for the tile's footprint, added to
+// the global rows.  Row r of wave w starts at relative index
+// kCarrySlots * w + lo[w]; global index = gbase + relative index, valid in
+// [0, n).  `dst(r, n)` gives global row r and sets its length n (null: skip).
+template <int NROWS, class Dst>
+__device__ __forceinline__ void carry_fold(const double* lds, int rl_cap, const CarryShared& cs,
+                                           int64_t gbase, const Dst& dst) {
+  constexpr int nrows = NROWS;
+  constexpr int W = kBlock / 64;
+  const int half = rl_cap / 2;
+  int lo_min = 1 << 30, hi_max = -(1 << 30);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    if (cs.rl[w] == 0) continue;
+    lo_min = min(lo_min, kCarrySlots * w + cs.lo[w]);
+    hi_max = max(hi_max, kCarrySlots * w + cs.lo[w] + cs.rl[w] - 1);
+  }
+  if (hi_max < lo_min) return;
+#pragma unroll
+  for (int r = 0; r < nrows; ++r) {
+    int64_t n = 0;
+    double* g = dst(r, n);
+    if (!g) continue;                                  // uniform
+    for (int e = lo_min + (int)threadIdx.x; e <= hi_max; e += kBlock) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int idx = e - kCarrySlots * w - cs.lo[w];
+        if (idx >= 0 && idx < cs.rl[w])
+          s += lds[((size_t)w * nrows + r) * rl_cap + psplit(idx, half)];
+      }
+      const int64_t j = gbase + e;
+      if (j >= 0 && j < n) atomicAdd(g + j, s);
+    }
+  }
+}
+
+// One 512-source tile of the TDI adjoint for M templates sharing the output
+// grid and TDI orbits (a[0] the longest; see tdi_adjoint_tile).  lds:
+// carry_lds_doubles(M * 6, rl_cap, 2 * M, N) doubles.
+template <int N, int GEN, int M>
+__device__ __forceinline__ void tdi_adjoint_carry_tile(const TdiAdjArgs (&a)[M],
+                                                       const bool (&live)[M], int64_t tile,
+                                                       double* lds, int rl_cap, CarryShared& cs) {
+  constexpr int H = N / 2;
+  constexpr int ND = TdiTab<GEN>::v.ndirect;
+  constexpr int NR = M * 6;
+  const GroupTable<GEN>& GT = group_table<GEN>();
+  const TdiAdjArgs& a0 = a[0];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool lane0 = lane == 0;
+  const int half = rl_cap / 2;
+  double* rows = lds + (size_t)w * NR * rl_cap;
+  double* park = lds + (size_t)(kBlock / 64) * NR * rl_cap + (size_t)w * 2 * M * (N - 1);
+
+  const int64_t i0 = tile * kCarryTile;
+  const int64_t ia = i0 + kCarrySlots * w + 2 * lane;     // output index of slot a (b: +1)
+  const int64_t last = a0.n_out - 1;
+  const int64_t pa = a0.out_start + min(ia, last), pb = a0.out_start + min(ia + 1, last);
+  double La[6], Lb[6];
+  light_times(a0.orb, a0.t_off + (double)pa * a0.dt, La);
+  light_times(a0.orb, a0.t_off + (double)pb * a0.dt, Lb);
+
+  // relative row range of the wave: direct terms at 0..127, delayed terms'
+  // carries at [c, c + N + 126] for every shift c = sh - (H - 1)
+  double dlo, dhi, dlo_b, dhi_b, e_unused;
+  group_delay_bounds(La, GT.chain, dlo, dhi);
+  group_delay_bounds(Lb, GT.chain, dlo_b, dhi_b);
+  const int c_lo = min(split_delay(dhi, a0.inv_dt, e_unused),
+                       split_delay(dhi_b, a0.inv_dt, e_unused)) - (H - 1);
+  const int c_hi = max(split_delay(dlo, a0.inv_dt, e_unused),
+                       split_delay(dlo_b, a0.inv_dt, e_unused)) - (H - 1);
+  const int lo = __builtin_amdgcn_readfirstlane(min(0, wave_min(c_lo)));
+  const int hi = __builtin_amdgcn_readfirstlane(max(kCarrySlots - 1, wave_max(c_hi) + N + kCarrySlots - 2));
+  const bool fits = hi - lo + 1 <= rl_cap;
+
+  double g[M][2][3];
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      g[k][s][0] = g[k][s][1] = g[k][s][2] = 0.0;
+      if (live[k] && ia + s < a[k].n_out)
+        load_channel_grads(a[k].g_out, a[k].channels, a[k].n_out, ia + s, g[k][s]);
+    }
+
+  if (fits) {
+    for (int j = lane; j < NR * rl_cap; j += 64) rows[j] = 0.0;
+    // undelayed terms: the lane's own samples
+#pragma unroll
+    for (int t = 0; t < ND; ++t) {
+      const Direct dr = TdiTab<GEN>::v.direct[t];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        double* row = rows + (k * 6 + dr.link) * rl_cap;
+        row[psplit(2 * lane - lo, half)] += (double)dr.sign * g[k][0][dr.chan];
+        row[psplit(2 * lane + 1 - lo, half)] += (double)dr.sign * g[k][1][dr.chan];
+      }
+    }
+    // delayed terms: the streams' common scale goes into the values
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[k][s][c] *= LagrangeStream<N>::kScale;
+
+    // one carry per template per shift value present in the wave (almost
+    // always one); values of slots with another shift are masked to zero
+    // rows that feed one channel: one use, or two uses of one channel whose
+    // second link receives the same carry times the sign ratio
+#pragma unroll 1
+    for (int gi = 0; gi < GT.first[3]; ++gi) {
+      const GroupRow& G = GT.row[gi];
+      double ea, eb;
+      const int sa = split_delay(row_delay(G, La), a0.inv_dt, ea);
+      const int sb = split_delay(row_delay(G, Lb), a0.inv_dt, eb);
+      const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sa, sb)));
+      const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sa, sb)));
+      const bool two = G.nuse == 2;                   // uniform
+      for (int sg = s_lo; sg <= s_hi; ++sg) {
+        double va[M], vb[M], A[M], B[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const double xa = G.sgn[0][0] * g[k][0][0] + G.sgn[0][1] * g[k][0][1] +
+                            G.sgn[0][2] * g[k][0][2];
+          const double xb = G.sgn[0][0] * g[k][1][0] + G.sgn[0][1] * g[k][1][1] +
+                            G.sgn[0][2] * g[k][1][2];
+          va[k] = sa == sg ? xa : 0.0;
+          vb[k] = sb == sg ? xb : 0.0;
+        }
+        carry_scatter<N, M>(ea, eb, va, vb, A, B, park, lane0);
+        const int o = sg - (H - 1) - lo;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          carry_add<N>(rows + (k * 6 + G.link[0]) * rl_cap, half, o, lane, 1.0, A[k], B[k],
+                       park + k * (N - 1));
+          if (two)
+            carry_add<N>(rows + (k * 6 + G.link[1]) * rl_cap, half, o, lane, G.ratio, A[k],
+                         B[k], park + k * (N - 1));
+        }
+      }
+    }
+    // two-link groups whose uses feed different channels
+#pragma unroll 1
+    for (int gi = GT.first[3]; gi < GT.n; ++gi) {
+      const GroupRow& G = GT.row[gi];
+      double ea, eb;
+      const int sa = split_delay(row_delay(G, La), a0.inv_dt, ea);
+      const int sb = split_delay(row_delay(G, Lb), a0.inv_dt, eb);
+      const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sa, sb)));
+      const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sa, sb)));
+      for (int sg = s_lo; sg <= s_hi; ++sg) {
+        double va[2 * M], vb[2 * M], A[2 * M], B[2 * M];
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double xa = G.sgn[u][0] * g[k][0][0] + G.sgn[u][1] * g[k][0][1] +
+                              G.sgn[u][2] * g[k][0][2];
+            const double xb = G.sgn[u][0] * g[k][1][0] + G.sgn[u][1] * g[k][1][1] +
+                              G.sgn[u][2] * g[k][1][2];
+            va[2 * k + u] = sa == sg ? xa : 0.0;
+            vb[2 * k + u] = sb == sg ? xb : 0.0;
+          }
+        carry_scatter<N, 2 * M>(ea, eb, va, vb, A, B, park, lane0);
+        const int o = sg - (H - 1) - lo;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            carry_add<N>(rows + (k * 6 + G.link[u]) * rl_cap, half, o, lane, 1.0, A[2 * k + u],
+                         B[2 * k + u], park + (2 * k + u) * (N - 1));
+      }
+    }
+  } else {
+    // footprint wider than the rows: scatter straight to global memory
+    auto scatter = [&](const TdiAdjArgs& ak, int64_t i, const double (&L)[6],
+                       const double (&gs)[3]) {
+      if (i >= ak.n_out) return;
+      const int64_t p = ak.out_start + i;
+#pragma unroll
+      for (int t = 0; t < ND; ++t) {
+        const Direct dr = TdiTab<GEN>::v.direct[t];
+        atomicAdd(ak.g_y + (int64_t)dr.link * ak.n_y + p, (double)dr.sign * gs[dr.chan]);
+      }
+#pragma unroll 1
+      for (int gi = 0; gi < GT.n; ++gi) {
+        const GroupRow& G = GT.row[gi];
+        double eps;
+        const int sh = split_delay(row_delay(G, L), ak.inv_dt, eps);
+#pragma unroll 1
+        for (int u = 0; u < G.nuse; ++u) {
+          const double v = G.sgn[u][0] * gs[0] + G.sgn[u][1] * gs[1] + G.sgn[u][2] * gs[2];
+          scatter_global<N>(ak.g_y + (int64_t)G.link[u] * ak.n_y, p + sh - (H - 1), ak.n_y, eps,
+                            v);
+        }
+      }
+    };
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      if (!live[k]) continue;
+      scatter(a[k], ia, La, g[k][0]);
+      scatter(a[k], ia + 1, Lb, g[k][1]);
+    }
+  }
+  if (lane0) {
+    cs.lo[w] = lo;
+    cs.rl[w] = fits ? hi - lo + 1 : 0;
+  }
+  __syncthreads();
+  carry_fold<NR>(lds, rl_cap, cs, a0.out_start + i0, [&](int r, int64_t& n) -> double* {
+    const int k = r / 6, l = r % 6;
+#pragma unroll
+    for (int kk = 0; kk < M; ++kk)
+      if (kk == k && live[kk]) {
+        n = a[kk].n_y;
+        return a[kk].g_y + (int64_t)l * a[kk].n_y;
+      }
+    return nullptr;
+  });
+}
+
+template <int N, int GEN>
+__global__ __launch_bounds__(kBlock, LR_TDI_CARRY_MIN_WAVES) void tdi_adjoint_carry_kernel(TdiAdjArgs a) {
+  extern __shared__ double lds_dyn[];
+  __shared__ CarryShared cs;
+  const TdiAdjArgs x[1] = {a};
+  const bool live[1] = {true};
+  tdi_adjoint_carry_tile<N, GEN, 1>(x, live, blockIdx.x, lds_dyn, a.rl_cap, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,6 +705,203 @@ __device__ __forceinline__ void project_sky_tile(const ProjAdjArgs& a, int64_t t
   }
 }
 
+// ---------------------------------------------------------------------------
+// Projection adjoint, carry form
+// ---------------------------------------------------------------------------
+// What the nine positions of one link sample need: light times, k.x_s / c,
+// antenna patterns and the upstream gradient scaled by 1/(2(1 - k.n)).
+// Field f is v[f]; a lane's second slot keeps its copy in LDS ([field][lane]
+// rows of the wave), which leaves the registers to the carry.
+constexpr int kPcKx = 0, kPcL = 3, kPcXip = 9, kPcXic = 12, kPcCl = 15, kPcFields = 21;
+
+struct ProjCarryRegs {
+  double v[kPcFields];
+  __device__ __forceinline__ double operator()(int f) const { return v[f]; }
+};
+struct ProjCarryLds {
+  const double* p;   // field 0 of the lane; fields 64 doubles apart
+  __device__ __forceinline__ double operator()(int f) const { return p[f * 64]; }
+};
+
+__device__ __forceinline__ void proj_carry_slot(const ProjAdjArgs& a, const Sky& sk, int64_t i,
+                                                double (&v)[kPcFields]) {
+  const int64_t last = a.n_y - 1;
+  const int64_t q = a.y_start + min(i, last);
+  LinkGeom g;
+  link_geometry(a.orb, a.t_off + (double)q * a.dt, sk, g);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[kPcKx + k] = g.kx[k];
+    v[kPcXip + k] = g.xip[k];
+    v[kPcXic + k] = g.xic[k];
+  }
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    v[kPcL + l] = g.L[l];
+    const double gy = i <= last ? a.g_y[(int64_t)l * a.n_y + i] : 0.0;
+    v[kPcCl + l] = gy / (2.0 * (1.0 - kDir[l] * g.kn[kArm[l]]));
+  }
+}
+
+// Delay of position P and the amplitudes it scatters onto h+ and hx
+// (receptions 0..2 subtract the links received there, emissions 3..8 add).
+template <int P, class Slot>
+__device__ __forceinline__ double proj_carry_pos(const Slot& s, double& ap, double& ac) {
+  if constexpr (P >= 3) {
+    constexpr int l = P - 3, arm = kArm[l];
+    const double cl = s(kPcCl + l);
+    ap = cl * s(kPcXip + arm);
+    ac = cl * s(kPcXic + arm);
+    return s(kPcL + l) + s(kPcKx + kLinkEmit[l] - 1);
+  } else {
+    ap = 0.0;
+    ac = 0.0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+      if (kLinkRecv[l] - 1 == P) {
+        const double cl = s(kPcCl + l);
+        ap -= cl * s(kPcXip + kArm[l]);
+        ac -= cl * s(kPcXic + kArm[l]);
+      }
+    return s(kPcKx + P);
+  }
+}
+
+template <int N, int P>
+__device__ __forceinline__ void proj_carry_position(const ProjAdjArgs& a, const ProjCarryRegs& sa,
+                                                    const ProjCarryLds& sb, int lo, int lane,
+                                                    bool lane0, double* rows, int rl_cap,
+                                                    double* park) {
+  constexpr int H = N / 2;
+  const int half = rl_cap / 2;
+  double va[2], vb[2], ea, eb;
+  const int sha = split_delay(proj_carry_pos<P>(sa, va[0], va[1]), a.inv_dt, ea);
+  const int shb = split_delay(proj_carry_pos<P>(sb, vb[0], vb[1]), a.inv_dt, eb);
+  const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sha, shb)));
+  const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sha, shb)));
+  // the streams' common scale goes into the values
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    va[c] *= LagrangeStream<N>::kScale;
+    vb[c] *= LagrangeStream<N>::kScale;
+  }
+  for (int sg = s_lo; sg <= s_hi; ++sg) {
+    double xa[2], xb[2], A[2], B[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      xa[c] = sha == sg ? va[c] : 0.0;
+      xb[c] = shb == sg ? vb[c] : 0.0;
+    }
+    carry_scatter<N, 2>(ea, eb, xa, xb, A, B, park, lane0);
+    const int o = sg - (H - 1) - lo;
+    carry_add<N>(rows, half, o, lane, 1.0, A[0], B[0], park);
+    carry_add<N>(rows + rl_cap, half, o, lane, 1.0, A[1], B[1], park + (N - 1));
+  }
+}
+
+// One 512-link-sample tile of the projection adjoint (g_y -> g_h+, g_hx).
+// lds: proj_carry_lds_doubles(rl_cap, N) doubles.
+__host__ __device__ constexpr size_t proj_carry_lds_doubles(int rl_cap, int N) {
+  return carry_lds_doubles(2, rl_cap, 2, N) + (size_t)(kBlock / 64) * kPcFields * 64;
+}
+
+template <int N>
+__device__ __forceinline__ void project_adjoint_carry_tile(const ProjAdjArgs& a, int64_t tile,
+                                                           double* lds, int rl_cap,
+                                                           CarryShared& cs,
+                                                           double (&s_trig)[2][2]) {
+  constexpr int H = N / 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool lane0 = lane == 0;
+  double* rows = lds + (size_t)w * 2 * rl_cap;
+  double* park = lds + (size_t)(kBlock / 64) * 2 * rl_cap + (size_t)w * 2 * (N - 1);
+
+  const SkyTrig tr = load_sky(a.sky, s_trig);
+  const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
+  const int64_t i0 = tile * kCarryTile;
+  const int64_t ia = i0 + kCarrySlots * w + 2 * lane;
+  ProjCarryRegs sa;
+  proj_carry_slot(a, sk, ia, sa.v);
+  double* sb_lds = lds + carry_lds_doubles(2, rl_cap, 2, N) + (size_t)w * kPcFields * 64 + lane;
+  {
+    double v[kPcFields];
+    proj_carry_slot(a, sk, ia + 1, v);
+#pragma unroll
+    for (int f = 0; f < kPcFields; ++f) sb_lds[f * 64] = v[f];
+  }
+  const ProjCarryLds sb{sb_lds};
+
+  // relative row range: every position's carry covers [c, c + N + 126]
+  int c_lo = 1 << 30, c_hi = -(1 << 30);
+  {
+    double e_unused, u0, u1;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int x = split_delay(sa(kPcKx + p), a.inv_dt, e_unused);
+      const int y = split_delay(sb(kPcKx + p), a.inv_dt, e_unused);
+      c_lo = min(c_lo, min(x, y));
+      c_hi = max(c_hi, max(x, y));
+    }
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      const int e = kPcKx + kLinkEmit[l] - 1;
+      const int x = split_delay(sa(kPcL + l) + sa(e), a.inv_dt, e_unused);
+      const int y = split_delay(sb(kPcL + l) + sb(e), a.inv_dt, e_unused);
+      c_lo = min(c_lo, min(x, y));
+      c_hi = max(c_hi, max(x, y));
+    }
+    (void)u0; (void)u1;
+  }
+  const int lo = __builtin_amdgcn_readfirstlane(wave_min(c_lo) - (H - 1));
+  const int hi = __builtin_amdgcn_readfirstlane(wave_max(c_hi) - (H - 1) + N + kCarrySlots - 2);
+  const bool fits = hi - lo + 1 <= rl_cap;
+
+  if (fits) {
+    for (int j = lane; j < 2 * rl_cap; j += 64) rows[j] = 0.0;
+#define LR_PCARRY(P)                                                                          \
+    proj_carry_position<N, P>(a, sa, sb, lo, lane, lane0, rows, rl_cap, park);               \
+    __builtin_amdgcn_sched_barrier(0);
+    LR_PCARRY(0) LR_PCARRY(1) LR_PCARRY(2) LR_PCARRY(3) LR_PCARRY(4) LR_PCARRY(5)
+    LR_PCARRY(6) LR_PCARRY(7) LR_PCARRY(8)
+#undef LR_PCARRY
+  } else {
+    // footprint wider than the rows: scatter straight to global memory
+    auto scatter = [&](const auto& S, int64_t i) {
+      if (i >= a.n_y) return;
+      const int64_t q = a.y_start + i;
+#define LR_PGLOBAL(P)                                                                         \
+      {                                                                                       \
+        double ap, ac, eps;                                                                   \
+        const int sh = split_delay(proj_carry_pos<P>(S, ap, ac), a.inv_dt, eps);              \
+        scatter_global<N>(a.g_hp, q + sh - (H - 1), a.n_h, eps, ap);                          \
+        scatter_global<N>(a.g_hc, q + sh - (H - 1), a.n_h, eps, ac);                          \
+      }
+      LR_PGLOBAL(0) LR_PGLOBAL(1) LR_PGLOBAL(2) LR_PGLOBAL(3) LR_PGLOBAL(4) LR_PGLOBAL(5)
+      LR_PGLOBAL(6) LR_PGLOBAL(7) LR_PGLOBAL(8)
+#undef LR_PGLOBAL
+    };
+    scatter(sa, ia);
+    scatter(sb, ia + 1);
+  }
+  if (lane0) {
+    cs.lo[w] = lo;
+    cs.rl[w] = fits ? hi - lo + 1 : 0;
+  }
+  __syncthreads();
+  carry_fold<2>(lds, rl_cap, cs, a.y_start + i0, [&](int r, int64_t& n) -> double* {
+    n = a.n_h;
+    return r == 0 ? a.g_hp : a.g_hc;
+  });
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock, LR_PADJ_CARRY_MIN_WAVES) void project_adjoint_carry_kernel(ProjAdjArgs a) {
+  extern __shared__ double lds_dyn[];
+  __shared__ CarryShared cs;
+  __shared__ double s_trig[2][2];
+  project_adjoint_carry_tile<N>(a, blockIdx.x, lds_dyn, a.rl_cap, cs, s_trig);
+}
+
 // Minimum resident waves per SIMD of the projection-adjoint and sky kernels
 // (build-time tuning knobs; 1 leaves the compiler unconstrained).
 #ifndef LR_PADJ_MIN_WAVES
@@ -460,8 +925,33 @@ __global__ __launch_bounds__(kBlock, LR_SKY_MIN_WAVES) void project_sky_kernel(P
   project_sky_tile<N>(a, blockIdx.x, win, sh_, a.sky_part + 2 * blockIdx.x);
 }
 
+// Allow a kernel more than the default 64 KB of dynamic LDS (a per-function
+// attribute; set before every such launch, which costs a host call only).
+template <class K>
+hipError_t allow_dynamic_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int N>
 hipError_t launch_tdi_adjoint(const TdiAdjArgs& a, int gen, hipStream_t s) {
+  if (a.rl_cap > 0) {
+    const int64_t blocks = (a.n_out + kCarryTile - 1) / kCarryTile;
+    const size_t bytes = carry_lds_doubles(6, a.rl_cap, 2, N) * sizeof(double);
+    if (gen == 1) {
+      hipError_t e = allow_dynamic_lds(tdi_adjoint_carry_kernel<N, 1>, bytes);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((tdi_adjoint_carry_kernel<N, 1>), dim3((unsigned)blocks), dim3(kBlock),
+                         bytes, s, a);
+    } else {
+      hipError_t e = allow_dynamic_lds(tdi_adjoint_carry_kernel<N, 2>, bytes);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((tdi_adjoint_carry_kernel<N, 2>), dim3((unsigned)blocks), dim3(kBlock),
+                         bytes, s, a);
+    }
+    return hipGetLastError();
+  }
   const int64_t blocks = (a.n_out + kBlock - 1) / kBlock;
   if (gen == 1)
     hipLaunchKernelGGL((tdi_adjoint_kernel<N, 1>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
@@ -470,13 +960,23 @@ hipError_t launch_tdi_adjoint(const TdiAdjArgs& a, int gen, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Scatter kernel, then (if a.sky_part) the sky-gradient kernel on the same
-// tiles.
+// Scatter kernel, then (if a.sky_part) the sky-gradient kernel on tiles of
+// kBlock link samples.
 template <int N>
 hipError_t launch_project_adjoint(const ProjAdjArgs& a, hipStream_t s) {
   const int64_t blocks = (a.n_y + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((project_adjoint_kernel<N>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (a.rl_cap > 0) {
+    const size_t bytes = proj_carry_lds_doubles(a.rl_cap, N) * sizeof(double);
+    e = allow_dynamic_lds(project_adjoint_carry_kernel<N>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((project_adjoint_carry_kernel<N>),
+                       dim3((unsigned)((a.n_y + kCarryTile - 1) / kCarryTile)), dim3(kBlock),
+                       bytes, s, a);
+  } else {
+    hipLaunchKernelGGL((project_adjoint_kernel<N>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  }
+  e = hipGetLastError();
   if (e == hipSuccess && a.sky_part) {
     hipLaunchKernelGGL((project_sky_kernel<N>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     e = hipGetLastError();

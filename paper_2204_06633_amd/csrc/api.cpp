@@ -27,6 +27,23 @@ int set_error(int status, const char* fmt, ...) {
   g_err = buf;
   return status;
 }
+
+// Wave row capacity of the carry adjoint kernels (even), or 0 when the
+// rows would not fit LDS (the atomic kernels then run).  `spread` bounds, in
+// seconds, how far apart the delays of one wave's stencils can lie; each row
+// holds the wave's 128 sources plus that spread plus one stencil.  `extra`:
+// further doubles of LDS per wave.
+int carry_row_capacity(int order, double spread, double dt, int rows, int ncarry, int extra) {
+  const int N = order + 1;
+  const double s = std::ceil(spread / dt);
+  if (!(s >= 0.0) || s > 1e6) return 0;
+  int cap = N + 128 + (int)s + 4;
+  cap += cap & 1;
+  const size_t bytes =
+      (size_t)4 * ((size_t)rows * cap + (size_t)ncarry * (N - 1) + (size_t)extra) * sizeof(double);
+  return bytes <= (size_t)150 * 1024 ? cap : 0;
+}
+
 }  // namespace lr
 
 namespace {
@@ -184,7 +201,7 @@ const char* lr_status_str(int s) {
 
 const char* lr_last_error(void) { return g_err.c_str(); }
 
-int lr_abi_version(void) { return 2; }
+int lr_abi_version(void) { return 3; }
 
 size_t lr_orbits_bytes(int64_t n) {
   if (n < 4) return 0;
@@ -360,6 +377,7 @@ int lr_tdi_adjoint(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, in
   a.out_start = out_start;
   a.n_out = n_out;
   a.g_y = g_y;
+  a.rl_cap = lr::carry_row_capacity(order, (generation == 1 ? 3 : 7) * orb->L_max, dt, 6, 2, 0);
   e = lr::run_tdi_adjoint(order, generation, a, s);
   if (e != hipSuccess) return hip_fail(e, "lr_tdi_adjoint launch");
   return LR_OK;
@@ -414,6 +432,7 @@ int lr_project_adjoint(const lr_orbits* orb, double t0_h, double dt, int64_t n_h
   a.g_hp = g_hp;
   a.g_hc = g_hc;
   a.sky_part = g_sky ? static_cast<double*>(work) : nullptr;
+  a.rl_cap = lr::carry_row_capacity(order, 2.01 * orb->L_max, dt, 2, 2, 21 * 64);
   e = lr::run_project_adjoint(order, a, s);
   if (e == hipSuccess && g_sky)
     e = lr::run_sky_finalize(a.sky_part, (n_y + lr::kTile - 1) / lr::kTile, g_sky, s);

@@ -17,12 +17,13 @@ namespace {
 using lr::set_error;
 
 constexpr int kYTile = 512;           // link samples per fused work item (2 per lane)
-constexpr int64_t kAdjTile = 256;     // samples per adjoint work item
+constexpr int64_t kAdjTile = 256;     // samples per adjoint work item (atomic kernels, sky)
+constexpr int64_t kCarryTile = 512;   // samples per work item of the carry adjoint kernels
 constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
 
 enum Region {
   R_TPL, R_ITEMS, R_COUNTER, R_ADJ_TPL, R_TDI_ITEMS, R_PROJ_ITEMS, R_SKY_PART, R_SKY_SPAN,
-  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_GY, R_COUNT
+  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_TDI_CITEMS, R_PADJ_CITEMS, R_GY, R_COUNT
 };
 
 static_assert(R_COUNT <= (int)(sizeof(((lr_batch*)nullptr)->off) / sizeof(size_t)),
@@ -34,6 +35,7 @@ struct Plan {
   std::vector<int> items;
   std::vector<lr::BatchAdjTemplate> adj;
   std::vector<int64_t> tdi_items, proj_items, sky_span, like_items, like_span, pairs;
+  std::vector<int64_t> tdi_citems, padj_citems;
   int64_t gy_doubles = 0, h_extent = 0, out_extent = 0, max_n_out = 0;
   size_t bytes[R_COUNT] = {};
   size_t off[R_COUNT] = {};
@@ -113,6 +115,10 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
     P.sky_span.push_back(first);
     P.sky_span.push_back((int64_t)P.proj_items.size() / 2 - first);
     P.sky_span.push_back(b);
+    for (int64_t tl = 0; tl < (A.n_y + kCarryTile - 1) / kCarryTile; ++tl) {
+      P.padj_citems.push_back(b);
+      P.padj_citems.push_back(tl);
+    }
     const int64_t lfirst = (int64_t)P.like_items.size() / 2;
     const int64_t len = rows * T.n_out;
     for (int64_t c = 0; c < len; c += kLikeChunk) {
@@ -138,6 +144,10 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
       P.tdi_items.push_back(pr);
       P.tdi_items.push_back(tl);
     }
+    for (int64_t tl = 0; tl < (t[b0].n_out + kCarryTile - 1) / kCarryTile; ++tl) {
+      P.tdi_citems.push_back(pr);
+      P.tdi_citems.push_back(tl);
+    }
   }
 
   P.bytes[R_TPL] = P.tpl.size() * sizeof(lr::BatchTemplate);
@@ -152,6 +162,8 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   P.bytes[R_LIKE_PART] = P.like_items.size() / 2 * sizeof(double);
   P.bytes[R_LIKE_SPAN] = P.like_span.size() * sizeof(int64_t);
   P.bytes[R_PAIRS] = adjoint ? P.pairs.size() * sizeof(int64_t) : 0;
+  P.bytes[R_TDI_CITEMS] = adjoint ? P.tdi_citems.size() * sizeof(int64_t) : 0;
+  P.bytes[R_PADJ_CITEMS] = adjoint ? P.padj_citems.size() * sizeof(int64_t) : 0;
   P.bytes[R_GY] = adjoint ? (size_t)P.gy_doubles * sizeof(double) : 0;
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
@@ -253,6 +265,8 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   put(R_LIKE_ITEMS, P.like_items.data());
   put(R_LIKE_SPAN, P.like_span.data());
   put(R_PAIRS, P.pairs.data());
+  put(R_TDI_CITEMS, P.tdi_citems.data());
+  put(R_PADJ_CITEMS, P.padj_citems.data());
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(ws, img.data(), P.off[R_GY], hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -282,6 +296,8 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   out->n_tdi_items = (int64_t)P.tdi_items.size() / 2;
   out->n_proj_items = (int64_t)P.proj_items.size() / 2;
   out->n_like_items = (int64_t)P.like_items.size() / 2;
+  out->n_tdi_citems = (int64_t)P.tdi_citems.size() / 2;
+  out->n_padj_citems = (int64_t)P.padj_citems.size() / 2;
   out->gy_doubles = adjoint ? P.gy_doubles : 0;
   out->h_extent = P.h_extent;
   out->out_extent = P.out_extent;
@@ -352,13 +368,22 @@ int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
   a.g_hc = g_hc;
   a.sky_part = g_sky ? at<double>(b, R_SKY_PART) : nullptr;
   a.pairs = at<const int64_t>(b, R_PAIRS);
+  a.sky_items = at<const int64_t>(b, R_PROJ_ITEMS);
+  // carry kernels (deterministic) where their rows fit LDS, else atomic ones
+  const int cap_t = lr::carry_row_capacity(b->order, (b->generation == 1 ? 3 : 7) * b->tdi.L_max,
+                                           b->dt, 12, 4, 0);
+  const int cap_p = lr::carry_row_capacity(b->order, 2.01 * b->proj.L_max, b->dt, 2, 2, 21 * 64);
   if (e == hipSuccess && b->n_tdi_items > 0) {
-    a.items = at<const int64_t>(b, R_TDI_ITEMS);
-    e = lr::run_batch_tdi_adjoint(b->order, b->generation, a, b->n_tdi_items, s);
+    a.rl_cap = cap_t;
+    a.items = at<const int64_t>(b, cap_t > 0 ? R_TDI_CITEMS : R_TDI_ITEMS);
+    e = lr::run_batch_tdi_adjoint(b->order, b->generation, a,
+                                  cap_t > 0 ? b->n_tdi_citems : b->n_tdi_items, s);
   }
   if (e == hipSuccess && b->n_proj_items > 0) {
-    a.items = at<const int64_t>(b, R_PROJ_ITEMS);
-    e = lr::run_batch_project_adjoint(b->order, a, b->n_proj_items, s);
+    a.rl_cap = cap_p;
+    a.items = at<const int64_t>(b, cap_p > 0 ? R_PADJ_CITEMS : R_PROJ_ITEMS);
+    e = lr::run_batch_project_adjoint(b->order, a, cap_p > 0 ? b->n_padj_citems : b->n_proj_items,
+                                      b->n_proj_items, s);
   }
   if (e == hipSuccess && g_sky && b->n_proj_items > 0)
     e = lr::run_batch_sky_finalize(a.sky_part, at<const int64_t>(b, R_SKY_SPAN), b->n_templates,

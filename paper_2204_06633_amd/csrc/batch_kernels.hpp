@@ -276,6 +276,7 @@ __device__ __forceinline__ TdiAdjArgs batch_tdi_args(const BatchAdjArgs& a,
   x.out_start = a.F;
   x.n_out = T.n_out;
   x.g_y = a.g_y + T.gy_off;
+  x.rl_cap = 0;
   return x;
 }
 
@@ -312,6 +313,7 @@ __device__ __forceinline__ ProjAdjArgs batch_proj_args(const BatchAdjArgs& a,
   x.g_hp = a.g_hp + T.h_off;
   x.g_hc = a.g_hc + T.h_off;
   x.sky_part = nullptr;
+  x.rl_cap = 0;
   return x;
 }
 
@@ -327,25 +329,70 @@ template <int N>
 __global__ __launch_bounds__(kBlock, LR_SKY_MIN_WAVES) void batch_project_sky_kernel(BatchAdjArgs a) {
   __shared__ double2 win[kAdjProjCap(N)];
   __shared__ ProjAdjShared sh_;
-  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  const int64_t b = a.sky_items[2 * blockIdx.x], tile = a.sky_items[2 * blockIdx.x + 1];
   project_sky_tile<N>(batch_proj_args(a, a.tpl[b]), tile, win, sh_, a.sky_part + 2 * blockIdx.x);
 }
 
+// Carry forms: work item = (pair of templates, tile of kCarryTile outputs) for
+// the TDI adjoint (both templates' carries share each weight sequence), and
+// (template, tile of kCarryTile link samples) for the projection adjoint.
+template <int N, int GEN>
+__global__ __launch_bounds__(kBlock, LR_TDI_CARRY_MIN_WAVES) void batch_tdi_adjoint_carry_kernel(BatchAdjArgs a) {
+  extern __shared__ double lds_dyn[];
+  __shared__ CarryShared cs;
+  const int64_t pr = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  const int64_t b0 = a.pairs[2 * pr], b1 = a.pairs[2 * pr + 1];
+  const TdiAdjArgs x[2] = {batch_tdi_args(a, a.tpl[b0]),
+                           batch_tdi_args(a, a.tpl[b1 >= 0 ? b1 : b0])};
+  const bool live[2] = {true, b1 >= 0 && tile * kCarryTile < x[1].n_out};
+  tdi_adjoint_carry_tile<N, GEN, 2>(x, live, tile, lds_dyn, a.rl_cap, cs);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock, LR_PADJ_CARRY_MIN_WAVES) void batch_project_adjoint_carry_kernel(BatchAdjArgs a) {
+  extern __shared__ double lds_dyn[];
+  __shared__ CarryShared cs;
+  __shared__ double s_trig[2][2];
+  const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
+  project_adjoint_carry_tile<N>(batch_proj_args(a, a.tpl[b]), tile, lds_dyn, a.rl_cap, cs,
+                                s_trig);
+}
+
+// a.items: the carry lists (tiles of kCarryTile) when a.rl_cap > 0, else the
+// atomic lists (tiles of kBlock).
 template <int N, int GEN>
 hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s) {
+  if (a.rl_cap > 0) {
+    const size_t bytes = carry_lds_doubles(12, a.rl_cap, 4, N) * sizeof(double);
+    hipError_t e = allow_dynamic_lds(batch_tdi_adjoint_carry_kernel<N, GEN>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_tdi_adjoint_carry_kernel<N, GEN>), dim3((unsigned)n_items),
+                       dim3(kBlock), bytes, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((batch_tdi_adjoint_kernel<N, GEN>), dim3((unsigned)n_items), dim3(kBlock), 0,
                      s, a);
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s) {
-  hipLaunchKernelGGL((batch_project_adjoint_kernel<N>), dim3((unsigned)n_items), dim3(kBlock), 0,
-                     s, a);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess && a.sky_part) {
-    hipLaunchKernelGGL((batch_project_sky_kernel<N>), dim3((unsigned)n_items), dim3(kBlock), 0,
-                       s, a);
+hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items,
+                                        int64_t n_sky_items, hipStream_t s) {
+  hipError_t e;
+  if (a.rl_cap > 0) {
+    const size_t bytes = proj_carry_lds_doubles(a.rl_cap, N) * sizeof(double);
+    e = allow_dynamic_lds(batch_project_adjoint_carry_kernel<N>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_project_adjoint_carry_kernel<N>), dim3((unsigned)n_items),
+                       dim3(kBlock), bytes, s, a);
+  } else {
+    hipLaunchKernelGGL((batch_project_adjoint_kernel<N>), dim3((unsigned)n_items), dim3(kBlock),
+                       0, s, a);
+  }
+  e = hipGetLastError();
+  if (e == hipSuccess && a.sky_part && n_sky_items > 0) {
+    hipLaunchKernelGGL((batch_project_sky_kernel<N>), dim3((unsigned)n_sky_items), dim3(kBlock),
+                       0, s, a);
     e = hipGetLastError();
   }
   return e;
@@ -365,6 +412,7 @@ hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, 
                                                       hipStream_t);                            \
   template hipError_t launch_batch_tdi_adjoint<NT, 2>(const BatchAdjArgs&, int64_t,             \
                                                       hipStream_t);                            \
-  template hipError_t launch_batch_project_adjoint<NT>(const BatchAdjArgs&, int64_t, hipStream_t);
+  template hipError_t launch_batch_project_adjoint<NT>(const BatchAdjArgs&, int64_t, int64_t,    \
+                                                      hipStream_t);
 
 }  // namespace lr

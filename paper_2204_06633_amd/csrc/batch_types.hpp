@@ -47,6 +47,7 @@ struct BatchAdjArgs {
   OrbitView orb_p, orb_t;
   const BatchAdjTemplate* tpl;  // [n_templates], caller's order
   const int64_t* items;         // [n_items][2]: template (TDI: pair), tile
+  const int64_t* sky_items;     // [n][2]: template, tile of kBlock link samples (sky kernel)
   const int64_t* pairs;         // [n_pairs][2]: caller indices, longer first, -1 = none
   double t_off_y;               // time of link sample 0 (= output index -F) minus the TDI grid's
   double dt, inv_dt;
@@ -59,7 +60,8 @@ struct BatchAdjArgs {
   double* g_y;
   double* g_hp;
   double* g_hc;
-  double* sky_part;             // [n_proj_items][2] or null
+  double* sky_part;             // [n_sky_items][2] or null
+  int rl_cap;                   // wave row capacity of the carry kernels (0: atomic kernels)
 };
 
 // Launchers (instantiated per tap count in batch_*.hip).
@@ -70,7 +72,8 @@ int fused_occupancy();
 template <int N, int GEN>
 hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
 template <int N>
-hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
+hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items,
+                                        int64_t n_sky_items, hipStream_t s);
 
 hipError_t run_fused_forward(int order, int gen, int group, const BatchFwdArgs& a, int blocks,
                              hipStream_t s);
@@ -78,6 +81,6 @@ int fused_blocks_per_cu(int order, int gen, int group);
 hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int64_t n_items,
                                  hipStream_t s);
 hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,
-                                     hipStream_t s);
+                                     int64_t n_sky_items, hipStream_t s);
 
 }  // namespace lr

@@ -97,9 +97,9 @@ hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int6
 }
 
 hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,
-                                     hipStream_t s) {
+                                     int64_t n_sky_items, hipStream_t s) {
   switch (order) {
-#define X(ORD, NT) case ORD: return launch_batch_project_adjoint<NT>(a, n_items, s);
+#define X(ORD, NT) case ORD: return launch_batch_project_adjoint<NT>(a, n_items, n_sky_items, s);
     LR_ORDER_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -40,6 +40,7 @@ struct TdiAdjArgs {
   double dt, inv_dt;
   int64_t out_start, n_out;
   double* g_y;          // [6][n_y], zero-filled before the launch
+  int rl_cap;           // wave row capacity of the carry kernel (even); 0: atomic kernel
 };
 
 struct ProjAdjArgs {
@@ -55,6 +56,7 @@ struct ProjAdjArgs {
   double* g_hp;         // [n_h], zero-filled before the launch
   double* g_hc;
   double* sky_part;     // [blocks][2] partial sky gradients, or null
+  int rl_cap;           // wave row capacity of the carry kernel (even); 0: atomic kernel
 };
 
 // Per-tap-count launchers (N = order + 1), instantiated in forward_*.hip.
@@ -70,6 +72,11 @@ hipError_t launch_project_adjoint(const ProjAdjArgs& a, hipStream_t s);
 
 // Records a formatted message for lr_last_error() and returns `status`.
 int set_error(int status, const char* fmt, ...);
+
+// Wave row capacity of the carry adjoint kernels for a delay spread of
+// `spread` seconds (rows per wave, concurrent carries, further doubles of LDS
+// per wave), or 0 if the rows do not fit LDS.
+int carry_row_capacity(int order, double spread, double dt, int rows, int ncarry, int extra);
 
 // Workgroup size of the tiled kernels (output samples per workgroup).
 constexpr int kTile = 256;

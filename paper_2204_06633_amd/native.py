@@ -325,7 +325,8 @@ class lr_batch(ctypes.Structure):
                 ("tile_out", ctypes.c_int), ("blocks", ctypes.c_int), ("adjoint", ctypes.c_int),
                 ("n_templates", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_tdi_items", ctypes.c_int64), ("n_proj_items", ctypes.c_int64),
-                ("n_like_items", ctypes.c_int64), ("gy_doubles", ctypes.c_int64),
+                ("n_like_items", ctypes.c_int64), ("n_tdi_citems", ctypes.c_int64),
+                ("n_padj_citems", ctypes.c_int64), ("gy_doubles", ctypes.c_int64),
                 ("h_extent", ctypes.c_int64), ("out_extent", ctypes.c_int64),
                 ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 16)]
 

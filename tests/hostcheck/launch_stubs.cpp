@@ -32,7 +32,7 @@ int fused_blocks_per_cu(int, int, int) { return 3; }
 hipError_t run_batch_tdi_adjoint(int, int, const BatchAdjArgs&, int64_t, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
-hipError_t run_batch_project_adjoint(int, const BatchAdjArgs&, int64_t, hipStream_t) {
+hipError_t run_batch_project_adjoint(int, const BatchAdjArgs&, int64_t, int64_t, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
 }  // namespace lr

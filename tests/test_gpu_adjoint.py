@@ -81,6 +81,64 @@ def test_project_adjoint_matches_oracle(torch_cuda, order):
     cases.check(np.stack([ghp.cpu().numpy(), ghc.cpu().numpy()]), np.stack([rhp, rhc]), TOL_ADJ)
 
 
+def test_adjoint_bitwise_reproducible(torch_cuda):
+    """The carry kernels sum every scatter in a fixed order and each global
+    entry receives at most two additions onto zero: two runs agree bit for
+    bit (TDI and projection adjoints, 200k samples)."""
+    from paper_2204_06633_amd import native
+    torch = torch_cuda
+    case = cases.make_case("repro", "keplerian", 200_000, 10.0, 25, 2, "AET", seed=17)
+    g = case.grid
+    tpl = _template(case)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    g_out = torch.randn((3, g.n_out), dtype=torch.float64, device="cuda", generator=gen)
+    ya = native.tdi_adjoint(tpl.orb_tdi, g.t0_h + g.y_start * g.dt, g.dt, g.n_y, 2, 25, "AET",
+                            g.out_start - g.y_start, g_out)
+    yb = native.tdi_adjoint(tpl.orb_tdi, g.t0_h + g.y_start * g.dt, g.dt, g.n_y, 2, 25, "AET",
+                            g.out_start - g.y_start, g_out)
+    sky = _t(torch, [case.lam, case.beta])
+    hp, hc = _t(torch, case.hp), _t(torch, case.hc)
+    pa = native.project_adjoint(tpl.orb_proj, g.t0_h, g.dt, g.n_h, hp, hc, sky, 25, g.y_start, ya)
+    pb = native.project_adjoint(tpl.orb_proj, g.t0_h, g.dt, g.n_h, hp, hc, sky, 25, g.y_start, ya)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    for x, y in zip(pa, pb):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("order", [5, 25])
+def test_adjoints_atomic_path_small_dt(torch_cuda, order):
+    """At dt = 0.01 s a wave's footprint (seven light times of TDI delays,
+    two of projection spread) no longer fits the LDS rows of the carry
+    kernels and the atomic kernels run: both transposes against the
+    oracle."""
+    from paper_2204_06633_amd import native
+    torch = torch_cuda
+    case = cases.make_case("tiny_dt", "keplerian", 700, 0.01, order, 2, "XYZ", seed=70 + order)
+    g = case.grid
+    tpl = _template(case)
+    rng = np.random.default_rng(order + 1)
+    g_out = rng.standard_normal((3, g.n_out))
+    t0_y = g.t0_h + g.y_start * g.dt
+    got = native.tdi_adjoint(tpl.orb_tdi, t0_y, g.dt, g.n_y, 2, order, "XYZ",
+                             g.out_start - g.y_start, _t(torch, g_out))
+    torch.cuda.synchronize()
+    orb = oracle.Orbits.from_samples(case.orbits_proj)
+    ref = oracle.tdi_adjoint(orb, t0_y, g.dt, g.n_y, 2, order,
+                             np.arange(g.out_start - g.y_start, g.out_start - g.y_start + g.n_out),
+                             g_out)
+    cases.check(got.cpu().numpy(), ref, TOL_ADJ, "tdi adjoint")
+    g_y = rng.standard_normal((6, g.n_y))
+    sky = _t(torch, [case.lam, case.beta])
+    ghp, ghc, _ = native.project_adjoint(tpl.orb_proj, g.t0_h, g.dt, g.n_h, None, None, sky,
+                                         order, g.y_start, _t(torch, g_y), want_sky=False)
+    torch.cuda.synchronize()
+    rhp, rhc = oracle.project_adjoint(orb, g.t0_h, g.dt, g.n_h, case.lam, case.beta, order,
+                                      np.arange(g.y_start, g.y_start + g.n_y), g_y)
+    cases.check(np.stack([ghp.cpu().numpy(), ghc.cpu().numpy()]), np.stack([rhp, rhc]), TOL_ADJ,
+                "projection adjoint")
+
+
 def test_adjoint_brute_force_transpose(torch_cuda):
     """Tiny grid: R built column by column from unit impulses (oracle), then
     R^T g against the GPU adjoint."""
