@@ -362,8 +362,8 @@ __device__ __forceinline__ void tdi_adjoint_carry_tile(const TdiAdjArgs (&a)[M],
       double ea, eb;
       const int sa = split_delay(row_delay(G, La), a0.inv_dt, ea);
       const int sb = split_delay(row_delay(G, Lb), a0.inv_dt, eb);
-      const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sa, sb)));
-      const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sa, sb)));
+      int s_lo, s_hi;
+      shift_range(sa, sb, s_lo, s_hi);
       const bool two = G.nuse == 2;                   // uniform
       for (int sg = s_lo; sg <= s_hi; ++sg) {
         double va[M], vb[M], A[M], B[M];
@@ -376,7 +376,7 @@ __device__ __forceinline__ void tdi_adjoint_carry_tile(const TdiAdjArgs (&a)[M],
           va[k] = sa == sg ? xa : 0.0;
           vb[k] = sb == sg ? xb : 0.0;
         }
-        carry_scatter<N, M>(ea, eb, va, vb, A, B, park, lane0);
+        carry_scatter<N, M, false>(ea, eb, va, vb, A, B, park, lane0);
         const int o = sg - (H - 1) - lo;
 #pragma unroll
         for (int k = 0; k < M; ++k) {
@@ -395,8 +395,8 @@ __device__ __forceinline__ void tdi_adjoint_carry_tile(const TdiAdjArgs (&a)[M],
       double ea, eb;
       const int sa = split_delay(row_delay(G, La), a0.inv_dt, ea);
       const int sb = split_delay(row_delay(G, Lb), a0.inv_dt, eb);
-      const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sa, sb)));
-      const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sa, sb)));
+      int s_lo, s_hi;
+      shift_range(sa, sb, s_lo, s_hi);
       for (int sg = s_lo; sg <= s_hi; ++sg) {
         double va[2 * M], vb[2 * M], A[2 * M], B[2 * M];
 #pragma unroll
@@ -410,7 +410,7 @@ __device__ __forceinline__ void tdi_adjoint_carry_tile(const TdiAdjArgs (&a)[M],
             va[2 * k + u] = sa == sg ? xa : 0.0;
             vb[2 * k + u] = sb == sg ? xb : 0.0;
           }
-        carry_scatter<N, 2 * M>(ea, eb, va, vb, A, B, park, lane0);
+        carry_scatter<N, 2 * M, false>(ea, eb, va, vb, A, B, park, lane0);
         const int o = sg - (H - 1) - lo;
 #pragma unroll
         for (int k = 0; k < M; ++k)
@@ -777,8 +777,8 @@ __device__ __forceinline__ void proj_carry_position(const ProjAdjArgs& a, const 
   double va[2], vb[2], ea, eb;
   const int sha = split_delay(proj_carry_pos<P>(sa, va[0], va[1]), a.inv_dt, ea);
   const int shb = split_delay(proj_carry_pos<P>(sb, vb[0], vb[1]), a.inv_dt, eb);
-  const int s_lo = __builtin_amdgcn_readfirstlane(wave_min(min(sha, shb)));
-  const int s_hi = __builtin_amdgcn_readfirstlane(wave_max(max(sha, shb)));
+  int s_lo, s_hi;
+  shift_range(sha, shb, s_lo, s_hi);
   // the streams' common scale goes into the values
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -792,7 +792,7 @@ __device__ __forceinline__ void proj_carry_position(const ProjAdjArgs& a, const 
       xa[c] = sha == sg ? va[c] : 0.0;
       xb[c] = shb == sg ? vb[c] : 0.0;
     }
-    carry_scatter<N, 2>(ea, eb, xa, xb, A, B, park, lane0);
+    carry_scatter<N, 2, false>(ea, eb, xa, xb, A, B, park, lane0);
     const int o = sg - (H - 1) - lo;
     carry_add<N>(rows, half, o, lane, 1.0, A[0], B[0], park);
     carry_add<N>(rows + rl_cap, half, o, lane, 1.0, A[1], B[1], park + (N - 1));

@@ -1,5 +1,5 @@
 // Batched adjoint kernels for tap counts 26, 28, 30, 32.
-#include "batch_kernels.hpp"
+#include "batch_adjoint_kernels.hpp"
 
 namespace lr {
 LR_INSTANTIATE_BATCH_ADJ(26)

@@ -34,6 +34,18 @@ __device__ __forceinline__ double lane_down(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Wave-uniform range [lo, hi] of the integer shifts of a wave's slots: one
+// ballot when they all agree (all but a few waves), else wave reductions.
+__device__ __forceinline__ void shift_range(int sa, int sb, int& lo, int& hi) {
+  const int s0 = __builtin_amdgcn_readfirstlane(sa);
+  if (__all(sa == s0 && sb == s0)) {
+    lo = hi = s0;
+    return;
+  }
+  lo = __builtin_amdgcn_readfirstlane(wave_min(min(sa, sb)));
+  hi = __builtin_amdgcn_readfirstlane(wave_max(max(sa, sb)));
+}
+
 // Parity-split position of element j in a row of (even) capacity cap: even
 // elements first, then odd ones.  Lanes that touch elements o + 2L and
 // o + 2L + 1 then read consecutive doubles in each half (no bank conflicts).
@@ -43,8 +55,10 @@ __device__ __forceinline__ int psplit(int j, int half) { return (j & 1) * half +
 // With NC == 1 the value is folded into the suffix products.  On return
 // A[c], B[c] hold the targets of slots 2L and 2L+1 (relative index
 // N - 1 + slot), and park[c * (N - 1) + j] (wave-private LDS) the target of
-// relative index j = 0..N-2.  The scale kScale is not applied.
-template <int N, int NC>
+// relative index j = 0..N-2.  The scale kScale is not applied.  KEEP_NU keeps
+// slot a's factors from the suffix pass for the prefix pass (N more
+// registers, two operations less per tap).
+template <int N, int NC, bool KEEP_NU>
 __device__ __forceinline__ void carry_scatter(double ea, double eb, const double (&va)[NC],
                                               const double (&vb)[NC], double (&A)[NC],
                                               double (&B)[NC], double* park, bool lane0) {
@@ -54,7 +68,7 @@ __device__ __forceinline__ void carry_scatter(double ea, double eb, const double
   // (they would stay live beside the suffix products)
   asm volatile("" : "+v"(ea), "+v"(eb));
   const double de = eb - ea;
-  double Sa[N], Sb[N];
+  double Sa[N], Sb[N], nu[N];
   Sa[N - 1] = NC == 1 ? va[0] : 1.0;
   Sb[N - 1] = NC == 1 ? vb[0] : 1.0;
   double d = ea + (double)(H - 1) - (double)(N - 1);   // eps_a - x_{N-1}
@@ -62,11 +76,13 @@ __device__ __forceinline__ void carry_scatter(double ea, double eb, const double
   for (int k = N - 1; k >= 1; --k) {
     const double na = S.s[k] * d;
     const double nb = fma(de, S.s[k], na);
+    if (KEEP_NU) nu[k] = na;
     Sa[k - 1] = Sa[k] * na;
     Sb[k - 1] = Sb[k] * nb;
     d += 1.0;
   }
   // d = eps_a - x_0
+  if (KEEP_NU) nu[0] = S.s[0] * d;
   double Pa = 1.0, Pb = 1.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) { A[c] = 0.0; B[c] = 0.0; }
@@ -90,23 +106,28 @@ __device__ __forceinline__ void carry_scatter(double ea, double eb, const double
       }
     }
     if (k < N - 1) {
-      const double na = S.s[k] * d;
+      const double na = KEEP_NU ? nu[k] : S.s[k] * d;
       const double nb = fma(de, S.s[k], na);
       Pa *= na;
       Pb *= nb;
-      d -= 1.0;
+      if (!KEEP_NU) d -= 1.0;
     }
   }
 }
 
 // Add a finished carry to a wave-private parity-split row: slots at
 // relative index o + N - 1 + 2L (+1), parked sums at o + j (lanes j < N-1).
+// o and half are wave-uniform, so both slot positions are a uniform offset
+// plus the lane.
 template <int N>
 __device__ __forceinline__ void carry_add(double* row, int half, int o, int lane, double f,
                                           double A, double B, const double* park) {
-  const int ja = o + N - 1 + 2 * lane;
-  row[psplit(ja, half)] += f * A;
-  row[psplit(ja + 1, half)] += f * B;
+  const int base = o + N - 1;
+  const int h0 = base >> 1;
+  const int pa = (base & 1) ? half + h0 : h0;             // element base + 2L
+  const int pb = (base & 1) ? h0 + 1 : half + h0;         // element base + 2L + 1
+  row[pa + lane] += f * A;
+  row[pb + lane] += f * B;
   if (lane < N - 1) row[psplit(o + lane, half)] += f * park[lane];
 }
 
