@@ -176,6 +176,23 @@ int lr_project_adjoint(const lr_orbits *orb, double t0_h, double dt, int64_t n_h
                        double *g_hc, double *g_sky, void *work, size_t work_bytes,
                        void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as lr_project_adjoint, with the sky-gradient partial sums kept in a static
+ * device array of lr_noalloc_scratch_bytes() bytes (1 MiB; one copy per GPU,
+ * held until the process ends) instead of a caller workspace.  The library
+ * allocates nothing.  With g_sky != NULL, n_y may be at most 16,777,216 link
+ * samples (65,536 tiles of 256); larger n_y returns LR_E_WORKSPACE before
+ * any launch.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (different streams, host threads) race; each
+ * call overwrites all the partial sums it reads.  The first call on a device
+ * looks up the array's device address (hipGetSymbolAddress). */
+size_t lr_noalloc_scratch_bytes(void);
+int lr_project_adjoint_noalloc(const lr_orbits *orb, double t0_h, double dt, int64_t n_h,
+                               const double *hp, const double *hc, const double *sky, int order,
+                               int64_t y_start, int64_t n_y, const double *g_y, double *g_hp,
+                               double *g_hc, double *g_sky, void *stream);
+
 /* ------------------------------------------------------------------------
  * White-noise likelihood, Sec. II.A eq. (like) with the channel sum of
  * Sec. IV.C, for noise of standard deviation sigma per sample and channel:

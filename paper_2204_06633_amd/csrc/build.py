@@ -20,7 +20,7 @@ SOURCES = (["forward_%s.hip" % k for k in "abcd"] + ["adjoint_%s.hip" % k for k 
            ["batchfwd%d_%s.hip" % (g, k) for g in (1, 2) for k in "abcd"] +
            ["batchadj_%s.hip" % k for k in "abcd"] +
            ["util.hip", "fd_kernels.hip", "gb_kernels.hip", "dispatch.cpp", "api.cpp", "api_batch.cpp",
-            "api_fd.cpp", "api_gb.cpp"])
+            "api_fd.cpp", "api_gb.cpp", "api_noalloc.hip"])
 ARCH = os.environ.get("LR_OFFLOAD_ARCH", "gfx950")
 
 

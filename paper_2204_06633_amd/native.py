@@ -74,9 +74,13 @@ def lib():
                                      vp, ctypes.c_size_t, vp]
     L.lr_loglike_workspace.restype = ctypes.c_size_t
     L.lr_loglike.argtypes = [vp, vp, i64, d, vp, vp, vp, ctypes.c_size_t, vp]
+    L.lr_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    L.lr_noalloc_scratch_bytes.argtypes = []
+    L.lr_project_adjoint_noalloc.argtypes = [po, d, d, i64, vp, vp, vp, i32, i64, i64, vp, vp, vp,
+                                             vp, vp]
     for name in ("lr_orbits_init", "lr_projection_padding", "lr_tdi_padding",
                  "lr_project_links", "lr_tdi_combine", "lr_tdi_adjoint", "lr_project_adjoint",
-                 "lr_loglike"):
+                 "lr_loglike", "lr_project_adjoint_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -282,6 +286,36 @@ def project_adjoint(orb: Orbits, t0_h, dt, n_h, hp, hc, sky, order, y_start, g_y
                                     work.numel() * 8 if want_sky else 0, _stream(stream)),
            "lr_project_adjoint")
     return g_hp, g_hc, g_sky
+
+
+def project_adjoint_noalloc(orb: Orbits, t0_h, dt, n_h, hp, hc, sky, order, y_start, g_y,
+                            g_hp, g_hc, g_sky=None, stream=None):
+    """lr_project_adjoint_noalloc: project_adjoint with caller-provided outputs
+    and the sky-gradient partial sums in the library's static device
+    scratch (no allocation by the library).  g_sky is optional."""
+    if g_y.dim() != 2 or g_y.shape[0] != 6:
+        raise ValueError("g_y must be [6][n_y], got shape %s" % (tuple(g_y.shape),))
+    n_y = g_y.shape[-1]
+    _size(hp, "hp", numel=n_h)
+    _size(hc, "hc", numel=n_h)
+    _size(sky, "sky", numel=2)
+    _size(g_hp, "g_hp", numel=n_h)
+    _size(g_hc, "g_hc", numel=n_h)
+    _size(g_sky, "g_sky", numel=2)
+    _same_device(("g_y", g_y), ("hp", hp), ("hc", hc), ("sky", sky), ("g_hp", g_hp),
+                 ("g_hc", g_hc), ("g_sky", g_sky))
+    _check(lib().lr_project_adjoint_noalloc(orb.ref, float(t0_h), float(dt), int(n_h),
+                                            _opt(hp, "hp"), _opt(hc, "hc"), _dev(sky, "sky"),
+                                            int(order), int(y_start), int(n_y), _dev(g_y, "g_y"),
+                                            _dev(g_hp, "g_hp"), _dev(g_hc, "g_hc"),
+                                            _opt(g_sky, "g_sky"), _stream(stream)),
+           "lr_project_adjoint_noalloc")
+    return g_hp, g_hc, g_sky
+
+
+def noalloc_scratch_bytes():
+    """Bytes of the static device scratch behind the *_noalloc entry points."""
+    return int(lib().lr_noalloc_scratch_bytes())
 
 
 def loglike(h, data, sigma, want_grad=True, out=None, g_h=None, work=None, stream=None):
