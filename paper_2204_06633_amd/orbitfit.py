@@ -15,6 +15,12 @@
   orbits.
 * ``configurations``: the four orbit pairings of Sec. V for (projection,
   TDI): ESA, EQ, ESAEQ and EQESA, "ESA" standing for the accurate orbits.
+* ``fitting_factor``: the Sec. II.A fitting factor, the overlap between the
+  data and the template at the maximum of the likelihood, the maximum found
+  by Nelder-Mead in the sampling coordinates from a starting point (the
+  paper finds it with its sampler); ``TemplateScorer`` evaluates one
+  template on the GPU (HIP polarisations, response with any orbit pairing,
+  frequency-domain statistics against the data).
 
 Host code: orbit fitting runs once per analysis, on coarse orbit samples.
 """
@@ -95,3 +101,85 @@ def overlap_statistics(stats, ss):
     overlap = rho_ex / math.sqrt(ss)
     return {"rho_opt": rho_opt, "rho_ex": rho_ex, "overlap": overlap, "mismatch": 1.0 - overlap,
             "loglike": -0.5 * st[..., 0]}
+
+
+def fitting_factor(score, theta0, step, maxfev=4000, xatol=1e-12, fatol=1e-10):
+    """Fitting factor (Sec. II.A): maximise the log-likelihood over the
+    template parameters, then report the overlap there.
+
+    ``score(theta) -> (loglike, overlap)`` for one parameter vector;
+    ``theta0``: start (e.g. the injection); ``step``: the initial simplex
+    edge per parameter.  Returns dict(theta, loglike, fitting_factor,
+    loglike_start, overlap_start, nfev)."""
+    from scipy.optimize import minimize
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    step = np.asarray(step, dtype=np.float64)
+    cache = {}
+
+    def neg(th):
+        key = tuple(np.asarray(th, dtype=np.float64))
+        if key not in cache:
+            cache[key] = score(np.asarray(th, dtype=np.float64))
+        ll = cache[key][0]
+        return -ll if np.isfinite(ll) else np.inf
+
+    ll0, ov0 = score(theta0)
+    simplex = np.vstack([theta0] + [theta0 + step[i] * np.eye(len(theta0))[i]
+                                    for i in range(len(theta0))])
+    res = minimize(neg, theta0, method="Nelder-Mead",
+                   options={"maxfev": maxfev, "xatol": xatol, "fatol": fatol,
+                            "initial_simplex": simplex, "adaptive": True})
+    best = np.asarray(res.x, dtype=np.float64)
+    if -res.fun < ll0:                     # the start is never worse than the result
+        best = theta0
+    ll, ov = score(best)
+    return {"theta": best, "loglike": float(ll), "fitting_factor": float(ov),
+            "loglike_start": float(ll0), "overlap_start": float(ov0), "nfev": int(res.nfev)}
+
+
+class TemplateScorer:
+    """(log L, overlap) of one Galactic-binary template against fixed data on
+    the GPU: lr_gb_polarizations -> lr_project_links / lr_tdi_combine (any
+    projection and TDI orbits) -> lr_fd_loglike statistics.  ``theta`` in the
+    sampler's coordinates (sampler.to_source).  ``ss`` = <s|s> of the data."""
+
+    def __init__(self, orb_proj, orb_tdi, grid, data, w_ae, w_t, order=25, generation=2,
+                 device="cuda"):
+        import torch
+
+        from . import native, response
+        self.torch = torch
+        self.tpl = response.Template(orb_proj, orb_tdi, grid, order, generation, "AET")
+        self.grid = grid
+        self.plan = native.FdPlan(data, w_ae, w_t, grid.dt)
+        self.out = torch.empty((3, grid.n_out), dtype=torch.float64, device=device)
+        self.y = torch.empty((6, grid.n_y), dtype=torch.float64, device=device)
+        self.stats = torch.empty((1, 3), dtype=torch.float64, device=device)
+        self.hp = torch.empty((1, grid.n_h), dtype=torch.float64, device=device)
+        self.hc = torch.empty_like(self.hp)
+        self.device = device
+        self.ss = None
+        self.stats_of(None)   # <s|s> from a zero template: rr = <s|s>
+
+    def stats_of(self, theta):
+        from . import native, response, sampler
+        torch = self.torch
+        g = self.grid
+        if theta is None:
+            self.out.zero_()
+        else:
+            src = sampler.to_source(torch.as_tensor(theta, dtype=torch.float64,
+                                                    device=self.device)[None]).contiguous()
+            native.gb_polarizations(src, -g.out_start, g.n_h, g.dt, hp=self.hp, hc=self.hc)
+            response.plain_forward(self.tpl, self.hp[0], self.hc[0], src[0, 6:8].contiguous(),
+                                   y=self.y, out=self.out)
+        self.plan.loglike(self.out, want_grad=False, stats=self.stats)
+        st = self.stats[0].cpu().numpy()
+        if theta is None:
+            self.ss = float(st[0])
+        return st
+
+    def __call__(self, theta):
+        rr, hh, sh = self.stats_of(theta)
+        ov = sh / math.sqrt(hh * self.ss) if hh > 0 else 0.0
+        return -0.5 * rr, ov

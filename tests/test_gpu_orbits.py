@@ -71,3 +71,56 @@ def test_orbit_configurations_match_oracle(torch_cuda):
         assert abs(got["mismatch"][k] - ref["mismatch"]) <= 1e-10
     assert abs(got["mismatch"][0]) <= 1e-14
     assert np.all(got["mismatch"][1:] > 1e-9)              # the approximations lose overlap
+
+
+def test_fitting_factor_of_the_orbit_models(torch_cuda):
+    """Sec. II.A fitting factor: the likelihood maximised (Nelder-Mead from
+    the injection) for templates with each orbit model against noise-free
+    data from the accurate orbits.  The accurate model is the control
+    (fitting factor 1); the approximations fall below 1.  At the parameters
+    the GPU found, the oracle's response and inner products give the same
+    overlap (the evaluation pinned; the optimiser is pinned on the host)."""
+    torch = torch_cuda
+    import oracle
+    from oracle import fd as ofd
+    from oracle import waveform as owf
+    from paper_2204_06633_amd import inputs, native, orbitfit, response, sampler, workloads
+    c = workloads.orbit_config_case(int(0.05 * inputs.YEAR / 10.0), 10.0)
+    g = c.grid
+    dev = torch.device("cuda")
+    gpu_orb = {"acc": native.Orbits.from_samples(c.accurate),
+               "eq": native.Orbits.from_samples(c.equal_arm)}
+    cpu_orb = {"acc": oracle.Orbits.from_samples(c.accurate),
+               "eq": oracle.Orbits.from_samples(c.equal_arm)}
+    lam, beta = c.params[6], c.params[7]
+    tpl = response.Template(gpu_orb["acc"], gpu_orb["acc"], g, c.order, c.generation, "AET")
+    data, _ = response.plain_forward(tpl, torch.tensor(c.hp, device=dev),
+                                     torch.tensor(c.hc, device=dev),
+                                     torch.tensor([lam, beta], dtype=torch.float64, device=dev))
+    n_fft = native.fd_length(g.n_out)
+    w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
+    wd = torch.tensor(w_ae, device=dev), torch.tensor(w_t, device=dev)
+    th0 = sampler.to_theta(torch.tensor(c.params)).numpy()
+    step = np.array([1e-3, 1e-6, 1e-18, 1e-3, 1e-3, 1e-3, 1e-4, 1e-4])
+    s_ref = oracle.response(cpu_orb["acc"], cpu_orb["acc"], g, c.hp, c.hc, lam, beta, c.order,
+                            c.generation, "AET")
+    for name, maxfev in (("ESA", 300), ("EQ", 2500)):
+        p, t = orbitfit.configurations("acc", "eq")[name]
+        sc = orbitfit.TemplateScorer(gpu_orb[p], gpu_orb[t], g, data, *wd, order=c.order)
+        r = orbitfit.fitting_factor(sc, th0, step, maxfev=maxfev)
+        print("%-4s fitting factor %.12f (overlap at the injection %.12f), log L %.6e -> %.6e, "
+              "%d evaluations" % (name, r["fitting_factor"], r["overlap_start"],
+                                  r["loglike_start"], r["loglike"], r["nfev"]), flush=True)
+        assert r["loglike"] >= r["loglike_start"]
+        assert r["fitting_factor"] <= 1.0 + 1e-12
+        src = sampler.to_source(torch.tensor(r["theta"])).numpy()
+        hp, hc = owf.polarizations(src, g.waveform_times())
+        h_ref = oracle.response(cpu_orb[p], cpu_orb[t], g, hp, hc, src[6], src[7], c.order,
+                                c.generation, "AET")
+        ref = ofd.overlap(h_ref, s_ref, w_ae, w_t, g.dt, n_fft)
+        assert abs(r["fitting_factor"] - ref["overlap"]) <= 1e-10, (r["fitting_factor"], ref)
+        if name == "ESA":
+            assert abs(r["fitting_factor"] - 1.0) <= 1e-10
+        else:
+            assert r["fitting_factor"] < 1.0 - 1e-12
+            assert r["fitting_factor"] >= r["overlap_start"] - 1e-9

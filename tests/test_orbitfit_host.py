@@ -79,3 +79,34 @@ def test_overlap_statistics_against_oracle():
     # Cauchy-Schwarz: overlap <= 1, equality for h = s (and any positive multiple)
     same = ofd.overlap(2.0 * s, s, w_ae, w_t, dt, n_fft)
     assert abs(same["mismatch"]) < 1e-14 and 0 < ref["mismatch"] < 1
+
+
+def test_fitting_factor_finds_the_likelihood_maximum():
+    """A closed-form score: log L = -1/2 (x - x*)^T Q (x - x*) with the maximum
+    off the start, overlap = exp(-|x - x_o|^2) peaking elsewhere.  The fitting
+    factor is the overlap at the likelihood maximum x* (Sec. II.A), not the
+    largest overlap."""
+    rng = np.random.default_rng(1)
+    D = 8
+    a = rng.standard_normal((D, D))
+    Q = a @ a.T + D * np.eye(D)
+    x_star = rng.standard_normal(D) * 0.3
+    x_o = x_star + 0.2
+
+    def score(x):
+        d = x - x_star
+        return -0.5 * float(d @ Q @ d), math.exp(-float(np.sum((x - x_o) ** 2)))
+
+    r = orbitfit.fitting_factor(score, np.zeros(D), np.full(D, 0.1), maxfev=20000)
+    assert np.max(np.abs(r["theta"] - x_star)) < 1e-6
+    assert abs(r["fitting_factor"] - math.exp(-float(np.sum((x_star - x_o) ** 2)))) < 1e-9
+    assert r["loglike"] >= r["loglike_start"]
+
+
+def test_fitting_factor_at_the_start_when_it_is_the_maximum():
+    """Data equal to the template at the start: the start is the likelihood
+    maximum and the fitting factor is the overlap there (1)."""
+    x0 = np.array([0.3, -1.0, 2.0])
+    score = lambda x: (-float(np.sum((x - x0) ** 2)), 1.0 / (1.0 + float(np.sum((x - x0) ** 2))))
+    r = orbitfit.fitting_factor(score, x0, np.full(3, 0.05))
+    assert abs(r["fitting_factor"] - 1.0) < 1e-12 and np.max(np.abs(r["theta"] - x0)) < 1e-6
