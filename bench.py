@@ -148,8 +148,8 @@ def bench_headline(steps, warmup, keep):
     tpl = bc.layout.templates()
     batch, tuned = autotune.tuned_batch(tpl, orb, orb, bc.t0, bc.dt, bc.order, bc.generation,
                                         bc.channels, hp, hc, sky)
-    log("autotuned: group %d, grid x%.1f (%d work-groups)" % (tuned["group"],
-                                                             tuned["grid_scale"], batch.blocks))
+    log("autotuned: group %d, tile %d, grid x%.1f (%d work-groups)"
+        % (tuned["group"], batch.tile, tuned["grid_scale"], batch.blocks))
     out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
     graph = _capture(lambda: batch.response(hp, hc, sky, out=out))
     for _ in range(warmup):
@@ -188,7 +188,7 @@ def bench_headline(steps, warmup, keep):
     ops = costs.lane_ops_fused_forward(bc.grids, bc.order, bc.generation, group)
     nbytes = costs.batch_bytes(bc.grids, 3)
     traffic = recorded_traffic("fused_forward_batch512", FUSED_SOURCES)
-    kernel = "fused_forward_kernel<26,2,%d>" % group
+    kernel = "fused_forward_kernel<26,2,%d,%d>" % (group, batch.tile // 2)
     roof = _roofline(ops, ms_launch, kernel, traffic, nbytes)
     roof["note"] = ("mean HIP-event time of the graph replay on the launch stream (the "
                     "counter reset kernel, ~2 us, and the fused kernel)")
@@ -203,7 +203,8 @@ def bench_headline(steps, warmup, keep):
     del graph, out, hp, hc
     res = {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
            "value": rate, "ms_per_step": ms_step, "ms_per_launch_events": ms_launch,
-           "group": group, "grid_scale": tuned["grid_scale"], "blocks": batch.blocks,
+           "group": group, "tile": batch.tile, "grid_scale": tuned["grid_scale"],
+           "blocks": batch.blocks,
            "roofline": roof,
            "plain_per_template": {"value": plain_rate, "unit": UNIT, "templates_timed": len(pick),
                                   "time_samples": n_plain, "ms": ms_plain,
@@ -216,6 +217,10 @@ def bench_headline(steps, warmup, keep):
 # ---------------------------------------------------------------------------
 
 def bench_walkers(steps, warmup, keep):
+    """256 one-year walkers at dt = 15 s in waveform mode: each walker's h+ /
+    hx synthesised inside the fused kernel from its 8 source parameters
+    (lr_response_gb), the A/E/T likelihood, and the adjoint down to the 8
+    parameters (lr_response_adjoint_gb): no h or h-gradient arrays."""
     import torch
 
     from paper_2204_06633_amd import autotune, costs, native, workloads
@@ -224,18 +229,18 @@ def bench_walkers(steps, warmup, keep):
     log("walkers: %s, %d walkers, %d samples" % (bc.name, len(bc.grids), bc.n_samples))
     orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     orb_t = native.Orbits.from_samples(bc.orbits_tdi, device=dev)
-    hp, hc = workloads.device_polarizations(bc, dev)
-    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    params = torch.tensor(bc.params, dtype=torch.float64, device=dev).contiguous()
     tpl = bc.layout.templates()
     tuned = autotune.tune(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
-                          hp, hc, sky)
+                          None, None, None, params=params)
     batch = native.Batch(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
-                         group=tuned["group"], adjoint=True, device=dev)
+                         group=tuned["group"], tile=tuned.get("tile", 0), adjoint=True,
+                         device=dev)
     batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
     out = torch.empty(batch.out_extent, dtype=torch.float64, device=dev)
     # data: walker 0's response plus white noise (sigma = 1e-21), one copy per
     # walker block
-    batch.response(hp, hc, sky, out=out)
+    batch.response_gb(params, out=out)
     sigma = 1e-21
     gen = torch.Generator(device=dev)
     gen.manual_seed(5)
@@ -245,45 +250,41 @@ def bench_walkers(steps, warmup, keep):
     del one
     ll = torch.empty(batch.n, dtype=torch.float64, device=dev)
     g_out = torch.empty_like(out)
-    ghp = torch.empty(batch.h_extent, dtype=torch.float64, device=dev)
-    ghc = torch.empty_like(ghp)
-    gsky = torch.empty((batch.n, 2), dtype=torch.float64, device=dev)
+    g_par = torch.empty_like(params)
 
     def step():
-        batch.response(hp, hc, sky, out=out)
+        batch.response_gb(params, out=out)
         batch.loglike(out, data, sigma, ll=ll, g_out=g_out)
-        batch.adjoint(hp, hc, sky, g_out, g_hp=ghp, g_hc=ghc, g_sky=gsky)
+        batch.adjoint_gb(params, g_out, g_params=g_par)
 
     graph = _capture(step)
     ms = _timed(graph.replay, steps, warmup)
-    ms_fwd = _timed(lambda: batch.response(hp, hc, sky, out=out), steps, 1)
+    ms_fwd = _timed(lambda: batch.response_gb(params, out=out), steps, 1)
     ms_like = _timed(lambda: batch.loglike(out, data, sigma, ll=ll, g_out=g_out), steps, 1)
-    ms_adj = _timed(lambda: batch.adjoint(hp, hc, sky, g_out, g_hp=ghp, g_hc=ghc, g_sky=gsky),
-                    steps, 1)
+    ms_adj = _timed(lambda: batch.adjoint_gb(params, g_out, g_params=g_par), steps, 1)
     n = bc.n_samples
-    finite = bool(torch.isfinite(ll).all()) and bool(torch.isfinite(gsky).all())
+    finite = bool(torch.isfinite(ll).all()) and bool(torch.isfinite(g_par).all())
     ops = costs.lane_ops_fwd_adjoint(bc.grids, bc.order, bc.generation, tuned["group"], 2)
     ops_adj = ops - costs.lane_ops_fused_forward(bc.grids, bc.order, bc.generation,
                                                  tuned["group"])
-    nbytes = costs.fwd_adjoint_step_bytes(bc.grids, 3)
+    nbytes = costs.fwd_adjoint_step_bytes_gb(bc.grids, 3)
     for k in keep:
         g = bc.grids[k]
-        ho = bc.layout.h_offsets[k]
-        keep[k] = dict(hp=hp[ho:ho + g.n_h].cpu().numpy(), hc=hc[ho:ho + g.n_h].cpu().numpy(),
-                       out=batch.output_block(out, k).cpu().numpy())
-    del graph, out, data, g_out, ghp, ghc, hp, hc
+        keep[k] = dict(params=bc.params[k], out=batch.output_block(out, k).cpu().numpy())
+    del graph, out, data, g_out
     return {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
             "value": 6.0 * n / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms,
-            "steps": steps, "graph": True, "group": tuned["group"],
+            "steps": steps, "graph": True, "group": tuned["group"], "tile": batch.tile,
             "stage_ms": {"forward": ms_fwd, "likelihood": ms_like, "adjoint": ms_adj},
             "step_over_forward": ms / ms_fwd, "gradients_finite": finite,
-            "roofline": _roofline(ops, ms, "whole step (fused forward, likelihood, TDI "
-                                           "adjoint, projection adjoint, sky gradient)",
-                                  None, nbytes),
-            "roofline_adjoint": _roofline(ops_adj, ms_adj, "lr_response_adjoint (all its "
+            "roofline": _roofline(ops, ms, "whole step (fused forward with in-kernel waveform, "
+                                           "likelihood, TDI adjoint, projection adjoint to the "
+                                           "parameter sums, sky gradient)", None, nbytes),
+            "roofline_adjoint": _roofline(ops_adj, ms_adj, "lr_response_adjoint_gb (all its "
                                                            "kernels)"),
-            "step": "lr_response -> lr_batch_loglike (A/E/T, sigma 1e-21) -> "
-                    "lr_response_adjoint (g_h+, g_hx, g_sky) in one HIP graph"}, bc
+            "step": "lr_response_gb -> lr_batch_loglike (A/E/T, sigma 1e-21) -> "
+                    "lr_response_adjoint_gb (d log L / d 8 source parameters per walker) in "
+                    "one HIP graph; no h+/hx or h-gradient arrays"}, bc
 
 
 # ---------------------------------------------------------------------------
@@ -388,6 +389,7 @@ def bench_single_template(steps):
 # ---------------------------------------------------------------------------
 
 def bench_widened(steps, st):
+    import numpy as np
     import torch
 
     from paper_2204_06633_amd import costs, inputs, native, orbitfit, response, waveform, \
@@ -456,12 +458,29 @@ def bench_widened(steps, st):
     ms_orb = _timed(orbit_step, max(3, steps // 4), 1)
     oc_st = oc_stats.cpu().numpy()
     oc_diag = orbitfit.overlap_statistics(oc_st, ss=oc_st[0, 1])
+    # fitting factor (Sec. II.A): Nelder-Mead on the GPU likelihood from the
+    # injection, per approximate orbit model, against the accurate-orbit data
+    from paper_2204_06633_amd import sampler as smp
+    th0 = smp.to_theta(torch.tensor(oc.params)).numpy()
+    step = np.array([1e-3, 1e-6, 1e-18, 1e-3, 1e-3, 1e-3, 1e-4, 1e-4])
+    ff = {}
+    t_ff = time.perf_counter()
+    for name in ("EQ", "ESAEQ", "EQESA"):
+        p, t = oc_cfg[name]
+        sc = orbitfit.TemplateScorer(oc_orb[p], oc_orb[t], oc.grid, oc_h[0].clone(), w_ae_d,
+                                     w_t_d, order=oc.order)
+        r = orbitfit.fitting_factor(sc, th0, step, maxfev=1500)
+        ff[name] = {"fitting_factor": r["fitting_factor"], "overlap_at_injection":
+                    r["overlap_start"], "loglike_at_injection": r["loglike_start"],
+                    "loglike_at_maximum": r["loglike"], "evaluations": r["nfev"]}
+        del sc
     res["orbit_models"] = {
         "ms_per_step": ms_orb, "eq_fit_lam1_m1": list(oc.eq_params),
         "step": "4 templates (orbit models) forward + frequency-domain statistics against the "
                 "accurate-orbit data, 1 yr",
         "mismatch": {k: float(oc_diag["mismatch"][i]) for i, k in enumerate(oc_names)},
-        "rho_opt": {k: float(oc_diag["rho_opt"][i]) for i, k in enumerate(oc_names)}}
+        "rho_opt": {k: float(oc_diag["rho_opt"][i]) for i, k in enumerate(oc_names)},
+        "fitting_factor": ff, "fitting_factor_seconds": time.perf_counter() - t_ff}
     del oc_plan, oc_h, oc_y, oc_orb
 
     # the differentiation step: the paper's Fig. 3 binary, data = injection +
@@ -593,6 +612,7 @@ def cpu_baseline(c3, c3_keep, c5, c5_keep, target_s):
 
     import oracle
     from oracle import compare
+    from oracle import waveform as owf
     from paper_2204_06633_amd import workloads
     cores = oracle.max_threads()
     res = {"kind": "oracle", "cores": cores, "cpu_model": _cpu_model(), "unit": UNIT,
@@ -605,8 +625,12 @@ def cpu_baseline(c3, c3_keep, c5, c5_keep, target_s):
         cs = []
         for k, v in keep.items():
             g = bc.grids[k]
+            if "hp" in v:
+                hp, hc = v["hp"], v["hc"]
+            else:                                   # waveform mode: the oracle's own waveform
+                hp, hc = owf.polarizations(np.asarray(v["params"]), g.waveform_times())
             cs.append((k, workloads.Case("t%d" % k, bc.orbits_proj, bc.orbits_tdi, g,
-                                         bc.params[k], v["hp"], v["hc"], bc.order,
+                                         bc.params[k], hp, hc, bc.order,
                                          bc.generation, bc.channels), v["out"]))
         return op, ot, cs
 

@@ -232,29 +232,34 @@ typedef struct {
     double t0, dt;
     int order, generation, channels, group;
     int front, tile_out, blocks, adjoint;
+    int tile, reserved;  /* link samples per forward work item; padding */
     int64_t n_templates, n_items, n_tdi_items, n_proj_items, n_like_items;
     int64_t n_tdi_citems, n_padj_citems;
     int64_t gy_doubles, h_extent, out_extent;
     void *ws;
-    size_t off[16];      /* workspace region offsets (bytes) */
+    size_t off[24];      /* workspace region offsets (bytes) */
 } lr_batch;
 
 /* Device workspace bytes for a batch.  With adjoint != 0 it includes the
  * link-gradient scratch of lr_response_adjoint (6 values per link sample of
  * every template). */
 size_t lr_batch_workspace(const lr_template *t, int64_t n, const lr_orbits *tdi, double dt,
-                          int order, int generation, int channels, int group, int adjoint);
+                          int order, int generation, int channels, int group, int tile,
+                          int adjoint);
 
 /* Validate a batch (per-template padding from lr_projection_padding /
  * lr_tdi_padding, orbit coverage, output blocks), build the work lists and
  * copy them into ws (synchronises `stream` once; call it outside graph
  * capture).  t: [host][n]; group = templates per work item (1, 2 or 4);
- * t0: absolute time of output sample 0.  Errors: LR_E_ARG, LR_E_RANGE,
- * LR_E_UNSUPPORTED (dt so small that the TDI stencil does not fit a tile),
+ * tile = link samples per forward work item (256, 512 or 1024, not 1024
+ * with group 4; 0 = 512): the autotuner's tile-length knob; results do not
+ * depend on group, tile or grid.  t0: absolute time of output sample 0.
+ * Errors: LR_E_ARG, LR_E_RANGE, LR_E_UNSUPPORTED (dt so small that the TDI
+ * stencil does not fit a tile, or an uncompiled group/tile pair),
  * LR_E_WORKSPACE, LR_E_HIP. */
 int lr_batch_prepare(const lr_template *t, int64_t n, const lr_orbits *proj,
                      const lr_orbits *tdi, double t0, double dt, int order, int generation,
-                     int channels, int group, int adjoint, void *ws, size_t ws_bytes,
+                     int channels, int group, int tile, int adjoint, void *ws, size_t ws_bytes,
                      lr_batch *out, void *stream);
 
 /* Forward response of every template (Sec. IV.B-IV.C): hp, hc hold the
@@ -266,6 +271,18 @@ int lr_batch_prepare(const lr_template *t, int64_t n, const lr_orbits *proj,
  * LR_E_HIP (launch). */
 int lr_response(const lr_batch *b, const double *hp, const double *hc, const double *sky,
                 double *out, void *stream);
+
+/* lr_response with h+ and hx synthesised inside the fused kernel (each work
+ * item writes the Galactic-binary waveform of Sec. III straight into its LDS
+ * window) from parameter rows instead of read from HBM: params device [n][8]
+ * = (A, f0, fdot, phi0, iota, psi, lam, beta) in the caller's order, sky
+ * angles included.  Template k's h sample j (j in [0, n_h)) is the waveform
+ * at t = (j - out_start) dt: waveform time 0 at output sample 0, the
+ * convention of lr_gb_polarizations with k0 = -out_start.  Bit for bit equal
+ * to lr_gb_polarizations followed by lr_response.  The templates' h_offset is
+ * not used; the batch needs no h arrays.  Graph-capturable.  Errors:
+ * LR_E_ARG, LR_E_HIP. */
+int lr_response_gb(const lr_batch *b, const double *params, double *out, void *stream);
 
 /* Transpose of lr_response (needs a batch prepared with adjoint != 0):
  * g_out laid out like out; g_hp, g_hc like hp, hc over [0, h_extent),
@@ -280,6 +297,21 @@ int lr_response(const lr_batch *b, const double *hp, const double *hc, const dou
 int lr_response_adjoint(const lr_batch *b, const double *hp, const double *hc,
                         const double *sky, const double *g_out, double *g_hp, double *g_hc,
                         double *g_sky, void *stream);
+
+/* Transpose of lr_response_gb down to the source parameters: g_params
+ * device [n][8] receives d<g_out, out>/d(A, f0, fdot, phi0, iota, psi, lam,
+ * beta) for every template (zeros for an empty one), g_out laid out like
+ * out.  The TDI and projection adjoints run as in lr_response_adjoint, but
+ * each projection tile turns its share of the h+/hx gradient straight into
+ * the seven parameter-gradient sums of the waveform (Sec. III) and the sky
+ * tiles synthesise h from the parameters, so no h or h-gradient arrays
+ * exist; per-template sums are reduced in tile order (deterministic).
+ * Needs a batch prepared with adjoint != 0.  Graph-capturable.  Errors:
+ * LR_E_WORKSPACE (no adjoint workspace), LR_E_ARG, LR_E_UNSUPPORTED (dt so
+ * small, below about L/50, that the projection footprints do not fit LDS),
+ * LR_E_HIP. */
+int lr_response_adjoint_gb(const lr_batch *b, const double *params, const double *g_out,
+                           double *g_params, void *stream);
 
 /* Per-template white-noise log-likelihood (as lr_loglike, Sec. II.A) of a
  * batch output: data laid out like out; loglike device [n] (0 for an empty

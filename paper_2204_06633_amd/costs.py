@@ -150,3 +150,11 @@ def fwd_adjoint_step_bytes(grids, rows=3):
     data and writes their gradient; the adjoint reads that gradient and
     h+, hx (for the sky gradient) and writes the gradients of h+ and hx."""
     return sum(48.0 * g.n_h + 8.0 * rows * 5 * g.n_out for g in grids if g.n_out > 0)
+
+
+def fwd_adjoint_step_bytes_gb(grids, rows=3):
+    """The same step in waveform mode (h synthesised in the kernels from the
+    parameters): the forward writes the channels; the likelihood reads them
+    and the data and writes their gradient; the adjoint reads that gradient.
+    No h+, hx or h-gradient traffic."""
+    return sum(8.0 * rows * 4 * g.n_out for g in grids if g.n_out > 0)

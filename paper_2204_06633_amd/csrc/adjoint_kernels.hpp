@@ -237,6 +237,7 @@ constexpr int kCarryTile = 4 * kCarrySlots;   // sources per workgroup (4 waves)
 struct CarryShared {
   int lo[kBlock / 64];    // per wave: relative index of its row element 0
   int rl[kBlock / 64];    // per wave: row length in use (0: wave took the global path)
+  double gb[7][kBlock / 64];   // waveform mode: per-wave parameter-gradient sums
 };
 
 // Doubles of dynamic LDS of a carry tile: per wave R rows of rl_cap plus
@@ -279,6 +280,42 @@ __device__ __forceinline__ void carry_fold(const double* lds, int rl_cap, const 
       const int64_t j = gbase + e;
       if (j >= 0 && j < n) atomicAdd(g + j, s);
     }
+  }
+}
+
+// The tile's footprint as values instead of global additions: for every
+// relative index with global index j = gbase + e in [0, n), fn(j, v) gets
+// the NROWS row sums (waves summed in wave order).  Each lane visits its own
+// subset of entries.
+template <int NROWS, class Fn>
+__device__ __forceinline__ void carry_fold_values(const double* lds, int rl_cap,
+                                                  const CarryShared& cs, int64_t gbase, int64_t n,
+                                                  const Fn& fn) {
+  constexpr int W = kBlock / 64;
+  const int half = rl_cap / 2;
+  int lo_min = 1 << 30, hi_max = -(1 << 30);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    if (cs.rl[w] == 0) continue;
+    lo_min = min(lo_min, kCarrySlots * w + cs.lo[w]);
+    hi_max = max(hi_max, kCarrySlots * w + cs.lo[w] + cs.rl[w] - 1);
+  }
+  for (int e = lo_min + (int)threadIdx.x; e <= hi_max; e += kBlock) {
+    const int64_t j = gbase + e;
+    if (j < 0 || j >= n) continue;
+    double v[NROWS];
+#pragma unroll
+    for (int r = 0; r < NROWS; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int idx = e - kCarrySlots * w - cs.lo[w];
+        if (idx >= 0 && idx < cs.rl[w])
+          s += lds[((size_t)w * NROWS + r) * rl_cap + psplit(idx, half)];
+      }
+      v[r] = s;
+    }
+    fn(j, v);
   }
 }
 
@@ -611,11 +648,13 @@ __device__ __forceinline__ void project_sky_tile(const ProjAdjArgs& a, int64_t t
   const int64_t hmax = a.n_h - 1;
 
   double hv[2][9], dh[2][9];
+  const HSource hs = a.params ? HSource::waveform(a.params, a.k0, a.dt, a.n_h)
+                              : HSource::arrays(a.hp, a.hc, a.n_h);
   if (count > 0 && count <= CAP) {
     for (int k = tid; k < count; k += kBlock) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > hmax ? hmax : j);
-      win[k] = make_double2(a.hp[j], a.hc[j]);
+      win[k] = hs.at(j);
     }
     __syncthreads();
 #pragma unroll
@@ -645,8 +684,9 @@ __device__ __forceinline__ void project_sky_tile(const ProjAdjArgs& a, int64_t t
         int64_t j = j0 + m;
         j = j < 0 ? 0 : (j > hmax ? hmax : j);
         const double c = st.coef(m), cd = st.coef_d(m);
-        st.step(c, cd, a.hp[j], sp, dsp);
-        st.step(c, cd, a.hc[j], sc, dsc);
+        const double2 hj = hs.at(j);
+        st.step(c, cd, hj.x, sp, dsp);
+        st.step(c, cd, hj.y, sc, dsc);
         st.next();
       }
       hv[0][p] = sp; hv[1][p] = sc;
@@ -864,7 +904,7 @@ __device__ __forceinline__ void project_adjoint_carry_tile(const ProjAdjArgs& a,
     LR_PCARRY(0) LR_PCARRY(1) LR_PCARRY(2) LR_PCARRY(3) LR_PCARRY(4) LR_PCARRY(5)
     LR_PCARRY(6) LR_PCARRY(7) LR_PCARRY(8)
 #undef LR_PCARRY
-  } else {
+  } else if (!a.params) {
     // footprint wider than the rows: scatter straight to global memory
     auto scatter = [&](const auto& S, int64_t i) {
       if (i >= a.n_y) return;
@@ -888,10 +928,61 @@ __device__ __forceinline__ void project_adjoint_carry_tile(const ProjAdjArgs& a,
     cs.rl[w] = fits ? hi - lo + 1 : 0;
   }
   __syncthreads();
-  carry_fold<2>(lds, rl_cap, cs, a.y_start + i0, [&](int r, int64_t& n) -> double* {
-    n = a.n_h;
-    return r == 0 ? a.g_hp : a.g_hc;
+  if (!a.params) {
+    carry_fold<2>(lds, rl_cap, cs, a.y_start + i0, [&](int r, int64_t& n) -> double* {
+      n = a.n_h;
+      return r == 0 ? a.g_hp : a.g_hc;
+    });
+    return;
+  }
+  // Waveform mode: the tile's share of g_h+, g_hx goes straight into the
+  // seven parameter-gradient sums (linear in g_h, so tile shares add up),
+  // summed per lane, then over the workgroup in a fixed order.
+  const gb::Source src = gb::load_source(a.params);
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (!fits) {
+    // a wave whose footprint exceeds its rows: every tap on its own
+    auto scatter = [&](const auto& S, int64_t i) {
+      if (i >= a.n_y) return;
+      const int64_t q = a.y_start + i;
+#define LR_PGB(P)                                                                             \
+      {                                                                                       \
+        double ap, ac, eps;                                                                   \
+        const int sh = split_delay(proj_carry_pos<P>(S, ap, ac), a.inv_dt, eps);              \
+        const int64_t j0 = q + sh - (H - 1);                                                  \
+        for (int m = 0; m < N; ++m) {                                                         \
+          const int64_t j = j0 + m;                                                           \
+          if (j < 0 || j >= a.n_h) continue;                                                  \
+          const double wm = lagrange_weight_at<N>(eps, m);                                    \
+          gb::adjoint_sums(src, (double)(a.k0 + j) * a.dt, wm * ap, wm * ac, acc);            \
+        }                                                                                     \
+      }
+      LR_PGB(0) LR_PGB(1) LR_PGB(2) LR_PGB(3) LR_PGB(4) LR_PGB(5) LR_PGB(6) LR_PGB(7) LR_PGB(8)
+#undef LR_PGB
+    };
+    scatter(sa, ia);
+    scatter(sb, ia + 1);
+  }
+  carry_fold_values<2>(lds, rl_cap, cs, a.y_start + i0, a.n_h, [&](int64_t j, const double (&v)[2]) {
+    gb::adjoint_sums(src, (double)(a.k0 + j) * a.dt, v[0], v[1], acc);
   });
+  // fixed-order reduction: shuffle tree in each wave, then the waves in order
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_down(acc[k], off);
+  }
+  if (lane0) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) cs.gb[k][w] = acc[k];
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double v = cs.gb[tid][0];
+#pragma unroll
+    for (int ww = 1; ww < kBlock / 64; ++ww) v += cs.gb[tid][ww];
+    a.gb_part[tid] = v;
+  }
 }
 
 template <int N>

@@ -201,7 +201,7 @@ const char* lr_status_str(int s) {
 
 const char* lr_last_error(void) { return g_err.c_str(); }
 
-int lr_abi_version(void) { return 3; }
+int lr_abi_version(void) { return 4; }
 
 size_t lr_orbits_bytes(int64_t n) {
   if (n < 4) return 0;
@@ -433,6 +433,9 @@ int lr_project_adjoint(const lr_orbits* orb, double t0_h, double dt, int64_t n_h
   a.g_hc = g_hc;
   a.sky_part = g_sky ? static_cast<double*>(work) : nullptr;
   a.rl_cap = lr::carry_row_capacity(order, 2.01 * orb->L_max, dt, 2, 2, 21 * 64);
+  a.params = nullptr;
+  a.k0 = 0;
+  a.gb_part = nullptr;
   e = lr::run_project_adjoint(order, a, s);
   if (e == hipSuccess && g_sky)
     e = lr::run_sky_finalize(a.sky_part, (n_y + lr::kTile - 1) / lr::kTile, g_sky, s);

@@ -10,32 +10,34 @@
 
 #include "../../include/lisaresp.h"
 #include "batch_types.hpp"
+#include "gb_types.hpp"
 #include "internal.hpp"
 
 namespace {
 
 using lr::set_error;
 
-constexpr int kYTile = 512;           // link samples per fused work item (2 per lane)
+constexpr int kYTileDefault = 512;    // link samples per fused work item (2 per lane)
 constexpr int64_t kAdjTile = 256;     // samples per adjoint work item (atomic kernels, sky)
 constexpr int64_t kCarryTile = 512;   // samples per work item of the carry adjoint kernels
 constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
 
 enum Region {
   R_TPL, R_ITEMS, R_COUNTER, R_ADJ_TPL, R_TDI_ITEMS, R_PROJ_ITEMS, R_SKY_PART, R_SKY_SPAN,
-  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_TDI_CITEMS, R_PADJ_CITEMS, R_GY, R_COUNT
+  R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_TDI_CITEMS, R_PADJ_CITEMS, R_GB_PART,
+  R_PADJ_SPAN, R_GY, R_COUNT
 };
 
 static_assert(R_COUNT <= (int)(sizeof(((lr_batch*)nullptr)->off) / sizeof(size_t)),
               "lr_batch.off has a slot per workspace region");
 
 struct Plan {
-  int F = 0, B = 0, T_out = 0;
+  int F = 0, B = 0, T_out = 0, Y = 0;
   std::vector<lr::BatchTemplate> tpl;
   std::vector<int> items;
   std::vector<lr::BatchAdjTemplate> adj;
   std::vector<int64_t> tdi_items, proj_items, sky_span, like_items, like_span, pairs;
-  std::vector<int64_t> tdi_citems, padj_citems;
+  std::vector<int64_t> tdi_citems, padj_citems, padj_span;
   int64_t gy_doubles = 0, h_extent = 0, out_extent = 0, max_n_out = 0;
   size_t bytes[R_COUNT] = {};
   size_t off[R_COUNT] = {};
@@ -44,13 +46,25 @@ struct Plan {
 
 bool valid_order(int order) { return order >= 1 && order <= 31 && (order % 2) == 1; }
 
+// Compiled fused-kernel variants: (templates per item, link samples per item).
+bool fused_variant_exists(int group, int tile) {
+  if (tile != 256 && tile != 512 && tile != 1024) return false;
+  if (group == 1 || group == 2) return true;
+  return group == 4 && tile <= 512;
+}
+
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, int order,
-              int generation, int channels, int group, int adjoint, Plan& P) {
+              int generation, int channels, int group, int tile, int adjoint, Plan& P) {
   if (n < 0 || (n > 0 && !t)) return set_error(LR_E_ARG, "bad template list");
   if (group != 1 && group != 2 && group != 4)
     return set_error(LR_E_UNSUPPORTED, "group %d (1, 2 or 4 templates per work item)", group);
+  if (tile == 0) tile = kYTileDefault;
+  if (!fused_variant_exists(group, tile))
+    return set_error(LR_E_UNSUPPORTED, "tile %d with group %d (tiles of 256, 512 or 1024 link "
+                                       "samples; 1024 not with groups of 4)", tile, group);
+  P.Y = tile;
   if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
     return set_error(LR_E_UNSUPPORTED, "channels %d", channels);
   if (!valid_order(order)) return set_error(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
@@ -58,11 +72,11 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   if (int st = lr_tdi_padding(tdi, order, generation, dt, &F, &B)) return st;
   P.F = (int)F;
   P.B = (int)B;
-  P.T_out = (kYTile - P.F - P.B) & ~1;
+  P.T_out = (tile - P.F - P.B) & ~1;
   if (P.T_out < 2)
     return set_error(LR_E_UNSUPPORTED, "dt = %g s is too small for the fused kernel (the TDI "
                                        "stencil needs %lld + %lld of %d link samples)",
-                     dt, (long long)F, (long long)B, kYTile);
+                     dt, (long long)F, (long long)B, tile);
   const int64_t rows = channels == LR_XYZ_AET ? 6 : 3;
 
   // grouped forward work list: longest templates first
@@ -115,10 +129,14 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
     P.sky_span.push_back(first);
     P.sky_span.push_back((int64_t)P.proj_items.size() / 2 - first);
     P.sky_span.push_back(b);
+    const int64_t cfirst = (int64_t)P.padj_citems.size() / 2;
     for (int64_t tl = 0; tl < (A.n_y + kCarryTile - 1) / kCarryTile; ++tl) {
       P.padj_citems.push_back(b);
       P.padj_citems.push_back(tl);
     }
+    P.padj_span.push_back(cfirst);
+    P.padj_span.push_back((int64_t)P.padj_citems.size() / 2 - cfirst);
+    P.padj_span.push_back(b);
     const int64_t lfirst = (int64_t)P.like_items.size() / 2;
     const int64_t len = rows * T.n_out;
     for (int64_t c = 0; c < len; c += kLikeChunk) {
@@ -164,6 +182,8 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   P.bytes[R_PAIRS] = adjoint ? P.pairs.size() * sizeof(int64_t) : 0;
   P.bytes[R_TDI_CITEMS] = adjoint ? P.tdi_citems.size() * sizeof(int64_t) : 0;
   P.bytes[R_PADJ_CITEMS] = adjoint ? P.padj_citems.size() * sizeof(int64_t) : 0;
+  P.bytes[R_GB_PART] = adjoint ? P.padj_citems.size() / 2 * 7 * sizeof(double) : 0;
+  P.bytes[R_PADJ_SPAN] = adjoint ? P.padj_span.size() * sizeof(int64_t) : 0;
   P.bytes[R_GY] = adjoint ? (size_t)P.gy_doubles * sizeof(double) : 0;
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
@@ -200,25 +220,57 @@ int check_batch(const lr_batch* b) {
   return LR_OK;
 }
 
+int launch_forward(const lr_batch* b, const double* hp, const double* hc, const double* sky,
+                   int sky_stride, const double* params, double* out, void* stream) {
+  lr::BatchFwdArgs a;
+  a.orb_p = view(b->proj);
+  a.orb_t = view(b->tdi);
+  a.tpl = at<const lr::BatchTemplate>(b, R_TPL);
+  a.items = at<const int>(b, R_ITEMS);
+  a.n_items = (int)b->n_items;
+  a.counter = at<int>(b, R_COUNTER);
+  a.t_off_p = b->t0 - b->proj.t0;
+  a.t_off_t = b->t0 - b->tdi.t0;
+  a.dt = b->dt;
+  a.inv_dt = 1.0 / b->dt;
+  a.F = b->front;
+  a.T_out = b->tile_out;
+  a.hp = hp;
+  a.hc = hc;
+  a.sky = sky;
+  a.sky_stride = sky_stride;
+  a.params = params;
+  a.channels = b->channels;
+  a.out = out;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_reset_counter(a.counter, s);
+  if (e == hipSuccess)
+    e = lr::run_fused_forward(b->order, b->generation, b->group, b->tile, a, b->blocks, s);
+  if (e != hipSuccess) return set_error(LR_E_HIP, "lr_response launch: %s", hipGetErrorString(e));
+  return LR_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t lr_batch_workspace(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt,
-                          int order, int generation, int channels, int group, int adjoint) {
+                          int order, int generation, int channels, int group, int tile,
+                          int adjoint) {
   Plan P;
-  if (make_plan(t, n, tdi, dt, order, generation, channels, group, adjoint, P)) return 0;
+  if (make_plan(t, n, tdi, dt, order, generation, channels, group, tile, adjoint, P)) return 0;
   return P.total;
 }
 
 int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
                      const lr_orbits* tdi, double t0, double dt, int order, int generation,
-                     int channels, int group, int adjoint, void* ws, size_t ws_bytes,
+                     int channels, int group, int tile, int adjoint, void* ws, size_t ws_bytes,
                      lr_batch* out, void* stream) {
   if (!out || !proj || !tdi) return set_error(LR_E_ARG, "null pointer");
   if (!std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt)) return set_error(LR_E_ARG, "bad t0 or dt");
   Plan P;
-  if (int st = make_plan(t, n, tdi, dt, order, generation, channels, group, adjoint, P)) return st;
+  if (int st = make_plan(t, n, tdi, dt, order, generation, channels, group, tile, adjoint, P))
+    return st;
   if (!ws || ws_bytes < P.total)
     return set_error(LR_E_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, P.total);
   int64_t fp, bp;
@@ -267,6 +319,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   put(R_PAIRS, P.pairs.data());
   put(R_TDI_CITEMS, P.tdi_citems.data());
   put(R_PADJ_CITEMS, P.padj_citems.data());
+  put(R_PADJ_SPAN, P.padj_span.data());
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(ws, img.data(), P.off[R_GY], hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -277,7 +330,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
   const int64_t n_items = (int64_t)P.items.size() / 2;
-  const int64_t per_cu = lr::fused_blocks_per_cu(order, generation, group);
+  const int64_t per_cu = lr::fused_blocks_per_cu(order, generation, group, P.Y);
 
   out->proj = *proj;
   out->tdi = *tdi;
@@ -289,6 +342,8 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   out->group = group;
   out->front = P.F;
   out->tile_out = P.T_out;
+  out->tile = P.Y;
+  out->reserved = 0;
   out->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)cus * per_cu));
   out->adjoint = adjoint ? 1 : 0;
   out->n_templates = n;
@@ -311,30 +366,14 @@ int lr_response(const lr_batch* b, const double* hp, const double* hc, const dou
   if (int st = check_batch(b)) return st;
   if (b->n_items == 0) return LR_OK;
   if (!hp || !hc || !sky || !out) return set_error(LR_E_ARG, "null pointer");
-  lr::BatchFwdArgs a;
-  a.orb_p = view(b->proj);
-  a.orb_t = view(b->tdi);
-  a.tpl = at<const lr::BatchTemplate>(b, R_TPL);
-  a.items = at<const int>(b, R_ITEMS);
-  a.n_items = (int)b->n_items;
-  a.counter = at<int>(b, R_COUNTER);
-  a.t_off_p = b->t0 - b->proj.t0;
-  a.t_off_t = b->t0 - b->tdi.t0;
-  a.dt = b->dt;
-  a.inv_dt = 1.0 / b->dt;
-  a.F = b->front;
-  a.T_out = b->tile_out;
-  a.hp = hp;
-  a.hc = hc;
-  a.sky = sky;
-  a.channels = b->channels;
-  a.out = out;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = lr::run_reset_counter(a.counter, s);
-  if (e == hipSuccess)
-    e = lr::run_fused_forward(b->order, b->generation, b->group, a, b->blocks, s);
-  if (e != hipSuccess) return set_error(LR_E_HIP, "lr_response launch: %s", hipGetErrorString(e));
-  return LR_OK;
+  return launch_forward(b, hp, hc, sky, 2, nullptr, out, stream);
+}
+
+int lr_response_gb(const lr_batch* b, const double* params, double* out, void* stream) {
+  if (int st = check_batch(b)) return st;
+  if (b->n_items == 0) return LR_OK;
+  if (!params || !out) return set_error(LR_E_ARG, "null pointer");
+  return launch_forward(b, nullptr, nullptr, params + 6, 8, params, out, stream);
 }
 
 int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
@@ -369,6 +408,9 @@ int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
   a.sky_part = g_sky ? at<double>(b, R_SKY_PART) : nullptr;
   a.pairs = at<const int64_t>(b, R_PAIRS);
   a.sky_items = at<const int64_t>(b, R_PROJ_ITEMS);
+  a.sky_stride = 2;
+  a.params = nullptr;
+  a.gb_part = nullptr;
   // carry kernels (deterministic) where their rows fit LDS, else atomic ones
   const int cap_t = lr::carry_row_capacity(b->order, (b->generation == 1 ? 3 : 7) * b->tdi.L_max,
                                            b->dt, 12, 4, 0);
@@ -390,6 +432,66 @@ int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
                                    g_sky, s);
   if (e != hipSuccess)
     return set_error(LR_E_HIP, "lr_response_adjoint launch: %s", hipGetErrorString(e));
+  return LR_OK;
+}
+
+int lr_response_adjoint_gb(const lr_batch* b, const double* params, const double* g_out,
+                           double* g_params, void* stream) {
+  if (int st = check_batch(b)) return st;
+  if (!b->adjoint) return set_error(LR_E_WORKSPACE, "batch prepared without adjoint workspace");
+  if (!params || !g_params || (b->n_tdi_items > 0 && !g_out))
+    return set_error(LR_E_ARG, "null pointer");
+  const size_t pb = (size_t)b->n_templates * 8 * sizeof(double);
+  if (pb && (reinterpret_cast<uintptr_t>(g_params) < reinterpret_cast<uintptr_t>(params) + pb &&
+             reinterpret_cast<uintptr_t>(params) < reinterpret_cast<uintptr_t>(g_params) + pb))
+    return set_error(LR_E_ARG, "g_params overlaps params");
+  const int cap_t = lr::carry_row_capacity(b->order, (b->generation == 1 ? 3 : 7) * b->tdi.L_max,
+                                           b->dt, 12, 4, 0);
+  const int cap_p = lr::carry_row_capacity(b->order, 2.01 * b->proj.L_max, b->dt, 2, 2, 21 * 64);
+  if (cap_p == 0)
+    return set_error(LR_E_UNSUPPORTED, "dt = %g s is too small for the parameter adjoint (the "
+                                       "projection footprints do not fit LDS)", b->dt);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = lr::run_fill_zero(at<double>(b, R_GY), b->gy_doubles, s);
+  lr::BatchAdjArgs a;
+  a.orb_p = view(b->proj);
+  a.orb_t = view(b->tdi);
+  a.tpl = at<const lr::BatchAdjTemplate>(b, R_ADJ_TPL);
+  a.t_off_y = (b->t0 - b->tdi.t0) - b->front * b->dt;
+  a.dt = b->dt;
+  a.inv_dt = 1.0 / b->dt;
+  a.F = b->front;
+  a.channels = b->channels;
+  a.hp = nullptr;
+  a.hc = nullptr;
+  a.sky = params + 6;
+  a.sky_stride = 8;
+  a.params = params;
+  a.g_out = g_out;
+  a.g_y = at<double>(b, R_GY);
+  a.g_hp = nullptr;
+  a.g_hc = nullptr;
+  a.sky_part = at<double>(b, R_SKY_PART);
+  a.gb_part = at<double>(b, R_GB_PART);
+  a.pairs = at<const int64_t>(b, R_PAIRS);
+  a.sky_items = at<const int64_t>(b, R_PROJ_ITEMS);
+  if (e == hipSuccess && b->n_tdi_items > 0) {
+    a.rl_cap = cap_t;
+    a.items = at<const int64_t>(b, cap_t > 0 ? R_TDI_CITEMS : R_TDI_ITEMS);
+    e = lr::run_batch_tdi_adjoint(b->order, b->generation, a,
+                                  cap_t > 0 ? b->n_tdi_citems : b->n_tdi_items, s);
+  }
+  if (e == hipSuccess && b->n_proj_items > 0) {
+    a.rl_cap = cap_p;
+    a.items = at<const int64_t>(b, R_PADJ_CITEMS);
+    e = lr::run_batch_project_adjoint(b->order, a, b->n_padj_citems, b->n_proj_items, s);
+  }
+  if (e == hipSuccess)
+    e = lr::run_gb_batch_finalize(a.gb_part, at<const int64_t>(b, R_PADJ_SPAN), a.sky_part,
+                                  at<const int64_t>(b, R_SKY_SPAN), params, b->n_templates,
+                                  g_params, s);
+  if (e != hipSuccess)
+    return set_error(LR_E_HIP, "lr_response_adjoint_gb launch: %s", hipGetErrorString(e));
   return LR_OK;
 }
 

@@ -54,14 +54,17 @@ __device__ __forceinline__ ProjAdjArgs batch_proj_args(const BatchAdjArgs& a,
   x.t_off = T.t_off_h;
   x.dt = a.dt;
   x.inv_dt = a.inv_dt;
-  x.sky = a.sky + 2 * T.index;
+  x.sky = a.sky + a.sky_stride * T.index;
   x.y_start = T.y_start;
   x.n_y = T.n_y;
   x.g_y = a.g_y + T.gy_off;
-  x.g_hp = a.g_hp + T.h_off;
-  x.g_hc = a.g_hc + T.h_off;
+  x.g_hp = a.g_hp ? a.g_hp + T.h_off : nullptr;
+  x.g_hc = a.g_hc ? a.g_hc + T.h_off : nullptr;
   x.sky_part = nullptr;
   x.rl_cap = 0;
+  x.params = a.params ? a.params + 8 * T.index : nullptr;
+  x.k0 = -(T.y_start + a.F);                        // waveform time 0 at output sample 0
+  x.gb_part = nullptr;
   return x;
 }
 
@@ -102,8 +105,9 @@ __global__ __launch_bounds__(kBlock, LR_PADJ_CARRY_MIN_WAVES) void batch_project
   __shared__ CarryShared cs;
   __shared__ double s_trig[2][2];
   const int64_t b = a.items[2 * blockIdx.x], tile = a.items[2 * blockIdx.x + 1];
-  project_adjoint_carry_tile<N>(batch_proj_args(a, a.tpl[b]), tile, lds_dyn, a.rl_cap, cs,
-                                s_trig);
+  ProjAdjArgs x = batch_proj_args(a, a.tpl[b]);
+  if (a.gb_part) x.gb_part = a.gb_part + 7 * blockIdx.x;
+  project_adjoint_carry_tile<N>(x, tile, lds_dyn, a.rl_cap, cs, s_trig);
 }
 
 // a.items: the carry lists (tiles of kCarryTile) when a.rl_cap > 0, else the

@@ -18,13 +18,13 @@
 
 namespace lr {
 
-// TDI of the lane's two outputs for M templates from their LDS link windows.
-template <int N, int GEN, int M>
+// TDI of the lane's two outputs for M templates from their LDS link windows
+// (rows of YT link samples).
+template <int N, int GEN, int M, int YT>
 __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* ylds,
                                           const double (&La)[6], const double (&Lb)[6], int c0,
                                           const bool (&live)[M], double (&acc)[M][2][3]) {
   constexpr int H = N / 2;
-  constexpr int YT = kFwdTile;
   constexpr int ND = TdiTab<GEN>::v.ndirect;
   const GroupTable<GEN>& GT = group_table<GEN>();
   // delayed terms accumulate unscaled streams; the undelayed ones are added
@@ -149,17 +149,17 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
 #define LR_FUSED2_MIN_WAVES 3
 #endif
 
-template <int N, int GEN, int M>
-__global__ __launch_bounds__(kBlock, M == 2 ? LR_FUSED2_MIN_WAVES : LR_FUSED_MIN_WAVES)
+template <int N, int GEN, int M, int BLOCK>
+__global__ __launch_bounds__(BLOCK, M == 2 ? LR_FUSED2_MIN_WAVES : LR_FUSED_MIN_WAVES)
 void fused_forward_kernel(BatchFwdArgs a) {
-  constexpr int YT = kFwdTile;
-  constexpr int CAPH = kFwdTile + N + kSlack;
+  constexpr int YT = kPerLane * BLOCK;                // link samples per work item
+  constexpr int CAPH = YT + N + kSlack;
   // Template k's h window lives in its own link rows until its projection
   // ends (the rows are written only after a barrier), so the window costs no
   // LDS of its own.
   static_assert(CAPH * sizeof(double2) <= 6 * YT * sizeof(double), "h window fits a row block");
   __shared__ __align__(16) double ylds[M * 6 * YT];
-  __shared__ int red[2][kBlock / 64];
+  __shared__ int red[2][BLOCK / 64];
   __shared__ double s_trig[2][2];
   __shared__ int s_item;
 
@@ -193,7 +193,7 @@ void fused_forward_kernel(BatchFwdArgs a) {
       __syncthreads();                                // s_trig free
       if (tid < 2) {
         double sn, cs;
-        sincos(a.sky[2 * T.index + tid], &sn, &cs);
+        sincos(a.sky[a.sky_stride * T.index + tid], &sn, &cs);
         s_trig[tid][0] = sn;
         s_trig[tid][1] = cs;
       }
@@ -201,8 +201,14 @@ void fused_forward_kernel(BatchFwdArgs a) {
       const Sky sk = sky_from_trig(s_trig[0][0], s_trig[0][1], s_trig[1][0], s_trig[1][1]);
       double ya[6], yb[6];
       double2* hwin = reinterpret_cast<double2*>(ylds + k * 6 * YT);
-      project_pair<N>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, a.hp + T.h_off,
-                      a.hc + T.h_off, T.n_h, T.out_start + i_base, sk, ra, hwin, red, ya, yb);
+      // h+ / hx: the caller's arrays, or the waveform synthesised into the
+      // window from the template's parameter row (waveform time 0 at output
+      // sample 0)
+      const HSource hs = a.params
+          ? HSource::waveform(a.params + 8 * T.index, -T.out_start, a.dt, T.n_h)
+          : HSource::arrays(a.hp + T.h_off, a.hc + T.h_off, T.n_h);
+      project_pair<N, BLOCK>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, hs,
+                             T.out_start + i_base, sk, ra, hwin, red, ya, yb);
       __syncthreads();                                // the window is read; rows may be written
 #pragma unroll
       for (int l = 0; l < 6; ++l) {
@@ -221,7 +227,7 @@ void fused_forward_kernel(BatchFwdArgs a) {
     light_times(a.orb_t, a.t_off_t + (double)(o0 + ob) * a.dt, La);
     light_times(a.orb_t, a.t_off_t + (double)(o0 + ob + 1) * a.dt, Lb);
     double acc[M][2][3];
-    fused_tdi<N, GEN, M>(a, ylds, La, Lb, a.F + ob, live, acc);
+    fused_tdi<N, GEN, M, YT>(a, ylds, La, Lb, a.F + ob, live, acc);
 
     // 3. store
     if (out_a) {
@@ -239,29 +245,34 @@ void fused_forward_kernel(BatchFwdArgs a) {
   }
 }
 
-template <int N, int GEN, int M>
+template <int N, int GEN, int M, int BLOCK>
 hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((fused_forward_kernel<N, GEN, M>), dim3(blocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((fused_forward_kernel<N, GEN, M, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s,
+                     a);
   return hipGetLastError();
 }
 
 // Resident workgroups per CU of the fused kernel (sizes the persistent grid).
-template <int N, int GEN, int M>
+template <int N, int GEN, int M, int BLOCK>
 int fused_occupancy() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_forward_kernel<N, GEN, M>, kBlock,
-                                                   0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_forward_kernel<N, GEN, M, BLOCK>,
+                                                   BLOCK, 0) != hipSuccess)
     nb = 1;
   return nb > 0 ? nb : 1;
 }
 
-#define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M)                                                 \
-  template hipError_t launch_fused_forward<NT, GEN, M>(const BatchFwdArgs&, int, hipStream_t); \
-  template int fused_occupancy<NT, GEN, M>();
+#define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M, BLOCK)                                 \
+  template hipError_t launch_fused_forward<NT, GEN, M, BLOCK>(const BatchFwdArgs&, int,   \
+                                                              hipStream_t);               \
+  template int fused_occupancy<NT, GEN, M, BLOCK>();
 
-#define LR_INSTANTIATE_BATCH_FWD(NT, GEN)   \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1)    \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2)    \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4)
+// Work items of 256, 512 or 1024 link samples (workgroups of 128, 256 or 512
+// lanes); groups of 4 at 1024 would need 196 KB of LDS and are left out.
+#define LR_INSTANTIATE_BATCH_FWD(NT, GEN)                                             \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 128) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 256) \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 512) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 128) \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 256) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 512) \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 128) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 256)
 
 }  // namespace lr

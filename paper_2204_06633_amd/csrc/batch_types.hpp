@@ -29,7 +29,9 @@ struct BatchFwdArgs {
   int T_out;                 // outputs per tile (even)
   const double* hp;
   const double* hc;
-  const double* sky;         // [n_templates][2] (lam, beta) in the caller's order
+  const double* sky;         // lam, beta of template k at sky[sky_stride * k + 0, 1]
+  int sky_stride;            // 2 (sky array) or 8 (rows of params)
+  const double* params;      // [n_templates][8] or null: synthesise h+ / hx from these
   int channels;
   double* out;
 };
@@ -62,12 +64,15 @@ struct BatchAdjArgs {
   double* g_hc;
   double* sky_part;             // [n_sky_items][2] or null
   int rl_cap;                   // wave row capacity of the carry kernels (0: atomic kernels)
+  int sky_stride;               // lam, beta of template k at sky[sky_stride * k + 0, 1]
+  const double* params;         // [n][8] or null: waveform mode (see ProjAdjArgs)
+  double* gb_part;              // waveform mode: [n_items][7] parameter-gradient sums
 };
 
 // Launchers (instantiated per tap count in batch_*.hip).
-template <int N, int GEN, int M>
+template <int N, int GEN, int M, int BLOCK>
 hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s);
-template <int N, int GEN, int M>
+template <int N, int GEN, int M, int BLOCK>
 int fused_occupancy();
 template <int N, int GEN>
 hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
@@ -75,9 +80,10 @@ template <int N>
 hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items,
                                         int64_t n_sky_items, hipStream_t s);
 
-hipError_t run_fused_forward(int order, int gen, int group, const BatchFwdArgs& a, int blocks,
-                             hipStream_t s);
-int fused_blocks_per_cu(int order, int gen, int group);
+// tile: link samples per work item (256, 512 or 1024; not 1024 with group 4)
+hipError_t run_fused_forward(int order, int gen, int group, int tile, const BatchFwdArgs& a,
+                             int blocks, hipStream_t s);
+int fused_blocks_per_cu(int order, int gen, int group, int tile);
 hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int64_t n_items,
                                  hipStream_t s);
 hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,

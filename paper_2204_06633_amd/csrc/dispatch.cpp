@@ -44,39 +44,49 @@ hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s) {
   }
 }
 
-#define LR_GROUP_CASES(NT, GEN)                                                   \
-  switch (group) {                                                                \
-    case 1: return launch_fused_forward<NT, GEN, 1>(a, blocks, s);                 \
-    case 2: return launch_fused_forward<NT, GEN, 2>(a, blocks, s);                 \
-    case 4: return launch_fused_forward<NT, GEN, 4>(a, blocks, s);                 \
-    default: return hipErrorInvalidValue;                                         \
+// (group, workgroup lanes) -> fused kernel instance; tile = 2 x lanes link
+// samples per work item.
+#define LR_FUSED_CASES(NT, GEN, CALL, FAIL)                                       \
+  switch (group * 10000 + tile / 2) {                                             \
+    case 10128: return CALL(NT, GEN, 1, 128);                                      \
+    case 10256: return CALL(NT, GEN, 1, 256);                                      \
+    case 10512: return CALL(NT, GEN, 1, 512);                                      \
+    case 20128: return CALL(NT, GEN, 2, 128);                                      \
+    case 20256: return CALL(NT, GEN, 2, 256);                                      \
+    case 20512: return CALL(NT, GEN, 2, 512);                                      \
+    case 40128: return CALL(NT, GEN, 4, 128);                                      \
+    case 40256: return CALL(NT, GEN, 4, 256);                                      \
+    default: return FAIL;                                                         \
   }
 
-hipError_t run_fused_forward(int order, int gen, int group, const BatchFwdArgs& a, int blocks,
-                             hipStream_t s) {
+#define LR_LAUNCH_FUSED(NT, GEN, M, B) launch_fused_forward<NT, GEN, M, B>(a, blocks, s)
+#define LR_OCC_FUSED(NT, GEN, M, B) fused_occupancy<NT, GEN, M, B>()
+
+hipError_t run_fused_forward(int order, int gen, int group, int tile, const BatchFwdArgs& a,
+                             int blocks, hipStream_t s) {
   switch (order) {
-#define X(ORD, NT) \
-  case ORD:        \
-    if (gen == 1) { LR_GROUP_CASES(NT, 1) } else { LR_GROUP_CASES(NT, 2) }
+#define X(ORD, NT)                                                                        \
+  case ORD:                                                                               \
+    if (gen == 1) {                                                                       \
+      LR_FUSED_CASES(NT, 1, LR_LAUNCH_FUSED, hipErrorInvalidValue)                        \
+    } else {                                                                              \
+      LR_FUSED_CASES(NT, 2, LR_LAUNCH_FUSED, hipErrorInvalidValue)                        \
+    }
     LR_ORDER_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
 }
 
-#define LR_OCC_CASES(NT, GEN)                           \
-  switch (group) {                                      \
-    case 1: return fused_occupancy<NT, GEN, 1>();        \
-    case 2: return fused_occupancy<NT, GEN, 2>();        \
-    case 4: return fused_occupancy<NT, GEN, 4>();        \
-    default: return 1;                                  \
-  }
-
-int fused_blocks_per_cu(int order, int gen, int group) {
+int fused_blocks_per_cu(int order, int gen, int group, int tile) {
   switch (order) {
-#define X(ORD, NT) \
-  case ORD:        \
-    if (gen == 1) { LR_OCC_CASES(NT, 1) } else { LR_OCC_CASES(NT, 2) }
+#define X(ORD, NT)                                                                        \
+  case ORD:                                                                               \
+    if (gen == 1) {                                                                       \
+      LR_FUSED_CASES(NT, 1, LR_OCC_FUSED, 1)                                              \
+    } else {                                                                              \
+      LR_FUSED_CASES(NT, 2, LR_OCC_FUSED, 1)                                              \
+    }
     LR_ORDER_CASES(X)
 #undef X
     default: return 1;

@@ -22,6 +22,7 @@
 #include <utility>
 
 #include "device_common.hpp"
+#include "gb_device.hpp"
 #include "internal.hpp"
 
 namespace lr {
@@ -139,6 +140,53 @@ __device__ __forceinline__ void proj_sample(const OrbitView& orb, double tau, do
   for (int k = 0; k < 3; ++k) { s.xip[k] = g.xip[k]; s.xic[k] = g.xic[k]; s.kn[k] = g.kn[k]; }
 }
 
+// Source of the h+ / hx samples a projection reads, by h-index j in
+// [0, n_h): arrays in HBM, or the Galactic-binary waveform (Sec. III)
+// evaluated at t_j = (k0 + j) dt from one parameter row (the fused batch
+// kernels synthesise their LDS windows this way; the waveform's constants
+// are set up once per template).
+struct HSource {
+  const double* hp;
+  const double* hc;
+  int64_t n_h;
+  bool wave;
+  gb::Source src;
+  double ap0, ac0, dt;
+  int64_t k0;
+
+  __device__ __forceinline__ static HSource arrays(const double* hp, const double* hc,
+                                                   int64_t n_h) {
+    HSource h;
+    h.hp = hp;
+    h.hc = hc;
+    h.n_h = n_h;
+    h.wave = false;
+    return h;
+  }
+  // params: A, f0, fdot, phi0, iota, psi (lam, beta unused here)
+  __device__ __forceinline__ static HSource waveform(const double* params, int64_t k0, double dt,
+                                                     int64_t n_h) {
+    HSource h;
+    h.hp = h.hc = nullptr;
+    h.n_h = n_h;
+    h.wave = true;
+    h.src = gb::load_source(params);
+    h.ap0 = -(1.0 + h.src.ci * h.src.ci) * h.src.A;
+    h.ac0 = -2.0 * h.src.ci * h.src.A;
+    h.dt = dt;
+    h.k0 = k0;
+    return h;
+  }
+  __device__ __forceinline__ double2 at(int64_t j) const {
+    if (wave) {                                   // uniform
+      double p, c;
+      gb::polarizations_at(src, ap0, ac0, (double)(k0 + j) * dt, p, c);
+      return make_double2(p, c);
+    }
+    return make_double2(hp[j], hc[j]);
+  }
+};
+
 // Window loads kept in flight per stream in project_pair (0: the compiler's
 // own schedule).  Build-time tuning knob (sched_group_barrier masks: 0x100
 // LDS reads, 0x002 VALU).
@@ -147,18 +195,18 @@ __device__ __forceinline__ void proj_sample(const OrbitView& orb, double tau, do
 #endif
 
 // Link responses of one template at the lane's two tile samples ra and ra+1
-// (ra even).  Tile element r has h-index hq0 + r and orbit time
+// (ra even), in a workgroup of BLOCK lanes (a tile of 2 BLOCK samples).  Tile element r has h-index hq0 + r and orbit time
 // t_off + (ti0 + r) * dt.  Uses the workgroup's LDS window and reduction
 // scratch; contains barriers, so every lane of the workgroup must call it.
-template <int N>
+template <int N, int BLOCK = kBlock>
 __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off, int64_t ti0,
-                                             double dt, double inv_dt, const double* hp,
-                                             const double* hc, int64_t n_h, int64_t hq0,
+                                             double dt, double inv_dt, const HSource& hs,
+                                             int64_t hq0,
                                              const Sky& sk, int ra, double2* win,
-                                             int (&red)[2][kBlock / 64], double (&ya)[6],
+                                             int (&red)[2][BLOCK / 64], double (&ya)[6],
                                              double (&yb)[6]) {
   constexpr int H = N / 2;
-  constexpr int CAP = kFwdTile + N + kSlack;
+  constexpr int CAP = kPerLane * BLOCK + N + kSlack;
   const int tid = threadIdx.x;
   ProjSample A, B;
   proj_sample(orb, t_off + (double)(ti0 + ra) * dt, inv_dt, sk, A);
@@ -173,18 +221,18 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
     hi = max(hi, max(A.sh[p], B.sh[p] + 1));
   }
   int wlo, whi;
-  block_range<kBlock>(ra + lo - (H - 1), ra + hi + H, red, wlo, whi);
+  block_range<BLOCK>(ra + lo - (H - 1), ra + hi + H, red, wlo, whi);
   const int count = whi - wlo + 1;
   const int64_t base = hq0 + wlo;                // h-index of window element 0
-  const int64_t hmax = n_h - 1;
+  const int64_t hmax = hs.n_h - 1;
   const int64_t qa = hq0 + ra;
 
   double na[6] = {0, 0, 0, 0, 0, 0}, nb[6] = {0, 0, 0, 0, 0, 0};
   if (count > 0 && count <= CAP) {
-    for (int k = tid; k < count; k += kBlock) {
+    for (int k = tid; k < count; k += BLOCK) {
       int64_t j = base + k;
       j = j < 0 ? 0 : (j > hmax ? hmax : j);
-      win[par<CAP>(k)] = make_double2(hp[j], hc[j]);
+      win[par<CAP>(k)] = hs.at(j);
     }
     __syncthreads();
 #pragma unroll
@@ -251,10 +299,11 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
         int64_t jj = jb + m;
         jj = jj < 0 ? 0 : (jj > hmax ? hmax : jj);
         st.tap(m);
-        pa = st.step_a(pa, hp[j], m);
-        ca = st.step_a(ca, hc[j], m);
-        pb = st.step_b(pb, hp[jj], m);
-        cb = st.step_b(cb, hc[jj], m);
+        const double2 va = hs.at(j), vb = hs.at(jj);
+        pa = st.step_a(pa, va.x, m);
+        ca = st.step_a(ca, va.y, m);
+        pb = st.step_b(pb, vb.x, m);
+        cb = st.step_b(cb, vb.y, m);
       }
       add_position_rt(p, A.xip, A.xic, pa, ca, na);
       add_position_rt(p, B.xip, B.xic, pb, cb, nb);
@@ -295,8 +344,8 @@ void project_links_kernel(ProjArgs a) {
   const SkyTrig tr = load_sky(a.sky, s_trig);
   const Sky sk = sky_from_trig(tr.sl, tr.cl, tr.sb, tr.cb);
   double ya[6], yb[6];
-  project_pair<N>(a.orb, a.t_off, a.y_start + i0, a.dt, a.inv_dt, a.hp, a.hc, a.n_h,
-                  a.y_start + i0, sk, ra, win, red, ya, yb);
+  project_pair<N>(a.orb, a.t_off, a.y_start + i0, a.dt, a.inv_dt,
+                  HSource::arrays(a.hp, a.hc, a.n_h), a.y_start + i0, sk, ra, win, red, ya, yb);
 
   if (!act_a) return;
   const int64_t i = i0 + ra;

@@ -26,5 +26,10 @@ struct GbArgs {
 int64_t gb_blocks(int64_t n_h);
 hipError_t run_gb_forward(const GbArgs& a, int64_t n_tpl, hipStream_t s);
 hipError_t run_gb_adjoint(const GbArgs& a, int64_t n_tpl, hipStream_t s);
+// g_params [n][8] of a batch in waveform mode from the per-tile sums (see
+// gb_batch_finalize_kernel); span and sky_span: [n][3] (first, count, index).
+hipError_t run_gb_batch_finalize(const double* gb_part, const int64_t* span,
+                                 const double* sky_part, const int64_t* sky_span,
+                                 const double* params, int64_t n, double* g_params, hipStream_t s);
 
 }  // namespace lr

@@ -57,6 +57,12 @@ struct ProjAdjArgs {
   double* g_hc;
   double* sky_part;     // [blocks][2] partial sky gradients, or null
   int rl_cap;           // wave row capacity of the carry kernel (even); 0: atomic kernel
+  // Waveform mode: h+ / hx are the Galactic-binary waveform of this parameter
+  // row at t_j = (k0 + j) dt (hp, hc, g_hp, g_hc unused); the carry kernel
+  // writes the tile's seven parameter-gradient sums to gb_part[0..6].
+  const double* params;
+  int64_t k0;
+  double* gb_part;
 };
 
 // Per-tap-count launchers (N = order + 1), instantiated in forward_*.hip.

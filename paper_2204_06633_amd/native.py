@@ -357,12 +357,13 @@ class lr_batch(ctypes.Structure):
                 ("dt", ctypes.c_double), ("order", ctypes.c_int), ("generation", ctypes.c_int),
                 ("channels", ctypes.c_int), ("group", ctypes.c_int), ("front", ctypes.c_int),
                 ("tile_out", ctypes.c_int), ("blocks", ctypes.c_int), ("adjoint", ctypes.c_int),
+                ("tile", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("n_templates", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_tdi_items", ctypes.c_int64), ("n_proj_items", ctypes.c_int64),
                 ("n_like_items", ctypes.c_int64), ("n_tdi_citems", ctypes.c_int64),
                 ("n_padj_citems", ctypes.c_int64), ("gy_doubles", ctypes.c_int64),
                 ("h_extent", ctypes.c_int64), ("out_extent", ctypes.c_int64),
-                ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 16)]
+                ("ws", ctypes.c_void_p), ("off", ctypes.c_size_t * 24)]
 
 
 def _batch_lib():
@@ -373,14 +374,18 @@ def _batch_lib():
     P = ctypes.POINTER
     pt, po, pb = P(lr_template), P(lr_orbits), P(lr_batch)
     L.lr_batch_workspace.restype = ctypes.c_size_t
-    L.lr_batch_workspace.argtypes = [pt, i64, po, d, i32, i32, i32, i32, i32]
-    L.lr_batch_prepare.argtypes = [pt, i64, po, po, d, d, i32, i32, i32, i32, i32, vp,
+    L.lr_batch_workspace.argtypes = [pt, i64, po, d, i32, i32, i32, i32, i32, i32]
+    L.lr_batch_prepare.argtypes = [pt, i64, po, po, d, d, i32, i32, i32, i32, i32, i32, vp,
                                    ctypes.c_size_t, pb, vp]
     L.lr_response.argtypes = [pb, vp, vp, vp, vp, vp]
+    L.lr_response_gb.argtypes = [pb, vp, vp, vp]
+    L.lr_response_adjoint_gb.argtypes = [pb, vp, vp, vp, vp]
     L.lr_response_adjoint.argtypes = [pb, vp, vp, vp, vp, vp, vp, vp, vp]
     L.lr_batch_loglike.argtypes = [pb, vp, vp, d, vp, vp, vp]
     L.lr_batch_set_grid.argtypes = [pb, i32]
-    for name in ("lr_batch_prepare", "lr_response", "lr_response_adjoint", "lr_batch_loglike",
+    for name in ("lr_batch_prepare", "lr_response", "lr_response_gb", "lr_response_adjoint",
+                 "lr_response_adjoint_gb",
+                 "lr_batch_loglike",
                  "lr_batch_set_grid"):
         getattr(L, name).restype = i32
     L._batch_ready = True
@@ -391,12 +396,14 @@ class Batch:
     """A prepared batch (lr_batch_prepare) and its device workspace.
 
     ``templates``: sequence of (h_offset, n_h, out_start, n_out, out_offset).
+    ``group``: templates per forward work item; ``tile``: link samples per
+    forward work item (256, 512, 1024; 0 = 512).
     The orbit objects must outlive the batch (it holds their device pointers).
     """
 
     def __init__(self, templates, orb_proj: Orbits, orb_tdi: Orbits, t0, dt, order=25,
                  generation=2, channels="XYZ", group=2, adjoint=False, device="cuda",
-                 stream=None):
+                 stream=None, tile=0):
         import torch
         L = _batch_lib()
         n = len(templates)
@@ -408,14 +415,15 @@ class Batch:
         self.channels = channels
         self.rows = 6 if channels == "XYZAET" else 3
         nbytes = L.lr_batch_workspace(arr, n, orb_tdi.ref, float(dt), int(order), int(generation),
-                                      CHANNELS[channels], int(group), int(bool(adjoint)))
+                                      CHANNELS[channels], int(group), int(tile),
+                                      int(bool(adjoint)))
         if nbytes == 0:
             raise LisaRespError(1, "lr_batch_workspace", L.lr_last_error().decode())
         self.ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
         self.c = lr_batch()
         _check(L.lr_batch_prepare(arr, n, orb_proj.ref, orb_tdi.ref, float(t0), float(dt),
                                   int(order), int(generation), CHANNELS[channels], int(group),
-                                  int(bool(adjoint)), ctypes.c_void_p(self.ws.data_ptr()),
+                                  int(tile), int(bool(adjoint)), ctypes.c_void_p(self.ws.data_ptr()),
                                   self.ws.numel() * 8, ctypes.byref(self.c), _stream(stream)),
                "lr_batch_prepare")
 
@@ -433,6 +441,11 @@ class Batch:
     def blocks(self):
         """Work-groups of the persistent forward launch."""
         return int(self.c.blocks)
+
+    @property
+    def tile(self):
+        """Link samples per forward work item."""
+        return int(self.c.tile)
 
     def set_grid(self, blocks):
         _check(_batch_lib().lr_batch_set_grid(ctypes.byref(self.c), int(blocks)),
@@ -457,6 +470,40 @@ class Batch:
                                         _dev(sky, "sky"), _dev(out, "out"), _stream(stream)),
                "lr_response")
         return out
+
+    def response_gb(self, params, out=None, stream=None):
+        """lr_response_gb: the forward with h+ / hx synthesised in the kernel
+        from Galactic-binary parameter rows params [n][8]."""
+        import torch
+        if params.dim() != 2 or params.shape[0] != self.n or params.shape[1] != 8:
+            raise ValueError("params must be [%d][8], got shape %s" % (self.n,
+                                                                     tuple(params.shape)))
+        if out is None:
+            out = torch.empty(max(self.out_extent, 1), dtype=torch.float64, device=params.device)
+        _size(out, "out", min_numel=self.out_extent)
+        _same_device(("params", params), ("out", out))
+        _check(_batch_lib().lr_response_gb(ctypes.byref(self.c), _dev(params, "params"),
+                                           _dev(out, "out"), _stream(stream)),
+               "lr_response_gb")
+        return out
+
+    def adjoint_gb(self, params, g_out, g_params=None, stream=None):
+        """lr_response_adjoint_gb: d<g_out, out>/d params [n][8] of the
+        waveform-mode forward (``response_gb``)."""
+        import torch
+        if params.dim() != 2 or params.shape[0] != self.n or params.shape[1] != 8:
+            raise ValueError("params must be [%d][8], got shape %s" % (self.n,
+                                                                     tuple(params.shape)))
+        if g_params is None:
+            g_params = torch.empty_like(params)
+        _size(g_params, "g_params", shape=(self.n, 8))
+        _size(g_out, "g_out", min_numel=self.out_extent)
+        _same_device(("params", params), ("g_out", g_out), ("g_params", g_params))
+        _check(_batch_lib().lr_response_adjoint_gb(ctypes.byref(self.c), _dev(params, "params"),
+                                                   _dev(g_out, "g_out"),
+                                                   _dev(g_params, "g_params"), _stream(stream)),
+               "lr_response_adjoint_gb")
+        return g_params
 
     def adjoint(self, hp, hc, sky, g_out, want_sky=True, g_hp=None, g_hc=None, g_sky=None,
                 stream=None):

@@ -13,8 +13,9 @@
 pair; ``copy`` runs one device-to-device copy of known size (the reference
 for scaling the HBM byte counters); ``batch`` runs the fused batched forward
 on the first ``--templates`` templates of the 512-template uneven batch
-(group 2); ``batch-adjoint`` runs forward, likelihood and adjoint of that
-many 1-yr, dt = 15 s walkers with hybrid orbits; ``fd`` runs the
+(``--group``, ``--tile``, ``--grid-scale``: the autotuner's knobs);
+``batch-adjoint`` runs forward, likelihood and adjoint of that many 1-yr,
+dt = 15 s walkers with hybrid orbits; ``fd`` runs the
 frequency-domain likelihood with its gradient on ``--templates`` one-year
 A/E/T series at dt = 10 s (2^22-point transforms); ``sampler`` runs
 tempered stretch-move steps of 4 x 50 walkers on one year at dt = 15 s.
@@ -33,6 +34,8 @@ def main(argv=None):
                     default="forward")
     ap.add_argument("--templates", type=int, default=64)
     ap.add_argument("--group", type=int, default=2)
+    ap.add_argument("--tile", type=int, default=0, help="link samples per fused work item")
+    ap.add_argument("--grid-scale", type=float, default=1.0)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args(argv)
@@ -106,7 +109,8 @@ def run_batch(args, dev):
     hp, hc = workloads.device_polarizations(bc, dev)
     sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
     b = native.Batch(bc.layout.templates(), orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation,
-                     bc.channels, group=args.group, adjoint=adj, device=dev)
+                     bc.channels, group=args.group, tile=args.tile, adjoint=adj, device=dev)
+    b.set_grid(max(1, int(round(b.blocks * args.grid_scale))))
     out = torch.empty(b.out_extent, dtype=torch.float64, device=dev)
     data = torch.zeros_like(out) if adj else None
     for r in range(args.reps):

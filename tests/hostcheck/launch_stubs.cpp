@@ -3,6 +3,7 @@
 // built and run on a machine without a GPU under the host sanitizers.  Each
 // records that it was reached and launches nothing.
 #include "../../paper_2204_06633_amd/csrc/batch_types.hpp"
+#include "../../paper_2204_06633_amd/csrc/gb_types.hpp"
 #include "../../paper_2204_06633_amd/csrc/internal.hpp"
 
 int g_launches = 0;
@@ -25,14 +26,18 @@ hipError_t run_reset_counter(int*, hipStream_t) { ++g_launches; return hipSucces
 hipError_t run_project_adjoint(int, const ProjAdjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_project_links(int, const ProjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_tdi(int, int, const TdiArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
-hipError_t run_fused_forward(int, int, int, const BatchFwdArgs&, int, hipStream_t) {
+hipError_t run_fused_forward(int, int, int, int, const BatchFwdArgs&, int, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
-int fused_blocks_per_cu(int, int, int) { return 3; }
+int fused_blocks_per_cu(int, int, int, int) { return 3; }
 hipError_t run_batch_tdi_adjoint(int, int, const BatchAdjArgs&, int64_t, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
 hipError_t run_batch_project_adjoint(int, const BatchAdjArgs&, int64_t, int64_t, hipStream_t) {
+  ++g_launches; return hipSuccess;
+}
+hipError_t run_gb_batch_finalize(const double*, const int64_t*, const double*, const int64_t*,
+                                 const double*, int64_t, double*, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
 }  // namespace lr

@@ -19,3 +19,11 @@ def test_cache_roundtrip(tmp_path):
     assert autotune.load_cache(p) == {}
     autotune.save_cache({"k": {"group": 2}}, p)
     assert autotune.load_cache(p) == {"k": {"group": 2}}
+
+
+def test_tile_variants():
+    """Groups 1, 2, 4 at tiles of 256, 512, 1024 link samples, except the
+    group of 4 at 1024 (its link rows would need 196 KB of LDS)."""
+    ok = {(g, t) for g in autotune.GROUPS for t in autotune.TILES if autotune.variant_exists(g, t)}
+    assert len(ok) == 8 and (4, 1024) not in ok and (4, 512) in ok and (1, 1024) in ok
+    assert not autotune.variant_exists(3, 512) and not autotune.variant_exists(2, 768)

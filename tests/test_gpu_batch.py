@@ -174,10 +174,11 @@ def test_graph_capture_replays_match_eager(torch_cuda):
             assert torch.equal(a, b), (r, k)
 
 
-def test_group_and_grid_do_not_change_results(torch_cuda, tmp_path):
+def test_group_tile_and_grid_do_not_change_results(torch_cuda, tmp_path):
     """Each template's arithmetic is the same whatever the group size and the
-    persistent grid: the outputs agree bit for bit; the autotuner returns one
-    of the candidates and caches it."""
+    persistent grid, and the tile length (256, 512, 1024 link samples per work
+    item): the outputs agree bit for bit; the autotuner returns one of the
+    candidates and caches it."""
     torch = torch_cuda
     from paper_2204_06633_amd import autotune, native
     n_out_list = [1200, 300, 2500, 777, 1, 1600]
@@ -188,16 +189,22 @@ def test_group_and_grid_do_not_change_results(torch_cuda, tmp_path):
     tpl = B["lay"].templates()
     t0 = B["grids"][0].t_start
     for g in (1, 2, 4):
-        b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g)
-        for blocks in (1, 3, b.blocks, 2 * b.blocks):
-            b.set_grid(blocks)
-            out = b.response(hp, hc, sky)
-            torch.cuda.synchronize()
-            assert torch.equal(out, ref), (g, blocks)
+        for tile in autotune.TILES:
+            if not autotune.variant_exists(g, tile):
+                continue
+            b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g, tile=tile)
+            assert b.tile == tile
+            for blocks in (1, 3, b.blocks, 2 * b.blocks):
+                b.set_grid(blocks)
+                out = b.response(hp, hc, sky)
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref), (g, tile, blocks)
     cache = str(tmp_path / "tune.json")
     r = autotune.tune(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky, reps=2, cache_path=cache)
     assert r["group"] in autotune.GROUPS and r["grid_scale"] in autotune.GRID_SCALES
-    assert len(r["trials"]) == len(autotune.GROUPS) * len(autotune.GRID_SCALES)
+    assert autotune.variant_exists(r["group"], r["tile"])
+    n_variants = sum(autotune.variant_exists(g, t) for g in autotune.GROUPS for t in autotune.TILES)
+    assert len(r["trials"]) == n_variants * len(autotune.GRID_SCALES)
     assert autotune.tune(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky,
                          cache_path=cache)["tuned_at"] == r["tuned_at"]
     b, _ = autotune.tuned_batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky, cache_path=cache)
@@ -242,3 +249,70 @@ def test_batch_adjoint_small_dt_against_oracle(torch_cuda):
                                            "AET")
         got = np.stack([ghp[ho:ho + g.n_h].cpu().numpy(), ghc[ho:ho + g.n_h].cpu().numpy()])
         cases.check(got, np.stack([rhp, rhc]), 1e-10, "template %d adjoint" % k)
+
+
+def test_waveform_mode_forward_and_parameter_adjoint(torch_cuda):
+    """lr_response_gb (h+ / hx synthesised in the fused kernel's windows from
+    the 8 source parameters) equals lr_gb_polarizations + lr_response bit
+    for bit, and the oracle (its own waveform, response) to 1e-11;
+    lr_response_adjoint_gb (straight to d/d params) equals the two-step
+    chain (lr_response_adjoint to g_h and the sky, lr_gb_polarizations_
+    adjoint) to 1e-9 per component and the oracle's chain (transposed
+    response, waveform vector-Jacobian product) for the six waveform
+    parameters to 1e-9; two runs agree bit for bit.  Uneven templates,
+    one empty."""
+    torch = torch_cuda
+    from oracle import waveform as owf
+    from paper_2204_06633_amd import native
+    n_out_list = [1300, 0, 777, 2048]
+    B = _build(torch, n_out_list, group=2, adjoint=True, seed=23)
+    batch = B["batch"]
+    params = _t(torch, B["params"])
+    gp_, gt_ = B["orbs"]
+    # the GPU waveform into the batch's h arrays (waveform time 0 at output 0)
+    hp = torch.zeros(max(batch.h_extent, 1), dtype=torch.float64, device="cuda")
+    hc = torch.zeros_like(hp)
+    for k, g in enumerate(B["grids"]):
+        if g.n_out == 0:
+            continue
+        ho = B["lay"].h_offsets[k]
+        a, b = native.gb_polarizations(params[k:k + 1].contiguous(), -g.out_start, g.n_h, g.dt)
+        hp[ho:ho + g.n_h] = a[0]
+        hc[ho:ho + g.n_h] = b[0]
+    sky = params[:, 6:8].contiguous()
+    out_ref = batch.response(hp, hc, sky)
+    out_gb = batch.response_gb(params)
+    torch.cuda.synchronize()
+    assert torch.equal(out_gb[:batch.out_extent], out_ref[:batch.out_extent])
+    op = oracle.Orbits.from_samples(B["sp"])
+    ot = op if B["st"] is B["sp"] else oracle.Orbits.from_samples(B["st"])
+    rng = np.random.default_rng(4)
+    g_out = torch.zeros_like(out_ref)
+    g_out[:batch.out_extent] = _t(torch, rng.standard_normal(batch.out_extent))
+    g_par = batch.adjoint_gb(params, g_out)
+    g_par2 = batch.adjoint_gb(params, g_out)
+    ghp, ghc, gsky = batch.adjoint(hp, hc, sky, g_out)
+    torch.cuda.synchronize()
+    assert torch.equal(g_par, g_par2)
+    for k, g in enumerate(B["grids"]):
+        if g.n_out == 0:
+            assert torch.all(g_par[k] == 0)
+            continue
+        ho, oo = B["lay"].h_offsets[k], B["lay"].out_offsets[k]
+        two = native.gb_polarizations_adjoint(params[k:k + 1].contiguous(), -g.out_start, g.dt,
+                                              ghp[ho:ho + g.n_h][None].contiguous(),
+                                              ghc[ho:ho + g.n_h][None].contiguous())[0]
+        two[6:8] = gsky[k]
+        got = g_par[k].cpu().numpy()
+        ref = two.cpu().numpy()
+        assert np.all(np.abs(got - ref) <= 1e-9 * np.abs(ref)), (k, got, ref)
+        # the oracle: waveform, transposed response, waveform VJP
+        p = B["params"][k]
+        h_p, h_c = owf.polarizations(p, g.waveform_times())
+        out_o = oracle.response(op, ot, g, h_p, h_c, p[6], p[7], 25, 2, "AET")
+        cases.check(out_gb[oo:oo + 3 * g.n_out].view(3, g.n_out).cpu().numpy(), out_o, TOL,
+                    "template %d waveform-mode forward" % k)
+        go = g_out[oo:oo + 3 * g.n_out].view(3, g.n_out).cpu().numpy()
+        rhp, rhc = oracle.response_adjoint(op, ot, g, p[6], p[7], 25, 2, go, "AET")
+        vjp = owf.polarizations_vjp(p, g.waveform_times(), rhp, rhc)
+        assert np.all(np.abs(got[:6] - vjp[:6]) <= 1e-9 * np.abs(vjp[:6])), (k, got, vjp)
