@@ -172,36 +172,67 @@ class PTSampler:
 
 
 class BatchLoglike:
-    """log L(theta) for walkers sharing one output grid: lr_gb_polarizations
-    -> lr_response (fused batch kernel) -> lr_fd_loglike statistics, ``m``
-    walkers per call.  ``batch``: a native.Batch of ``m`` equal templates
-    laid out back to back, each with n_h h-samples at waveform times
-    (k0 + j) dt (k0 = -out_start); ``plan``: an FdPlan on the data;
-    theta [M][8] with M a multiple of m."""
+    """log L(theta) for walkers sharing one output grid: lr_response_gb (the
+    fused batch kernel synthesising each walker's h+ / hx in its LDS windows
+    from the parameter rows) -> lr_fd_loglike statistics, ``m`` walkers per
+    call.  ``batch``: a native.Batch of ``m`` equal templates (their h
+    offsets unused), each with n_h h-samples at waveform times (k0 + j) dt,
+    k0 = -out_start; ``plan``: an FdPlan on the data; theta [M][8] with M a
+    multiple of m.
 
-    def __init__(self, batch, plan, k0, n_h, dt, m, device="cuda"):
+    With ``graph`` (the default) the sequence of one chunk of m walkers
+    (sampling coordinates -> source parameters, response, statistics,
+    log L) is captured once in a HIP graph with static input and output
+    buffers and replayed for every chunk.  Replays give the same numbers as
+    the eager sequence, bit for bit."""
+
+    def __init__(self, batch, plan, k0, n_h, dt, m, device="cuda", graph=True):
         self.batch, self.plan, self.m = batch, plan, m
         self.k0, self.n_h, self.dt = int(k0), int(n_h), float(dt)
         self.n_out = plan.n
         self.out = torch.empty(batch.out_extent, dtype=torch.float64, device=device)
         self.stats = torch.empty((m, 3), dtype=torch.float64, device=device)
-        self.hp = torch.empty((m, self.n_h), dtype=torch.float64, device=device)
-        self.hc = torch.empty_like(self.hp)
+        self.theta_in = torch.zeros((m, NDIM), dtype=torch.float64, device=device)
+        self.src = torch.empty((m, NDIM), dtype=torch.float64, device=device)
+        self.ll_out = torch.empty(m, dtype=torch.float64, device=device)
+        self.use_graph = bool(graph)
+        self.graph = None
+
+    def _chunk(self):
+        """One chunk on the current stream, from theta_in to ll_out."""
+        m = self.m
+        self.src.copy_(to_source(self.theta_in))
+        self.batch.response_gb(self.src, out=self.out)
+        h = self.out[:m * 3 * self.n_out].view(m, 3, self.n_out)
+        self.plan.loglike(h, want_grad=False, stats=self.stats)
+        torch.mul(self.stats[:, 0], -0.5, out=self.ll_out)
+
+    def _capture(self):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._chunk()                               # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._chunk()
+        self.graph = g
 
     def __call__(self, theta):
-        from . import native
         M, m = theta.shape[0], self.m
         if M % m:
             raise ValueError("%d proposals for a batch of %d walkers" % (M, m))
         out = []
         for c in range(0, M, m):
-            src = to_source(theta[c:c + m]).contiguous()
-            native.gb_polarizations(src, self.k0, self.n_h, self.dt, hp=self.hp, hc=self.hc)
-            self.batch.response(self.hp.view(-1), self.hc.view(-1), src[:, 6:8].contiguous(),
-                                out=self.out)
-            h = self.out[:m * 3 * self.n_out].view(m, 3, self.n_out)
-            self.plan.loglike(h, want_grad=False, stats=self.stats)
-            out.append(-0.5 * self.stats[:, 0].clone())
+            self.theta_in.copy_(theta[c:c + m])
+            if self.use_graph:
+                if self.graph is None:
+                    self._capture()
+                self.graph.replay()
+            else:
+                self._chunk()
+            out.append(self.ll_out.clone())
         return torch.cat(out)
 
 
@@ -236,24 +267,23 @@ def setup_run(sc, device="cuda", betas=(1.0, 0.25, 0.0625, 0.0), seed=9, tune=Tr
     g = sc.grid
     orb = native.Orbits.from_samples(sc.orbits, device=dev)
     src_all = torch.tensor(sc.injection, dtype=torch.float64, device=dev).repeat(sc.m, 1)
-    hp, hc = native.gb_polarizations(src_all, -g.out_start, g.n_h, g.dt)
     if tune:
         batch, tuned = autotune.tuned_batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt,
-                                            sc.order, sc.generation, "AET", hp.view(-1),
-                                            hc.view(-1), src_all[:, 6:8].contiguous())
+                                            sc.order, sc.generation, "AET", None, None, None,
+                                            params=src_all)
     else:
         batch = native.Batch(sc.layout(sc.m), orb, orb, g.t_start, g.dt, sc.order,
                              sc.generation, "AET", group=2, device=dev)
         tuned = {"group": 2, "grid_scale": 1.0}
     if log:
-        log("sampler: %s, %d proposals per half step, group %d, grid x%.1f"
-            % (sc.name, sc.m, tuned["group"], tuned["grid_scale"]))
+        log("sampler: %s, %d proposals per half step, group %d, tile %d, grid x%.1f"
+            % (sc.name, sc.m, tuned["group"], batch.tile, tuned["grid_scale"]))
     # noise-free data: the injection through the same batch machinery
     one = native.Batch(sc.layout(1), orb, orb, g.t_start, g.dt, sc.order, sc.generation, "AET",
                        group=1, device=dev)
     data = torch.empty(one.out_extent, dtype=torch.float64, device=dev)
-    one.response(hp[0].contiguous(), hc[0].contiguous(), src_all[:1, 6:8].contiguous(), out=data)
-    del hp, hc, one
+    one.response_gb(src_all[:1].contiguous(), out=data)
+    del one
     n_fft = native.fd_length(g.n_out)
     w_ae, w_t = inputs.noise_weights(n_fft, g.dt)
     plan = native.FdPlan(data.view(3, g.n_out), torch.tensor(w_ae, device=dev),

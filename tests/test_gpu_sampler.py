@@ -1,6 +1,9 @@
 """The tempered ensemble sampler (Sec. II.B) driving the batched GPU
 response and the frequency-domain likelihood, against the oracle's step
 driving the oracle's response and likelihood, on the same random numbers.
+The GPU likelihood of a half step is one replay of a captured HIP graph
+(polarisations, response, statistics); replays equal the eager sequence bit
+for bit.
 
 Bars: identical accept and swap decisions (every decision's margin
 |log u - log r| is checked to exceed 1e-6, so rounding cannot flip one);
@@ -63,6 +66,19 @@ def test_sampler_steps_match_oracle(torch_cuda):
     scale = np.array([1e-2, 1e-6, 1e-16, 1e-2, 1e-2, 1e-2, 1e-3, 1e-3])
     x0 = th0 + scale * rng.standard_normal((sc.T, sc.W, 8))
     x, ll, lp = ps.initial(torch.tensor(x0, device=dev))
+    assert ps.loglike.graph is not None                     # the graph path ran
+    # replays against the eager sequence on new inputs, with eager work and
+    # synchronisations in between
+    eager = sampler.BatchLoglike(batch, plan, -g.out_start, g.n_h, g.dt, sc.m, graph=False)
+    pert = np.random.default_rng(5)
+    for r in range(3):
+        th = x.reshape(-1, 8) + torch.tensor(scale * pert.standard_normal((sc.T * sc.W, 8)),
+                                             device=dev)
+        a = ps.loglike(th)
+        torch.cuda.synchronize()
+        b = eager(th)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), r
     xo = x0.copy()
     llo = np.array(oracle_loglike(x0.reshape(-1, 8))).reshape(sc.T, sc.W)
     lpo = np.zeros((sc.T, sc.W))
