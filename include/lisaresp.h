@@ -90,9 +90,18 @@ size_t lr_orbits_bytes(int64_t n);
 int lr_orbits_init(double t0, double dt, int64_t n, const double *x_sc, const double *ltt,
                    void *d_storage, size_t bytes, lr_orbits *out, void *stream);
 
+/* [host only] The same spline fit without a device: fills `out` with t0, dt,
+ * n and the bounds L_min, L_max, R_max (coef = NULL), which is all that
+ * lr_projection_padding and lr_tdi_padding read -- so a caller can size its
+ * padded buffers before anything is allocated or uploaded.  The handle is
+ * not valid for the compute calls.  Errors: LR_E_ARG as lr_orbits_init. */
+int lr_orbits_bounds(double t0, double dt, int64_t n, const double *x_sc, const double *ltt,
+                     lr_orbits *out);
+
 /* Samples of h+/hx that lr_project_links needs before the first and after
  * the last link sample it writes, for any sky position (from the orbit
- * bounds and the stencil half-width). */
+ * bounds and the stencil half-width).  `orb` from lr_orbits_init or
+ * lr_orbits_bounds. */
 int lr_projection_padding(const lr_orbits *orb, int order, double dt, int64_t *front,
                           int64_t *back);
 

@@ -126,6 +126,15 @@ int check_orbits(const lr_orbits* o) {
   return LR_OK;
 }
 
+// The padding rules need the bounds only (a handle from lr_orbits_bounds,
+// without device storage, will do).
+int check_orbit_bounds(const lr_orbits* o) {
+  if (!o || o->n < 4 || !(o->dt > 0.0) || !is_finite(o->L_min) || !is_finite(o->L_max) ||
+      !is_finite(o->R_max))
+    return fail(LR_E_ARG, "orbits not initialised");
+  return LR_OK;
+}
+
 // Every time t0 + j*dt, j in [j0, j1], lies on the orbit grid.
 int check_orbit_span(const lr_orbits* o, double t_off, double dt, int64_t j0, int64_t j1) {
   const double span = (double)(o->n - 1) * o->dt;
@@ -185,43 +194,23 @@ int check_tdi(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, int gen
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-const char* lr_status_str(int s) {
-  switch (s) {
-    case LR_OK: return "LR_OK";
-    case LR_E_ARG: return "LR_E_ARG: invalid argument";
-    case LR_E_RANGE: return "LR_E_RANGE: stencil or orbit evaluation outside the data";
-    case LR_E_UNSUPPORTED: return "LR_E_UNSUPPORTED: unsupported order, generation or mode";
-    case LR_E_WORKSPACE: return "LR_E_WORKSPACE: storage or workspace too small";
-    case LR_E_HIP: return "LR_E_HIP: HIP runtime error";
-    default: return "unknown lr_status";
-  }
-}
-
-const char* lr_last_error(void) { return g_err.c_str(); }
-
-int lr_abi_version(void) { return 4; }
-
-size_t lr_orbits_bytes(int64_t n) {
-  if (n < 4) return 0;
-  return (size_t)(n - 1) * lr::kSegStride * sizeof(double);
-}
-
-int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
-                   void* d_storage, size_t bytes, lr_orbits* out, void* stream) {
-  if (!out || !x_sc || !ltt || !d_storage) return fail(LR_E_ARG, "null pointer");
+// Spline fit of the coarse samples (Sec. IV.A: positions and light times are
+// interpolated with not-a-knot cubic splines) and the rigorous bounds of the
+// fitted light times and distances; host only.
+int fit_orbits(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
+               std::vector<double>& coef, lr_orbits& bounds) {
+  if (!x_sc || !ltt) return fail(LR_E_ARG, "null pointer");
   if (n < 4) return fail(LR_E_ARG, "need at least 4 coarse orbit samples (got %lld)", (long long)n);
   if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0)) return fail(LR_E_ARG, "bad orbit grid t0/dt");
-  if (bytes < lr_orbits_bytes(n))
-    return fail(LR_E_WORKSPACE, "orbit storage %zu bytes < %zu", bytes, lr_orbits_bytes(n));
   for (int64_t i = 0; i < n * 9; ++i)
     if (!is_finite(x_sc[i])) return fail(LR_E_ARG, "non-finite spacecraft position");
   for (int64_t i = 0; i < n * 6; ++i)
     if (!is_finite(ltt[i])) return fail(LR_E_ARG, "non-finite light travel time");
 
   const int64_t nseg = n - 1;
-  std::vector<double> coef((size_t)nseg * lr::kSegStride, 0.0);
+  coef.assign((size_t)nseg * lr::kSegStride, 0.0);
   for (int s = 0; s < 9; ++s)
     fit_not_a_knot(x_sc + s, 9, n, dt, coef.data() + 4 * s, lr::kSegStride);
   for (int l = 0; l < 6; ++l)
@@ -245,6 +234,63 @@ int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const do
       lmin = std::min(lmin, c[0] - var);
     }
   }
+  bounds = lr_orbits{};
+  bounds.t0 = t0;
+  bounds.dt = dt;
+  bounds.n = n;
+  bounds.coef = nullptr;
+  bounds.L_min = lmin;
+  bounds.L_max = lmax;
+  bounds.R_max = rmax;
+  return LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lr_status_str(int s) {
+  switch (s) {
+    case LR_OK: return "LR_OK";
+    case LR_E_ARG: return "LR_E_ARG: invalid argument";
+    case LR_E_RANGE: return "LR_E_RANGE: stencil or orbit evaluation outside the data";
+    case LR_E_UNSUPPORTED: return "LR_E_UNSUPPORTED: unsupported order, generation or mode";
+    case LR_E_WORKSPACE: return "LR_E_WORKSPACE: storage or workspace too small";
+    case LR_E_HIP: return "LR_E_HIP: HIP runtime error";
+    default: return "unknown lr_status";
+  }
+}
+
+const char* lr_last_error(void) { return g_err.c_str(); }
+
+int lr_abi_version(void) { return 4; }
+
+size_t lr_orbits_bytes(int64_t n) {
+  if (n < 4) return 0;
+  return (size_t)(n - 1) * lr::kSegStride * sizeof(double);
+}
+
+
+int lr_orbits_bounds(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
+                     lr_orbits* out) {
+  if (!out) return fail(LR_E_ARG, "null pointer");
+  std::vector<double> coef;
+  lr_orbits b;
+  if (int st = fit_orbits(t0, dt, n, x_sc, ltt, coef, b)) return st;
+  *out = b;
+  return LR_OK;
+}
+
+int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
+                   void* d_storage, size_t bytes, lr_orbits* out, void* stream) {
+  if (!out || !x_sc || !ltt || !d_storage) return fail(LR_E_ARG, "null pointer");
+  if (n < 4) return fail(LR_E_ARG, "need at least 4 coarse orbit samples (got %lld)", (long long)n);
+  if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0)) return fail(LR_E_ARG, "bad orbit grid t0/dt");
+  if (bytes < lr_orbits_bytes(n))
+    return fail(LR_E_WORKSPACE, "orbit storage %zu bytes < %zu", bytes, lr_orbits_bytes(n));
+  std::vector<double> coef;
+  lr_orbits b;
+  if (int st = fit_orbits(t0, dt, n, x_sc, ltt, coef, b)) return st;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(d_storage, coef.data(), coef.size() * sizeof(double),
@@ -253,19 +299,14 @@ int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const do
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "lr_orbits_init sync");
 
-  out->t0 = t0;
-  out->dt = dt;
-  out->n = n;
+  *out = b;
   out->coef = d_storage;
-  out->L_min = lmin;
-  out->L_max = lmax;
-  out->R_max = rmax;
   return LR_OK;
 }
 
 int lr_projection_padding(const lr_orbits* orb, int order, double dt, int64_t* front,
                           int64_t* back) {
-  if (int st = check_orbits(orb)) return st;
+  if (int st = check_orbit_bounds(orb)) return st;
   if (!front || !back) return fail(LR_E_ARG, "null pointer");
   if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
   if (!(dt > 0.0) || !is_finite(dt)) return fail(LR_E_ARG, "bad dt");
@@ -280,7 +321,7 @@ int lr_projection_padding(const lr_orbits* orb, int order, double dt, int64_t* f
 
 int lr_tdi_padding(const lr_orbits* orb, int order, int generation, double dt, int64_t* front,
                    int64_t* back) {
-  if (int st = check_orbits(orb)) return st;
+  if (int st = check_orbit_bounds(orb)) return st;
   if (!front || !back) return fail(LR_E_ARG, "null pointer");
   if (!valid_order(order)) return fail(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
   if (generation != 1 && generation != 2)

@@ -63,6 +63,7 @@ def lib():
     L.lr_orbits_bytes.restype = ctypes.c_size_t
     L.lr_orbits_bytes.argtypes = [i64]
     L.lr_orbits_init.argtypes = [d, d, i64, vp, vp, vp, ctypes.c_size_t, po, vp]
+    L.lr_orbits_bounds.argtypes = [d, d, i64, vp, vp, po]
     L.lr_projection_padding.argtypes = [po, i32, d, P(i64), P(i64)]
     L.lr_tdi_padding.argtypes = [po, i32, i32, d, P(i64), P(i64)]
     L.lr_project_links.argtypes = [po, d, d, i64, vp, vp, vp, i32, i64, i64, vp, vp]
@@ -78,7 +79,7 @@ def lib():
     L.lr_noalloc_scratch_bytes.argtypes = []
     L.lr_project_adjoint_noalloc.argtypes = [po, d, d, i64, vp, vp, vp, i32, i64, i64, vp, vp, vp,
                                              vp, vp]
-    for name in ("lr_orbits_init", "lr_projection_padding", "lr_tdi_padding",
+    for name in ("lr_orbits_init", "lr_orbits_bounds", "lr_projection_padding", "lr_tdi_padding",
                  "lr_project_links", "lr_tdi_combine", "lr_tdi_adjoint", "lr_project_adjoint",
                  "lr_loglike", "lr_project_adjoint_noalloc"):
         getattr(L, name).restype = i32
@@ -177,6 +178,30 @@ class Orbits:
         _check(lib().lr_tdi_padding(self.ref, int(order), int(generation), float(dt),
                                     ctypes.byref(f), ctypes.byref(b)), "lr_tdi_padding")
         return f.value, b.value
+
+
+class OrbitBounds:
+    """Host-only orbit handle (lr_orbits_bounds): the spline fit's bounds of
+    the light times and distances, enough for the padding rules, with no
+    device involved (sizing buffers before anything is allocated)."""
+
+    def __init__(self, t0, dt, x, ltt):
+        import numpy as np
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, 3, 3))
+        ltt = np.ascontiguousarray(np.asarray(ltt, dtype=np.float64).reshape(-1, 6))
+        if ltt.shape[0] != x.shape[0]:
+            raise ValueError("x and ltt have different lengths")
+        self.c = lr_orbits()
+        _check(lib().lr_orbits_bounds(float(t0), float(dt), x.shape[0], x.ctypes.data,
+                                      ltt.ctypes.data, ctypes.byref(self.c)), "lr_orbits_bounds")
+
+    @classmethod
+    def from_samples(cls, s):
+        return cls(s.t0, s.dt, s.x, s.ltt)
+
+    ref = Orbits.ref
+    projection_padding = Orbits.projection_padding
+    tdi_padding = Orbits.tdi_padding
 
 
 # ---------------------------------------------------------------------------

@@ -44,6 +44,18 @@ int main() {
   // the fit runs; the copy to the (absent) device then fails cleanly or succeeds
   const int st = lr_orbits_init(0.0, dto, n, x.data(), ltt.data(), store.data(), nb, &orb, nullptr);
   CHECK(st == LR_OK || st == LR_E_HIP);
+  // the host-only fit: bounds without a device, enough for the padding rules
+  lr_orbits hb{};
+  CHECK(lr_orbits_bounds(0.0, dto, 3, x.data(), ltt.data(), &hb) == LR_E_ARG);
+  CHECK(lr_orbits_bounds(0.0, dto, n, xnan.data(), ltt.data(), &hb) == LR_E_ARG);
+  CHECK(lr_orbits_bounds(0.0, dto, n, x.data(), ltt.data(), nullptr) == LR_E_ARG);
+  CHECK(lr_orbits_bounds(0.0, dto, n, x.data(), ltt.data(), &hb) == LR_OK);
+  CHECK(hb.coef == nullptr && hb.L_min <= hb.L_max && hb.L_max < 8.5 && hb.R_max > AU);
+  {
+    int64_t hf = 0, hbk = 0;
+    CHECK(lr_tdi_padding(&hb, 25, 2, 10.0, &hf, &hbk) == LR_OK && hf > 13 && hbk >= 13);
+    CHECK(lr_projection_padding(&hb, 25, 10.0, &hf, &hbk) == LR_OK && hf > 13 && hbk > 13);
+  }
   // a handle as lr_orbits_init fills it, for the host-only calls below
   orb.t0 = 0.0; orb.dt = dto; orb.n = n; orb.coef = store.data();
   orb.L_min = 8.3; orb.L_max = 8.4; orb.R_max = 1.02 * AU;

@@ -1,0 +1,258 @@
+"""Host-side replay of the kernels' stencil and window arithmetic (CPU only).
+
+The library sizes every padded series and every fused work item from its
+padding rules (lr_tdi_padding, lr_projection_padding), which rest on the
+bounds of its own spline fit (here from the host-only lr_orbits_bounds, no
+device involved).  This test takes the delays from the oracle's
+independently fitted orbit splines at every output sample of the benchmark
+workloads and replays the index arithmetic of the kernels on them:
+
+* shift s = floor(-d / dt) of a delay d (Sec. IV.E: integer part of the
+  retarded position), taps s - (H - 1) .. s + H for N = order + 1 taps,
+  H = N / 2;
+* plain path: every TDI tap of an output and every projection tap of a link
+  sample lies inside the series padded by the library's rule;
+* fused batched forward (Sec. IV.C on a work item's link rows): output r of a
+  work item sits at row F + r of rows of `tile` link samples; a stencil
+  start is clamped into [0, tile - 1 - N] (a lane's pair of samples reads one
+  element past its last tap), which only a wrong padding would hit -- so no
+  stored output may need the clamp, for every tile length the tuner offers;
+* the fused projection stages one window of tile + N + 64 samples per work
+  item; the test checks the benchmark workloads fit it (else the kernel takes
+  its slower global-memory path, correct but not what is measured).
+
+The TDI delays are the chained sums of light times of eqs. (tdi1)/(tdi2)
+(the oracle's term lists), the projection delays L_ij + k.x_j / c and
+k.x_i / c of Sec. IV.B.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tdi_terms
+from paper_2204_06633_amd import native, workloads
+
+C_LIGHT = 299792458.0
+TILES = (256, 512, 1024)
+SLACK = 64          # window samples beyond tile + taps in the fused projection
+CHUNK = 1 << 20
+
+
+def _spline(orb, series, tau):
+    """Oracle spline series (0..8 positions, 9..14 light times) at times
+    tau since the first coarse sample (numpy evaluation of its coefficients,
+    segment clamped as the oracle does)."""
+    k = np.clip(np.floor(tau / orb.dt).astype(np.int64), 0, orb.nseg - 1)
+    u = tau - k * orb.dt
+    c = orb.coef[series][k]
+    return c[:, 0] + u * (c[:, 1] + u * (c[:, 2] + u * c[:, 3]))
+
+
+def _term_paths(generation):
+    """Delayed terms' chains as lists of link indices (the undelayed terms,
+    paths of one spacecraft, read the sample itself)."""
+    paths = set()
+    for t in tdi_terms.michelson_terms(generation):
+        if len(t.path) > 1:
+            paths.add(tuple(tdi_terms.LINKS.index((t.path[i], t.path[i + 1]))
+                            for i in range(len(t.path) - 1)))
+    return sorted(paths)
+
+
+@functools.lru_cache(maxsize=None)
+def _year_case():
+    return workloads.year_case("AET")
+
+
+def _tdi_shift_range(orb_samples, t_abs, dt, generation):
+    """min and max over the delayed TDI terms of floor(-d/dt) at each time,
+    with the oracle's light times at the output time (chains summed)."""
+    orb = oracle.Orbits.from_samples(orb_samples)
+    paths = _term_paths(generation)
+    lo = np.empty(t_abs.size, dtype=np.int64)
+    hi = np.empty(t_abs.size, dtype=np.int64)
+    lt_lo, lt_hi = np.inf, -np.inf
+    for a in range(0, t_abs.size, CHUNK):
+        tau = t_abs[a:a + CHUNK] - orb.t0
+        L = [_spline(orb, 9 + l, tau) for l in range(6)]
+        lt_lo = min(lt_lo, min(x.min() for x in L))
+        lt_hi = max(lt_hi, max(x.max() for x in L))
+        s_lo = s_hi = None
+        for p in paths:
+            d = L[p[0]].copy()
+            for l in p[1:]:
+                d += L[l]
+            s = np.floor(-d / dt).astype(np.int64)
+            s_lo = s if s_lo is None else np.minimum(s_lo, s)
+            s_hi = s if s_hi is None else np.maximum(s_hi, s)
+        lo[a:a + CHUNK], hi[a:a + CHUNK] = s_lo, s_hi
+    return lo, hi, lt_lo, lt_hi
+
+
+def _projection_shift_range(orb_samples, t_abs, dt, lam, beta):
+    """min and max over the nine positions of floor(-d/dt) at each link
+    sample time, for one sky position, with the oracle's orbits."""
+    orb = oracle.Orbits.from_samples(orb_samples)
+    k, _, _ = oracle.sky_basis(lam, beta)
+    recv = [r - 1 for r, _ in tdi_terms.LINKS]
+    emit = [e - 1 for _, e in tdi_terms.LINKS]
+    lo = np.empty(t_abs.size, dtype=np.int64)
+    hi = np.empty(t_abs.size, dtype=np.int64)
+    r_max = 0.0
+    for a in range(0, t_abs.size, CHUNK):
+        tau = t_abs[a:a + CHUNK] - orb.t0
+        x = np.stack([np.stack([_spline(orb, 3 * s + c, tau) for c in range(3)])
+                      for s in range(3)])                      # [sc][xyz][t]
+        r_max = max(r_max, float(np.sqrt((x ** 2).sum(axis=1)).max()))
+        kx = np.einsum("c,sct->st", k, x) / C_LIGHT           # [sc][t]
+        ds = [kx[s] for s in range(3)]                        # receptions
+        for l in range(6):                                    # emissions
+            assert recv[l] != emit[l]
+            ds.append(_spline(orb, 9 + l, tau) + kx[emit[l]])
+        sh = np.floor(-np.stack(ds) / dt).astype(np.int64)
+        lo[a:a + CHUNK], hi[a:a + CHUNK] = sh.min(axis=0), sh.max(axis=0)
+    return lo, hi, r_max
+
+
+def _tdi_taps_ok(F, B, lo, hi, n_taps):
+    """Plain path: the taps of output o, y-indices F + o + s - (H-1) ..
+    F + o + s + H, inside the padded series [0, F + n_out + B)."""
+    H = n_taps // 2
+    o = np.arange(lo.size, dtype=np.int64)
+    return bool((F + o + lo - (H - 1)).min() >= 0 and (F + o + hi + H).max() <= F + lo.size - 1 + B)
+
+
+def _check_tdi(orb_samples, t_start, dt, n_out, order, generation, check_tiles):
+    n_taps = order + 1
+    H = n_taps // 2
+    bounds = native.OrbitBounds.from_samples(orb_samples)
+    F, B = bounds.tdi_padding(order, generation, dt)
+    t = t_start + dt * np.arange(n_out, dtype=np.float64)
+    lo, hi, lt_lo, lt_hi = _tdi_shift_range(orb_samples, t, dt, generation)
+    # the fit's rigorous bounds contain the (independently fitted) light times
+    assert bounds.c.L_min <= lt_lo and lt_hi <= bounds.c.L_max, \
+        (bounds.c.L_min, lt_lo, lt_hi, bounds.c.L_max)
+    assert _tdi_taps_ok(F, B, lo, hi, n_taps)
+    if not check_tiles:
+        return F, B
+    o = np.arange(n_out, dtype=np.int64)
+    for tile in TILES:
+        T_out = (tile - F - B) & ~1          # outputs per work item (the batch plan's rule)
+        assert T_out >= 2
+        r = o % T_out
+        top = tile - 1 - n_taps
+        start_lo = F + r + lo - (H - 1)
+        start_hi = F + r + hi - (H - 1)
+        assert start_lo.min() >= 0, (tile, int(start_lo.min()))
+        assert start_hi.max() <= top, (tile, int(start_hi.max()), top)
+    return F, B
+
+
+def _check_projection(orb_samples, t_start, dt, F, B, n_out, order, skies):
+    """Link samples of one template: output-relative indices -F .. n_out + B - 1
+    (link index i = 0 .. n_y - 1)."""
+    n_taps = order + 1
+    H = n_taps // 2
+    n_y = F + n_out + B
+    bounds = native.OrbitBounds.from_samples(orb_samples)
+    front, back = bounds.projection_padding(order, dt)
+    i = np.arange(n_y, dtype=np.int64)
+    t = t_start + dt * (i - F).astype(np.float64)
+    for lam, beta in skies:
+        lo, hi, r_max = _projection_shift_range(orb_samples, t, dt, lam, beta)
+        assert r_max <= bounds.c.R_max
+        # taps of link sample i at h-indices (relative to the first link
+        # sample) i + s - (H-1) .. i + s + H
+        assert (i + lo - (H - 1)).min() >= -front
+        assert (i + hi + H).max() <= n_y - 1 + back
+        a = i + lo - (H - 1)
+        b = i + hi + H
+        for tile in TILES:
+            # work item tl holds link samples tl*T_out .. tl*T_out + tile - 1
+            # and stages the window of their taps
+            T_out = (tile - F - B) & ~1
+            w = min(tile, n_y)
+            a_min = np.lib.stride_tricks.sliding_window_view(a, w)[::T_out].min(axis=1)
+            b_max = np.lib.stride_tricks.sliding_window_view(b, w)[::T_out].max(axis=1)
+            worst = int((b_max - a_min).max() + 1)
+            assert worst <= tile + n_taps + SLACK, (tile, worst)
+
+
+def test_year_template_taps_in_bounds():
+    case = _year_case()
+    g = case.grid
+    F, B = _check_tdi(case.orbits_tdi, g.t_start, g.dt, g.n_out, case.order, case.generation,
+                      check_tiles=False)
+    _check_projection(case.orbits_proj, g.t_start, g.dt, F, B, g.n_out, case.order,
+                      [(case.lam, case.beta)])
+
+
+def test_uneven_batch_work_items_in_bounds():
+    """Every template of the batch starts at output 0 of the shared grid and
+    the TDI delays depend on the orbits only, so the longest template's
+    outputs cover every work item of every template."""
+    bc = workloads.uneven_batch_case()
+    n_max = max(g.n_out for g in bc.grids)
+    F, B = _check_tdi(bc.orbits_tdi, bc.t0, bc.dt, n_max, bc.order, bc.generation,
+                      check_tiles=True)
+    pick = np.linspace(0, len(bc.grids) - 1, 3).astype(int)
+    _check_projection(bc.orbits_proj, bc.t0, bc.dt, F, B, n_max, bc.order,
+                      [tuple(bc.params[k, 6:8]) for k in pick])
+
+
+def test_walker_batch_work_items_in_bounds():
+    """Hybrid templates: rigid equal-arm orbits for the TDI delays, Keplerian
+    ones for the projection."""
+    bc = workloads.walker_batch_case(8)
+    n = bc.grids[0].n_out
+    F, B = _check_tdi(bc.orbits_tdi, bc.t0, bc.dt, n, bc.order, bc.generation, check_tiles=True)
+    _check_projection(bc.orbits_proj, bc.t0, bc.dt, F, B, n, bc.order,
+                      [tuple(bc.params[0, 6:8])])
+
+
+@pytest.mark.parametrize("order", [1, 7, 31])
+def test_short_dt_and_orders_in_bounds(order):
+    """A day at dt = 2 s (TDI stencils spanning ~30 samples) and the extreme
+    orders: the padding rules still hold, and every tile length still fits."""
+    bc = workloads.make_batch_case("day_dt2", [43200], 2.0, order, 2, "AET", seed=9)
+    F, B = _check_tdi(bc.orbits_tdi, bc.t0, bc.dt, 43200, order, 2, check_tiles=True)
+    _check_projection(bc.orbits_proj, bc.t0, bc.dt, F, B, 43200, order,
+                      [tuple(bc.params[0, 6:8])])
+
+
+def test_replay_catches_a_short_padding():
+    """The replay is not vacuous: with one sample of front (back) padding
+    less than the stencils of this workload really need, it fails."""
+    case = _year_case()
+    g = case.grid
+    n_taps = case.order + 1
+    H = n_taps // 2
+    bounds = native.OrbitBounds.from_samples(case.orbits_tdi)
+    F, B = bounds.tdi_padding(case.order, case.generation, g.dt)
+    t = g.t_start + g.dt * np.arange(g.n_out, dtype=np.float64)
+    lo, hi, _, _ = _tdi_shift_range(case.orbits_tdi, t, g.dt, case.generation)
+    o = np.arange(g.n_out, dtype=np.int64)
+    need_f = int(-(o + lo - (H - 1)).min())            # front samples the taps reach
+    need_b = int((o + hi + H).max()) - (g.n_out - 1)  # back samples
+    assert 0 < need_f <= F and need_b <= B
+    assert _tdi_taps_ok(need_f, need_b, lo, hi, n_taps)
+    assert not _tdi_taps_ok(need_f - 1, need_b, lo, hi, n_taps)
+    assert not _tdi_taps_ok(need_f, need_b - 1, lo, hi, n_taps)
+
+
+def test_orbit_bounds_host_only_matches_rules():
+    """lr_orbits_bounds gives the padding without a device, with the same
+    values for every order and generation as the rules' formulas."""
+    case = _year_case()
+    b = native.OrbitBounds.from_samples(case.orbits_tdi)
+    assert b.c.coef is None or b.c.coef == 0
+    for order in range(1, 32, 2):
+        half = (order + 1) // 2
+        for gen, chain in ((1, 3), (2, 7)):
+            f, bk = b.tdi_padding(order, gen, 10.0)
+            assert f == int(np.ceil(chain * b.c.L_max / 10.0)) + half + 1
+            assert bk == int(np.ceil(-chain * min(b.c.L_min, 0.0) / 10.0)) + half + 1
+    with pytest.raises(native.LisaRespError):
+        native.OrbitBounds(0.0, 1e4, np.zeros((3, 3, 3)), np.zeros((3, 6)))
