@@ -289,8 +289,10 @@ int lr_response(const lr_batch *b, const double *hp, const double *hc, const dou
  * at t = (j - out_start) dt: waveform time 0 at output sample 0, the
  * convention of lr_gb_polarizations with k0 = -out_start.  Bit for bit equal
  * to lr_gb_polarizations followed by lr_response.  The templates' h_offset is
- * not used; the batch needs no h arrays.  Graph-capturable.  Errors:
- * LR_E_ARG, LR_E_HIP. */
+ * not used; the batch needs no h arrays.  Graph-capturable.  Compiled for
+ * batches prepared with group 1 or 2 at tile 512 and group 2 at tile 1024
+ * (the waveform code is its own kernel variant).  Errors: LR_E_ARG,
+ * LR_E_UNSUPPORTED (another group/tile pair), LR_E_HIP. */
 int lr_response_gb(const lr_batch *b, const double *params, double *out, void *stream);
 
 /* Transpose of lr_response (needs a batch prepared with adjoint != 0):

@@ -38,9 +38,12 @@ TILES = (256, 512, 1024)
 GRID_SCALES = (0.5, 1.0, 2.0)
 
 
-def variant_exists(group, tile):
+def variant_exists(group, tile, wave=False):
     """Compiled fused-kernel variants (groups of 4 at 1024 would need 196 KB
-    of LDS)."""
+    of LDS); the waveform-mode kernel (``wave``) is compiled for groups of 1
+    and 2 at 512 link samples and of 2 at 1024."""
+    if wave:
+        return (group, tile) in ((1, 512), (2, 512), (2, 1024))
     return group in GROUPS and tile in TILES and not (group == 4 and tile == 1024)
 
 
@@ -120,7 +123,7 @@ def tune(templates, orb_proj, orb_tdi, t0, dt, order, generation, channels, hp, 
     dev = params.device if params is not None else hp.device
     key = tune_key(torch.cuda.get_device_name(dev), order, generation, channels, dt, templates)
     if params is not None:
-        key += "|gb"
+        key += "|wave"
     cache = load_cache(cache_path) if use_cache else {}
     if key in cache:
         return cache[key]
@@ -143,7 +146,7 @@ def tune(templates, orb_proj, orb_tdi, t0, dt, order, generation, channels, hp, 
     trials = []
     for g in GROUPS:
         for tile in TILES:
-            if not variant_exists(g, tile):
+            if not variant_exists(g, tile, wave=params is not None):
                 continue
             try:
                 b = native.Batch(lay, orb_proj, orb_tdi, t0, dt, order, generation, channels,

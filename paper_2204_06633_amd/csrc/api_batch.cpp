@@ -46,8 +46,10 @@ struct Plan {
 
 bool valid_order(int order) { return order >= 1 && order <= 31 && (order % 2) == 1; }
 
-// Compiled fused-kernel variants: (templates per item, link samples per item).
-bool fused_variant_exists(int group, int tile) {
+// Compiled fused-kernel variants: (templates per item, link samples per item),
+// array or waveform mode.
+bool fused_variant_exists(int group, int tile, bool wave) {
+  if (wave) return (group == 1 && tile == 512) || (group == 2 && (tile == 512 || tile == 1024));
   if (tile != 256 && tile != 512 && tile != 1024) return false;
   if (group == 1 || group == 2) return true;
   return group == 4 && tile <= 512;
@@ -61,7 +63,7 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   if (group != 1 && group != 2 && group != 4)
     return set_error(LR_E_UNSUPPORTED, "group %d (1, 2 or 4 templates per work item)", group);
   if (tile == 0) tile = kYTileDefault;
-  if (!fused_variant_exists(group, tile))
+  if (!fused_variant_exists(group, tile, false))
     return set_error(LR_E_UNSUPPORTED, "tile %d with group %d (tiles of 256, 512 or 1024 link "
                                        "samples; 1024 not with groups of 4)", tile, group);
   P.Y = tile;
@@ -245,7 +247,8 @@ int launch_forward(const lr_batch* b, const double* hp, const double* hc, const 
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = lr::run_reset_counter(a.counter, s);
   if (e == hipSuccess)
-    e = lr::run_fused_forward(b->order, b->generation, b->group, b->tile, a, b->blocks, s);
+    e = lr::run_fused_forward(b->order, b->generation, b->group, b->tile, params != nullptr, a,
+                              b->blocks, s);
   if (e != hipSuccess) return set_error(LR_E_HIP, "lr_response launch: %s", hipGetErrorString(e));
   return LR_OK;
 }
@@ -330,7 +333,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
   const int64_t n_items = (int64_t)P.items.size() / 2;
-  const int64_t per_cu = lr::fused_blocks_per_cu(order, generation, group, P.Y);
+  const int64_t per_cu = lr::fused_blocks_per_cu(order, generation, group, P.Y, false);
 
   out->proj = *proj;
   out->tdi = *tdi;
@@ -373,6 +376,9 @@ int lr_response_gb(const lr_batch* b, const double* params, double* out, void* s
   if (int st = check_batch(b)) return st;
   if (b->n_items == 0) return LR_OK;
   if (!params || !out) return set_error(LR_E_ARG, "null pointer");
+  if (!fused_variant_exists(b->group, b->tile, true))
+    return set_error(LR_E_UNSUPPORTED, "waveform mode with group %d, tile %d (compiled: group 1 "
+                                       "or 2 at tile 512, group 2 at tile 1024)", b->group, b->tile);
   return launch_forward(b, nullptr, nullptr, params + 6, 8, params, out, stream);
 }
 

@@ -1,9 +1,9 @@
 // Batched response kernels for gfx950 (FP64): many templates (sources or
 // MCMC walkers) sharing one output time grid, one launch.
 //
-// fused_forward_kernel<N, GEN, M> is persistent: each workgroup takes work
-// items (a group of M templates, a tile of output samples) from an atomic
-// counter until the list is exhausted.  For one item it
+// fused_forward_kernel<N, GEN, M, BLOCK, WAVE> is persistent: each workgroup
+// takes work items (a group of M templates, a tile of output samples) from an
+// atomic counter until the list is exhausted.  For one item it
 //   1. computes, template by template, the link series of the tile plus the
 //      TDI halo directly into LDS (projection, Sec. IV.B) -- the link series
 //      never reaches HBM;
@@ -140,17 +140,27 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
 
 // Minimum resident waves per SIMD for the fused kernel's register budget
 // (build-time tuning knobs; 1 leaves the compiler unconstrained).  Measured
-// fastest: two for groups of 1 and 4, three for groups of 2 (whose 49 KB of
-// LDS let three work-groups share a CU).
+// fastest: two for groups of 1 and 4; three for groups of 2 reading h from
+// HBM (whose 49 KB of LDS let three work-groups share a CU; 203 against 206
+// ms on the 512-template batch although the third wave costs some spills);
+// two for groups of 2 in waveform mode (the synthesis needs more registers:
+// 114 against 125 ms on 256 one-year walkers).
 #ifndef LR_FUSED_MIN_WAVES
 #define LR_FUSED_MIN_WAVES 2
 #endif
 #ifndef LR_FUSED2_MIN_WAVES
 #define LR_FUSED2_MIN_WAVES 3
 #endif
+#ifndef LR_FUSED2W_MIN_WAVES
+#define LR_FUSED2W_MIN_WAVES 2
+#endif
 
-template <int N, int GEN, int M, int BLOCK>
-__global__ __launch_bounds__(BLOCK, M == 2 ? LR_FUSED2_MIN_WAVES : LR_FUSED_MIN_WAVES)
+// WAVE: h+ / hx synthesised from each template's parameter row (Sec. III)
+// instead of read from the caller's arrays.  A compile-time choice: with the
+// waveform code in the same kernel the array path's registers spill.
+template <int N, int GEN, int M, int BLOCK, bool WAVE>
+__global__ __launch_bounds__(BLOCK, M == 2 ? (WAVE ? LR_FUSED2W_MIN_WAVES : LR_FUSED2_MIN_WAVES)
+                                           : LR_FUSED_MIN_WAVES)
 void fused_forward_kernel(BatchFwdArgs a) {
   constexpr int YT = kPerLane * BLOCK;                // link samples per work item
   constexpr int CAPH = YT + N + kSlack;
@@ -163,8 +173,12 @@ void fused_forward_kernel(BatchFwdArgs a) {
   __shared__ double s_trig[2][2];
   __shared__ int s_item;
 
-  const int tid = threadIdx.x;
   for (;;) {
+    // an opaque lane index per item: whatever derives from it (LDS offsets,
+    // stencil starts) is recomputed here instead of being hoisted out of the
+    // persistent loop and kept in scratch
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (tid == 0) s_item = atomicAdd(a.counter, 1);
     __syncthreads();
     const int item = s_item;
@@ -204,9 +218,11 @@ void fused_forward_kernel(BatchFwdArgs a) {
       // h+ / hx: the caller's arrays, or the waveform synthesised into the
       // window from the template's parameter row (waveform time 0 at output
       // sample 0)
-      const HSource hs = a.params
-          ? HSource::waveform(a.params + 8 * T.index, -T.out_start, a.dt, T.n_h)
-          : HSource::arrays(a.hp + T.h_off, a.hc + T.h_off, T.n_h);
+      HSource hs;
+      if constexpr (WAVE)
+        hs = HSource::waveform(a.params + 8 * T.index, -T.out_start, a.dt, T.n_h);
+      else
+        hs = HSource::arrays(a.hp + T.h_off, a.hc + T.h_off, T.n_h);
       project_pair<N, BLOCK>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, hs,
                              T.out_start + i_base, sk, ra, hwin, red, ya, yb);
       __syncthreads();                                // the window is read; rows may be written
@@ -245,34 +261,43 @@ void fused_forward_kernel(BatchFwdArgs a) {
   }
 }
 
-template <int N, int GEN, int M, int BLOCK>
+template <int N, int GEN, int M, int BLOCK, bool WAVE>
 hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((fused_forward_kernel<N, GEN, M, BLOCK>), dim3(blocks), dim3(BLOCK), 0, s,
-                     a);
+  hipLaunchKernelGGL((fused_forward_kernel<N, GEN, M, BLOCK, WAVE>), dim3(blocks), dim3(BLOCK),
+                     0, s, a);
   return hipGetLastError();
 }
 
 // Resident workgroups per CU of the fused kernel (sizes the persistent grid).
-template <int N, int GEN, int M, int BLOCK>
+template <int N, int GEN, int M, int BLOCK, bool WAVE>
 int fused_occupancy() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_forward_kernel<N, GEN, M, BLOCK>,
-                                                   BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, fused_forward_kernel<N, GEN, M, BLOCK, WAVE>, BLOCK, 0) != hipSuccess)
     nb = 1;
   return nb > 0 ? nb : 1;
 }
 
-#define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M, BLOCK)                                 \
-  template hipError_t launch_fused_forward<NT, GEN, M, BLOCK>(const BatchFwdArgs&, int,   \
-                                                              hipStream_t);               \
-  template int fused_occupancy<NT, GEN, M, BLOCK>();
+#define LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, M, BLOCK, WAVE)                              \
+  template hipError_t launch_fused_forward<NT, GEN, M, BLOCK, WAVE>(const BatchFwdArgs&, int, \
+                                                                    hipStream_t);             \
+  template int fused_occupancy<NT, GEN, M, BLOCK, WAVE>();
 
 // Work items of 256, 512 or 1024 link samples (workgroups of 128, 256 or 512
 // lanes); groups of 4 at 1024 would need 196 KB of LDS and are left out.
-#define LR_INSTANTIATE_BATCH_FWD(NT, GEN)                                             \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 128) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 256) \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 512) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 128) \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 256) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 512) \
-  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 128) LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 256)
+// Waveform mode: groups of 1 and 2 at 512 link samples and of 2 at 1024 (the
+// fastest array-mode shapes), which keeps the build time in bounds.
+#define LR_INSTANTIATE_BATCH_FWD(NT, GEN)                                                   \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 128, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 256, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 512, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 128, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 256, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 512, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 128, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 4, 256, false)                                        \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 1, 256, true)                                         \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 256, true)                                         \
+  LR_INSTANTIATE_BATCH_FWD_M(NT, GEN, 2, 512, true)
 
 }  // namespace lr

@@ -70,9 +70,9 @@ struct BatchAdjArgs {
 };
 
 // Launchers (instantiated per tap count in batch_*.hip).
-template <int N, int GEN, int M, int BLOCK>
+template <int N, int GEN, int M, int BLOCK, bool WAVE>
 hipError_t launch_fused_forward(const BatchFwdArgs& a, int blocks, hipStream_t s);
-template <int N, int GEN, int M, int BLOCK>
+template <int N, int GEN, int M, int BLOCK, bool WAVE>
 int fused_occupancy();
 template <int N, int GEN>
 hipError_t launch_batch_tdi_adjoint(const BatchAdjArgs& a, int64_t n_items, hipStream_t s);
@@ -80,10 +80,11 @@ template <int N>
 hipError_t launch_batch_project_adjoint(const BatchAdjArgs& a, int64_t n_items,
                                         int64_t n_sky_items, hipStream_t s);
 
-// tile: link samples per work item (256, 512 or 1024; not 1024 with group 4)
-hipError_t run_fused_forward(int order, int gen, int group, int tile, const BatchFwdArgs& a,
-                             int blocks, hipStream_t s);
-int fused_blocks_per_cu(int order, int gen, int group, int tile);
+// tile: link samples per work item (256, 512 or 1024; not 1024 with group
+// 4); wave: waveform mode (h from a.params; groups 1, 2 at 512 and 2 at 1024)
+hipError_t run_fused_forward(int order, int gen, int group, int tile, bool wave,
+                             const BatchFwdArgs& a, int blocks, hipStream_t s);
+int fused_blocks_per_cu(int order, int gen, int group, int tile, bool wave);
 hipError_t run_batch_tdi_adjoint(int order, int gen, const BatchAdjArgs& a, int64_t n_items,
                                  hipStream_t s);
 hipError_t run_batch_project_adjoint(int order, const BatchAdjArgs& a, int64_t n_items,

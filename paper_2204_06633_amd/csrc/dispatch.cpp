@@ -44,26 +44,29 @@ hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s) {
   }
 }
 
-// (group, workgroup lanes) -> fused kernel instance; tile = 2 x lanes link
-// samples per work item.
+// (waveform mode, group, workgroup lanes) -> fused kernel instance; tile =
+// 2 x lanes link samples per work item.
 #define LR_FUSED_CASES(NT, GEN, CALL, FAIL)                                       \
-  switch (group * 10000 + tile / 2) {                                             \
-    case 10128: return CALL(NT, GEN, 1, 128);                                      \
-    case 10256: return CALL(NT, GEN, 1, 256);                                      \
-    case 10512: return CALL(NT, GEN, 1, 512);                                      \
-    case 20128: return CALL(NT, GEN, 2, 128);                                      \
-    case 20256: return CALL(NT, GEN, 2, 256);                                      \
-    case 20512: return CALL(NT, GEN, 2, 512);                                      \
-    case 40128: return CALL(NT, GEN, 4, 128);                                      \
-    case 40256: return CALL(NT, GEN, 4, 256);                                      \
+  switch ((wave ? 100000 : 0) + group * 10000 + tile / 2) {                      \
+    case 10128: return CALL(NT, GEN, 1, 128, false);                              \
+    case 10256: return CALL(NT, GEN, 1, 256, false);                              \
+    case 10512: return CALL(NT, GEN, 1, 512, false);                              \
+    case 20128: return CALL(NT, GEN, 2, 128, false);                              \
+    case 20256: return CALL(NT, GEN, 2, 256, false);                              \
+    case 20512: return CALL(NT, GEN, 2, 512, false);                              \
+    case 40128: return CALL(NT, GEN, 4, 128, false);                              \
+    case 40256: return CALL(NT, GEN, 4, 256, false);                              \
+    case 110256: return CALL(NT, GEN, 1, 256, true);                              \
+    case 120256: return CALL(NT, GEN, 2, 256, true);                              \
+    case 120512: return CALL(NT, GEN, 2, 512, true);                              \
     default: return FAIL;                                                         \
   }
 
-#define LR_LAUNCH_FUSED(NT, GEN, M, B) launch_fused_forward<NT, GEN, M, B>(a, blocks, s)
-#define LR_OCC_FUSED(NT, GEN, M, B) fused_occupancy<NT, GEN, M, B>()
+#define LR_LAUNCH_FUSED(NT, GEN, M, B, W) launch_fused_forward<NT, GEN, M, B, W>(a, blocks, s)
+#define LR_OCC_FUSED(NT, GEN, M, B, W) fused_occupancy<NT, GEN, M, B, W>()
 
-hipError_t run_fused_forward(int order, int gen, int group, int tile, const BatchFwdArgs& a,
-                             int blocks, hipStream_t s) {
+hipError_t run_fused_forward(int order, int gen, int group, int tile, bool wave,
+                             const BatchFwdArgs& a, int blocks, hipStream_t s) {
   switch (order) {
 #define X(ORD, NT)                                                                        \
   case ORD:                                                                               \
@@ -78,7 +81,7 @@ hipError_t run_fused_forward(int order, int gen, int group, int tile, const Batc
   }
 }
 
-int fused_blocks_per_cu(int order, int gen, int group, int tile) {
+int fused_blocks_per_cu(int order, int gen, int group, int tile, bool wave) {
   switch (order) {
 #define X(ORD, NT)                                                                        \
   case ORD:                                                                               \

@@ -207,7 +207,8 @@ __device__ __forceinline__ void project_pair(const OrbitView& orb, double t_off,
                                              double (&yb)[6]) {
   constexpr int H = N / 2;
   constexpr int CAP = kPerLane * BLOCK + N + kSlack;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));          // not hoisted out of a caller's loop
   ProjSample A, B;
   proj_sample(orb, t_off + (double)(ti0 + ra) * dt, inv_dt, sk, A);
   __builtin_amdgcn_sched_barrier(0);     // one sample's geometry live at a time

@@ -26,10 +26,10 @@ hipError_t run_reset_counter(int*, hipStream_t) { ++g_launches; return hipSucces
 hipError_t run_project_adjoint(int, const ProjAdjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_project_links(int, const ProjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_tdi(int, int, const TdiArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
-hipError_t run_fused_forward(int, int, int, int, const BatchFwdArgs&, int, hipStream_t) {
+hipError_t run_fused_forward(int, int, int, int, bool, const BatchFwdArgs&, int, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
-int fused_blocks_per_cu(int, int, int, int) { return 3; }
+int fused_blocks_per_cu(int, int, int, int, bool) { return 3; }
 hipError_t run_batch_tdi_adjoint(int, int, const BatchAdjArgs&, int64_t, hipStream_t) {
   ++g_launches; return hipSuccess;
 }

@@ -27,3 +27,6 @@ def test_tile_variants():
     ok = {(g, t) for g in autotune.GROUPS for t in autotune.TILES if autotune.variant_exists(g, t)}
     assert len(ok) == 8 and (4, 1024) not in ok and (4, 512) in ok and (1, 1024) in ok
     assert not autotune.variant_exists(3, 512) and not autotune.variant_exists(2, 768)
+    wave = {(g, t) for g in autotune.GROUPS for t in autotune.TILES
+            if autotune.variant_exists(g, t, wave=True)}
+    assert wave == {(1, 512), (2, 512), (2, 1024)} and wave <= ok
