@@ -81,41 +81,48 @@ __global__ __launch_bounds__(64) void gb_finalize_kernel(GbArgs a, int64_t block
   if (threadIdx.x == 0) finalize_gradient(a.params + 8 * tpl, tot, a.g_params + 8 * tpl);
 }
 
-// Batched response adjoint in waveform mode: per template (one block), the
-// seven sums over its projection tiles and the sky partials over its sky
-// tiles, each in tile order, then the parameter gradient.  span rows:
-// (first item, items, template index).
+// Batched response adjoint in waveform mode: per template (one block of 64
+// lanes), the seven sums over its projection tiles and the two sky partials
+// over its sky tiles -- lane L adds the tiles i = L, L + 64, ... in order,
+// then a fixed-order tree over the lanes (deterministic) -- then the
+// parameter gradient.  span rows: (first item, items, template index).
 __global__ __launch_bounds__(64) void gb_batch_finalize_kernel(const double* gb_part,
                                                                const int64_t* span,
                                                                const double* sky_part,
                                                                const int64_t* sky_span,
                                                                const double* params,
                                                                double* g_params) {
-  __shared__ double tot[kGbSums + 2];
   const int64_t r = blockIdx.x;
-  const int tid = threadIdx.x;
-  if (tid < kGbSums) {
-    const int64_t first = span[3 * r], cnt = span[3 * r + 1];
-    double v = 0.0;
-    for (int64_t i = 0; i < cnt; ++i) v += gb_part[(first + i) * kGbSums + tid];
-    tot[tid] = v;
-  } else if (tid < kGbSums + 2) {
-    const int64_t first = sky_span[3 * r], cnt = sky_span[3 * r + 1];
-    double v = 0.0;
-    for (int64_t i = 0; i < cnt; ++i) v += sky_part[2 * (first + i) + (tid - kGbSums)];
-    tot[tid] = v;
+  const int lane = threadIdx.x;
+  const int64_t first = span[3 * r], cnt = span[3 * r + 1];
+  const int64_t sfirst = sky_span[3 * r], scnt = sky_span[3 * r + 1];
+  double v[kGbSums + 2];
+#pragma unroll
+  for (int c = 0; c < kGbSums + 2; ++c) v[c] = 0.0;
+  for (int64_t i = lane; i < cnt; i += 64) {
+    const double* row = gb_part + (first + i) * kGbSums;
+#pragma unroll
+    for (int c = 0; c < kGbSums; ++c) v[c] += row[c];
   }
-  __syncthreads();
-  if (tid == 0) {
+  for (int64_t i = lane; i < scnt; i += 64) {
+    v[kGbSums] += sky_part[2 * (sfirst + i)];
+    v[kGbSums + 1] += sky_part[2 * (sfirst + i) + 1];
+  }
+#pragma unroll
+  for (int c = 0; c < kGbSums + 2; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o, 64);
+  }
+  if (lane == 0) {
     const int64_t k = span[3 * r + 2];
     double* g = g_params + 8 * k;
-    if (span[3 * r + 1] == 0) {                       // empty template
+    if (cnt == 0) {                                   // empty template
       for (int c = 0; c < 8; ++c) g[c] = 0.0;
       return;
     }
-    finalize_gradient(params + 8 * k, tot, g);
-    g[6] = tot[kGbSums];
-    g[7] = tot[kGbSums + 1];
+    finalize_gradient(params + 8 * k, v, g);
+    g[6] = v[kGbSums];
+    g[7] = v[kGbSums + 1];
   }
 }
 
