@@ -65,7 +65,7 @@ def kernel_source_hash(names):
 
 
 FUSED_SOURCES = ("device_common.hpp", "forward_kernels.hpp", "batch_kernels.hpp",
-                 "batch_types.hpp")
+                 "batch_types.hpp", "gb_device.hpp")
 
 
 def recorded_traffic(name, sources):

@@ -4,7 +4,7 @@
     python -m paper_2204_06633_amd.profiling --what adjoint --reps 5
     python -m paper_2204_06633_amd.profiling --what copy --copy-mib 1024
     python -m paper_2204_06633_amd.profiling --what batch --templates 64
-    python -m paper_2204_06633_amd.profiling --what batch-adjoint --templates 32
+    python -m paper_2204_06633_amd.profiling --what batch-adjoint --templates 32 --waveform
     python -m paper_2204_06633_amd.profiling --what fd --templates 4
     python -m paper_2204_06633_amd.profiling --what sampler --reps 2
 
@@ -15,7 +15,9 @@ for scaling the HBM byte counters); ``batch`` runs the fused batched forward
 on the first ``--templates`` templates of the 512-template uneven batch
 (``--group``, ``--tile``, ``--grid-scale``: the autotuner's knobs);
 ``batch-adjoint`` runs forward, likelihood and adjoint of that many 1-yr,
-dt = 15 s walkers with hybrid orbits; ``fd`` runs the
+dt = 15 s walkers with hybrid orbits; ``--waveform`` runs either batch in
+waveform mode (h+ / hx synthesised in the kernels from each template's
+parameter row, the adjoint down to the 8 parameters); ``fd`` runs the
 frequency-domain likelihood with its gradient on ``--templates`` one-year
 A/E/T series at dt = 10 s (2^22-point transforms); ``sampler`` runs
 tempered stretch-move steps of 4 x 50 walkers on one year at dt = 15 s.
@@ -36,6 +38,8 @@ def main(argv=None):
     ap.add_argument("--group", type=int, default=2)
     ap.add_argument("--tile", type=int, default=0, help="link samples per fused work item")
     ap.add_argument("--grid-scale", type=float, default=1.0)
+    ap.add_argument("--waveform", action="store_true",
+                    help="waveform mode (lr_response_gb / lr_response_adjoint_gb)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args(argv)
@@ -106,18 +110,28 @@ def run_batch(args, dev):
     orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     orb_t = orb_p if bc.orbits_tdi is bc.orbits_proj else \
         native.Orbits.from_samples(bc.orbits_tdi, device=dev)
-    hp, hc = workloads.device_polarizations(bc, dev)
-    sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
+    if args.waveform:
+        params = torch.tensor(bc.params, dtype=torch.float64, device=dev).contiguous()
+        g_par = torch.empty_like(params)
+    else:
+        hp, hc = workloads.device_polarizations(bc, dev)
+        sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
     b = native.Batch(bc.layout.templates(), orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation,
                      bc.channels, group=args.group, tile=args.tile, adjoint=adj, device=dev)
     b.set_grid(max(1, int(round(b.blocks * args.grid_scale))))
     out = torch.empty(b.out_extent, dtype=torch.float64, device=dev)
     data = torch.zeros_like(out) if adj else None
     for r in range(args.reps):
-        b.response(hp, hc, sky, out=out)
+        if args.waveform:
+            b.response_gb(params, out=out)
+        else:
+            b.response(hp, hc, sky, out=out)
         if adj:
             _, g_out = b.loglike(out, data, 1e-21)
-            b.adjoint(hp, hc, sky, g_out)
+            if args.waveform:
+                b.adjoint_gb(params, g_out, g_params=g_par)
+            else:
+                b.adjoint(hp, hc, sky, g_out)
         torch.cuda.synchronize()
         print("%s step %d done (%d templates, %d samples)" % (args.what, r, len(bc.grids),
                                                             bc.n_samples), flush=True)
