@@ -25,7 +25,7 @@ constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
 enum Region {
   R_TPL, R_ITEMS, R_COUNTER, R_ADJ_TPL, R_TDI_ITEMS, R_PROJ_ITEMS, R_SKY_PART, R_SKY_SPAN,
   R_LIKE_ITEMS, R_LIKE_PART, R_LIKE_SPAN, R_PAIRS, R_TDI_CITEMS, R_PADJ_CITEMS, R_GB_PART,
-  R_PADJ_SPAN, R_GY, R_COUNT
+  R_PADJ_SPAN, R_GY, R_TRIG, R_COUNT
 };
 
 static_assert(R_COUNT <= (int)(sizeof(((lr_batch*)nullptr)->off) / sizeof(size_t)),
@@ -187,6 +187,7 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   P.bytes[R_GB_PART] = adjoint ? P.padj_citems.size() / 2 * 7 * sizeof(double) : 0;
   P.bytes[R_PADJ_SPAN] = adjoint ? P.padj_span.size() * sizeof(int64_t) : 0;
   P.bytes[R_GY] = adjoint ? (size_t)P.gy_doubles * sizeof(double) : 0;
+  P.bytes[R_TRIG] = (size_t)n * 4 * sizeof(double);
   size_t o = 0;
   for (int r = 0; r < R_COUNT; ++r) {
     P.off[r] = o;
@@ -241,11 +242,13 @@ int launch_forward(const lr_batch* b, const double* hp, const double* hc, const 
   a.hc = hc;
   a.sky = sky;
   a.sky_stride = sky_stride;
+  a.trig = at<double>(b, R_TRIG);
   a.params = params;
   a.channels = b->channels;
   a.out = out;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = lr::run_reset_counter(a.counter, s);
+  hipError_t e = lr::run_forward_prep(a.counter, sky, sky_stride, b->n_templates,
+                                      at<double>(b, R_TRIG), s);
   if (e == hipSuccess)
     e = lr::run_fused_forward(b->order, b->generation, b->group, b->tile, params != nullptr, a,
                               b->blocks, s);

@@ -122,13 +122,12 @@ __device__ __forceinline__ void fused_tdi(const BatchFwdArgs& a, const double* y
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     double dir[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-#pragma unroll
-    for (int t = 0; t < ND; ++t) {
-      const Direct dr = TdiTab<GEN>::v.direct[t];
+    static_for<ND>([&](auto t) {
+      constexpr Direct dr = TdiTab<GEN>::v.direct[decltype(t)::value];
       const double* w = ylds + (k * 6 + dr.link) * YT;
       dir[0][dr.chan] += (double)dr.sign * w[par<YT>(c0)];
       dir[1][dr.chan] += (double)dr.sign * w[par<YT>(c0 + 1)];
-    }
+    });
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -170,7 +169,6 @@ void fused_forward_kernel(BatchFwdArgs a) {
   static_assert(CAPH * sizeof(double2) <= 6 * YT * sizeof(double), "h window fits a row block");
   __shared__ __align__(16) double ylds[M * 6 * YT];
   __shared__ int red[2][BLOCK / 64];
-  __shared__ double s_trig[2][2];
   __shared__ int s_item;
 
   for (;;) {
@@ -181,9 +179,12 @@ void fused_forward_kernel(BatchFwdArgs a) {
     asm volatile("" : "+v"(tid));
     if (tid == 0) s_item = atomicAdd(a.counter, 1);
     __syncthreads();
-    const int item = s_item;
-    if (item >= a.n_items) break;                     // uniform: every lane read s_item
-    const int grp = a.items[2 * item], tile = a.items[2 * item + 1];
+    // uniform values in scalar registers: the item, its group and tile, and
+    // (below) the templates' records come through scalar loads
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= a.n_items) break;
+    const int grp = __builtin_amdgcn_readfirstlane(a.items[2 * item]);
+    const int tile = __builtin_amdgcn_readfirstlane(a.items[2 * item + 1]);
     const int64_t o0 = (int64_t)tile * a.T_out;       // output index of the tile's first output
     const int64_t i_base = o0 - a.F;                  // output index of tile element 0
 
@@ -204,15 +205,10 @@ void fused_forward_kernel(BatchFwdArgs a) {
       const int last = r_end - 1;
       const bool act_a = 2 * tid <= last, act_b = 2 * tid + 1 <= last;
       const int ra = act_a ? 2 * tid : (last & ~1);
-      __syncthreads();                                // s_trig free
-      if (tid < 2) {
-        double sn, cs;
-        sincos(a.sky[a.sky_stride * T.index + tid], &sn, &cs);
-        s_trig[tid][0] = sn;
-        s_trig[tid][1] = cs;
-      }
-      __syncthreads();
-      const Sky sk = sky_from_trig(s_trig[0][0], s_trig[0][1], s_trig[1][0], s_trig[1][1]);
+      // sin, cos of the sky angles, tabulated per template before the launch
+      // (no trigonometry, and none of its constants, in this loop)
+      const double* tr = a.trig + 4 * T.index;
+      const Sky sk = sky_from_trig(tr[0], tr[1], tr[2], tr[3]);
       double ya[6], yb[6];
       double2* hwin = reinterpret_cast<double2*>(ylds + k * 6 * YT);
       // h+ / hx: the caller's arrays, or the waveform synthesised into the
@@ -245,12 +241,16 @@ void fused_forward_kernel(BatchFwdArgs a) {
     double acc[M][2][3];
     fused_tdi<N, GEN, M, YT>(a, ylds, La, Lb, a.F + ob, live, acc);
 
-    // 3. store
+    // 3. store (the template records read again rather than kept live
+    // through the TDI: an opaque copy of the group index stops the compiler
+    // from reusing the first loads)
+    int grp_s = grp;
+    asm volatile("" : "+s"(grp_s));
     if (out_a) {
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         if (!live[k]) continue;
-        const BatchTemplate T = a.tpl[grp * M + k];
+        const BatchTemplate T = a.tpl[grp_s * M + k];
         const int64_t i = o0 + oa;
         if (i < T.n_out) store_channels(acc[k][0], a.channels, a.out + T.out_off, T.n_out, i);
         if (i + 1 < T.n_out)

@@ -31,6 +31,7 @@ struct BatchFwdArgs {
   const double* hc;
   const double* sky;         // lam, beta of template k at sky[sky_stride * k + 0, 1]
   int sky_stride;            // 2 (sky array) or 8 (rows of params)
+  const double* trig;        // [n_templates][4]: sin, cos of lam, then of beta (run_forward_prep)
   const double* params;      // [n_templates][8] or null: synthesise h+ / hx from these
   int channels;
   double* out;

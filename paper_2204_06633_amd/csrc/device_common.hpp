@@ -510,15 +510,28 @@ __device__ __forceinline__ double group_delay(const DelayGroup& g, const double 
 }
 
 // Wave (64 lanes) and workgroup min / max of an int.
+// ds_swizzle in bit mode: lane i reads lane i ^ X within its 32-lane half
+// (pattern xor_mask << 10 | and_mask 0x1f).  The pattern is an immediate, so
+// no lane-address registers have to be kept.
+#define LR_SWZ_XOR(v, X) __builtin_amdgcn_ds_swizzle((v), ((X) << 10) | 0x1f)
+
+// xor butterflies within each half-wave, then the two halves; the result is
+// wave-uniform.
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  v = min(v, LR_SWZ_XOR(v, 16));
+  v = min(v, LR_SWZ_XOR(v, 8));
+  v = min(v, LR_SWZ_XOR(v, 4));
+  v = min(v, LR_SWZ_XOR(v, 2));
+  v = min(v, LR_SWZ_XOR(v, 1));
+  return min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  v = max(v, LR_SWZ_XOR(v, 16));
+  v = max(v, LR_SWZ_XOR(v, 8));
+  v = max(v, LR_SWZ_XOR(v, 4));
+  v = max(v, LR_SWZ_XOR(v, 2));
+  v = max(v, LR_SWZ_XOR(v, 1));
+  return max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
 }
 
 }  // namespace lr

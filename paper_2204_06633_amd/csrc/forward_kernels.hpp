@@ -19,6 +19,7 @@
 // that position.  Stores are link- / channel-major and coalesced.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "device_common.hpp"
@@ -388,6 +389,17 @@ template <int GEN>
 struct TdiTab {
   static constexpr TdiTable<GEN> v = make_tdi_table<GEN>();
 };
+
+// f(std::integral_constant<int, I>) for I = 0 .. COUNT-1: lets a loop body
+// read the TDI table as constant expressions (no table loads, no run-time
+// signs or channel indices).
+template <int COUNT, int I = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < COUNT) {
+    f(std::integral_constant<int, I>{});
+    static_for<COUNT, I + 1>(f);
+  }
+}
 
 // Delay groups as a run-time table in constant memory: the kernels loop over
 // groups without unrolling, so only one group's state is live at a time.

@@ -99,7 +99,10 @@ hipError_t run_batch_loglike(const double* h, const double* d, const int64_t* it
                              hipStream_t s);
 hipError_t run_batch_sky_finalize(const double* part, const int64_t* span, int64_t n_templates,
                                   double* g_sky, hipStream_t s);
-hipError_t run_reset_counter(int* c, hipStream_t s);
+// Before a fused forward: zero the work counter and tabulate sin, cos of each
+// template's sky angles (trig[4k..4k+3] from sky[stride * k + 0, 1]).
+hipError_t run_forward_prep(int* counter, const double* sky, int stride, int64_t n,
+                            double* trig, hipStream_t s);
 hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s);
 
 // Runtime dispatch on the interpolation order (odd 1..31).

@@ -128,10 +128,6 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(const double* part,
   }
 }
 
-__global__ void reset_counter_kernel(int* c) {
-  if (threadIdx.x == 0) *c = 0;
-}
-
 hipError_t run_batch_loglike(const double* h, const double* d, const int64_t* items,
                              int64_t n_items, double inv_var, double* g, double* part,
                              const int64_t* span, int64_t n_templates, double* out,
@@ -151,8 +147,26 @@ hipError_t run_batch_sky_finalize(const double* part, const int64_t* span, int64
   return hipGetLastError();
 }
 
-hipError_t run_reset_counter(int* c, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, c);
+__global__ void forward_prep_kernel(int* counter, const double* sky, int stride, int64_t n,
+                                    double* trig) {
+  const int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (k == 0) *counter = 0;
+  if (k < n) {
+    double sn, cs;
+    sincos(sky[stride * k], &sn, &cs);
+    trig[4 * k] = sn;
+    trig[4 * k + 1] = cs;
+    sincos(sky[stride * k + 1], &sn, &cs);
+    trig[4 * k + 2] = sn;
+    trig[4 * k + 3] = cs;
+  }
+}
+
+hipError_t run_forward_prep(int* counter, const double* sky, int stride, int64_t n,
+                            double* trig, hipStream_t s) {
+  const int64_t blocks = n > 0 ? (n + 63) / 64 : 1;
+  hipLaunchKernelGGL(forward_prep_kernel, dim3((unsigned)blocks), dim3(64), 0, s, counter, sky,
+                     stride, n, trig);
   return hipGetLastError();
 }
 

@@ -22,7 +22,9 @@ hipError_t run_batch_loglike(const double*, const double*, const int64_t*, int64
 hipError_t run_batch_sky_finalize(const double*, const int64_t*, int64_t, double*, hipStream_t) {
   ++g_launches; return hipSuccess;
 }
-hipError_t run_reset_counter(int*, hipStream_t) { ++g_launches; return hipSuccess; }
+hipError_t run_forward_prep(int*, const double*, int, int64_t, double*, hipStream_t) {
+  ++g_launches; return hipSuccess;
+}
 hipError_t run_project_adjoint(int, const ProjAdjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_project_links(int, const ProjArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
 hipError_t run_tdi(int, int, const TdiArgs&, hipStream_t) { ++g_launches; return hipSuccess; }
