@@ -62,6 +62,12 @@ const char *lr_status_str(int status);
 const char *lr_last_error(void);
 /* ABI version of this header (bumped on incompatible changes). */
 int lr_abi_version(void);
+/* The build-time tuning switches the library was compiled with, as
+ * "NAME=value;NAME=value;..." (register budgets, load pipelining, the TDI
+ * adjoint's fold): the product build has the kernel headers' defaults, a
+ * variant build for measurements reports its own.  Static string; never
+ * NULL. */
+const char *lr_build_config(void);
 
 /* ------------------------------------------------------------------------
  * Orbits.  The paper interpolates the orbit data once per run and keeps it

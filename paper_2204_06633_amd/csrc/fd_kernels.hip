@@ -100,11 +100,9 @@ constexpr int stage_bits(int q, int s) {
 }
 
 // LDS layout: line c at c * line_stride, element x at x + x / 16 (one pad
-// per 16 elements, and an odd line stride in 16-byte units), so that the
-// strided stage writes and the column-wise accesses hit distinct banks.
-#ifndef LR_FD_LS_EXTRA
-#define LR_FD_LS_EXTRA 1
-#endif
+// per 16 elements, and an odd line stride in 16-byte units, LR_FD_LS_EXTRA
+// in fd_types.hpp), so that the strided stage writes and the column-wise
+// accesses hit distinct banks.
 constexpr int line_stride(int q) { return (1 << q) + (1 << q) / 16 + LR_FD_LS_EXTRA; }
 __device__ __forceinline__ int lpad(int x) { return x + (x >> 4); }
 

@@ -4,6 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Extra doubles of a transform line's LDS stride beyond its padded length
+// (build-time tuning switch; other small odd extras measured the same).
+#ifndef LR_FD_LS_EXTRA
+#define LR_FD_LS_EXTRA 1
+#endif
+
 namespace lr {
 
 // Transform geometry: N = 2^logN points per signal in `passes` passes of

@@ -60,6 +60,8 @@ def lib():
     L.lr_status_str.argtypes = [i32]
     L.lr_last_error.restype = ctypes.c_char_p
     L.lr_abi_version.restype = i32
+    L.lr_build_config.restype = ctypes.c_char_p
+    L.lr_build_config.argtypes = []
     L.lr_orbits_bytes.restype = ctypes.c_size_t
     L.lr_orbits_bytes.argtypes = [i64]
     L.lr_orbits_init.argtypes = [d, d, i64, vp, vp, vp, ctypes.c_size_t, po, vp]
@@ -85,6 +87,13 @@ def lib():
         getattr(L, name).restype = i32
     _lib = L
     return L
+
+
+def build_config():
+    """The tuning switches the loaded library was compiled with (a dict of
+    name -> int, from lr_build_config)."""
+    text = lib().lr_build_config().decode()
+    return {k: int(v) for k, v in (item.split("=") for item in text.split(";") if item)}
 
 
 def _check(status, where):

@@ -286,3 +286,41 @@ def test_gb_rejections_before_launch():
                                          None) == 4
     assert L.lr_gb_polarizations_adjoint(p, 2, 0, 3000, 10.0, hp, hc, 3000, p, w, nb,
                                          None) == 1                              # g aliases params
+
+
+# The product defaults of the build-time tuning switches (the values the
+# kernel headers define; measured choices, see the headers' comments).
+PRODUCT_SWITCHES = {"LR_PROJ_PIPE": 2, "LR_PROJ_MIN_WAVES": 1, "LR_TDI_MIN_WAVES": 4,
+                    "LR_FUSED_MIN_WAVES": 2, "LR_FUSED2_MIN_WAVES": 3, "LR_FUSED2W_MIN_WAVES": 2,
+                    "LR_TDI_CARRY_MIN_WAVES": 2, "LR_PADJ_CARRY_MIN_WAVES": 2,
+                    "LR_TDI_ADJ_FOLD": 1, "LR_PADJ_MIN_WAVES": 1, "LR_SKY_MIN_WAVES": 1,
+                    "LR_FD_LS_EXTRA": 1}
+
+
+def test_product_library_has_the_default_switches():
+    """The in-tree library (the one the tests, smoke() and bench.py load
+    unless LISARESP_LIB points elsewhere) was built without tuning -D flags:
+    a variant build for measurements cannot pass for the product."""
+    import os
+
+    from paper_2204_06633_amd import native
+    from paper_2204_06633_amd.csrc import build
+    assert native.LIB_PATH == build.TARGET or os.environ.get("LISARESP_LIB")
+    if os.environ.get("LISARESP_LIB"):
+        pytest.skip("LISARESP_LIB selects a variant build")
+    assert native.build_config() == PRODUCT_SWITCHES
+
+
+def test_switch_defaults_in_the_headers():
+    """Every switch the library reports is defined once, under #ifndef, in
+    a kernel header, with the product value above."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2204_06633_amd", "csrc")
+    found = {}
+    for name in os.listdir(csrc):
+        if name.endswith((".hpp", ".hip", ".cpp")):
+            text = open(os.path.join(csrc, name)).read()
+            for m in re.finditer(r"#ifndef (LR_[A-Z0-9_]+)\n#define \1 (\d+)\n#endif", text):
+                assert m.group(1) not in found, m.group(1)
+                found[m.group(1)] = int(m.group(2))
+    assert found == PRODUCT_SWITCHES
