@@ -191,7 +191,8 @@ def bench_headline(steps, warmup, keep):
     kernel = "fused_forward_kernel<26,2,%d,%d>" % (group, batch.tile // 2)
     roof = _roofline(ops, ms_launch, kernel, traffic, nbytes)
     roof["note"] = ("mean HIP-event time of the graph replay on the launch stream (the "
-                    "counter reset kernel, ~2 us, and the fused kernel)")
+                    "preparation kernel (work counter, sky trigonometry; a few us) and the fused "
+                    "kernel)")
 
     # keep what the CPU baseline compares: the sampled templates' inputs and
     # outputs, on the host
@@ -216,16 +217,19 @@ def bench_headline(steps, warmup, keep):
 # Walkers: forward + likelihood + adjoint of 256 one-year walkers
 # ---------------------------------------------------------------------------
 
-def bench_walkers(steps, warmup, keep):
+def bench_walkers(steps, warmup, keep, tdi_orbit_kind="rigid"):
     """256 one-year walkers at dt = 15 s in waveform mode: each walker's h+ /
     hx synthesised inside the fused kernel from its 8 source parameters
     (lr_response_gb), the A/E/T likelihood, and the adjoint down to the 8
-    parameters (lr_response_adjoint_gb): no h or h-gradient arrays."""
+    parameters (lr_response_adjoint_gb): no h or h-gradient arrays.  TDI
+    delays from rigid equal-arm orbits (hybrid template) or, with
+    tdi_orbit_kind="keplerian", from the same flexing orbits as the
+    projection (the full generic response)."""
     import torch
 
     from paper_2204_06633_amd import autotune, costs, native, workloads
     dev = torch.device("cuda:0")
-    bc = workloads.walker_batch_case()
+    bc = workloads.walker_batch_case(tdi_orbit_kind=tdi_orbit_kind)
     log("walkers: %s, %d walkers, %d samples" % (bc.name, len(bc.grids), bc.n_samples))
     orb_p = native.Orbits.from_samples(bc.orbits_proj, device=dev)
     orb_t = native.Orbits.from_samples(bc.orbits_tdi, device=dev)
@@ -338,7 +342,7 @@ def bench_single_template(steps):
     ms_tadj = _timed(lambda: native.tdi_adjoint(orb, t0_y, g.dt, g.n_y, case.generation,
                                                 case.order, case.channels, g.front_tdi, g_out,
                                                 g_y=g_y), steps, 2)
-    res["roofline_tdi_adjoint"] = _roofline(ops_tdi, ms_tadj, "tdi_adjoint_kernel<26,2> "
+    res["roofline_tdi_adjoint"] = _roofline(ops_tdi, ms_tadj, "tdi_adjoint_carry_kernel<26,2> "
                                             "(with the zero fill of g_y)")
     res["roofline_tdi_adjoint"]["over_forward_tdi"] = ms_tadj / ms_tdi
 
@@ -551,9 +555,10 @@ def bench_widened(steps, st):
                       "value": evals * 6.0 * sc.grid.n_out / (ms * 1e-3), "unit": UNIT,
                       "acceptance_per_temperature":
                           (acc_tot.float() / (sampler_steps * sc.W)).tolist(),
-                      "step": "tempered stretch move over 4 x 50 walkers: lr_gb_polarizations "
-                              "-> lr_response -> lr_fd_loglike (statistics) per half step, "
-                              "then tempering swaps"}
+                      "step": "tempered stretch move over 4 x 50 walkers: per half step one "
+                              "captured graph of lr_response_gb (waveform synthesised in the "
+                              "fused kernel) -> lr_fd_loglike (statistics), then tempering "
+                              "swaps"}
     return res
 
 
@@ -701,6 +706,7 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2204_06633_amd import native
     c3_keep = {0: None, 137: None, 255: None, 301: None, 384: None, 450: None, 500: None,
                511: None}
     c5_keep = {0: None, 85: None, 170: None, 255: None}
@@ -720,10 +726,13 @@ def main():
                    "group": head["group"], "blocks": head["blocks"]},
         "roofline": head["roofline"],
         "headline": head,
+        "build_config": native.build_config(),
     }
     c5 = None
     if not args.headline_only:
         result["walkers"], c5 = bench_walkers(3, 1, c5_keep)
+        torch.cuda.empty_cache()
+        result["walkers_keplerian"], _ = bench_walkers(3, 1, {}, tdi_orbit_kind="keplerian")
         torch.cuda.empty_cache()
         single, st = bench_single_template(args.steps)
         result["single_template"] = single

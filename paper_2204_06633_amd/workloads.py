@@ -170,11 +170,12 @@ def uneven_batch_case(n_templates=512, seed=3):
                            25, 2, "AET", seed)
 
 
-def walker_batch_case(n_walkers=256, seed=5, spread=1e-6):
+def walker_batch_case(n_walkers=256, seed=5, spread=1e-6, tdi_orbit_kind="rigid"):
     """MCMC walkers around one Galactic binary: 1 yr at dt = 15 s each,
     Keplerian orbits for the projection and rigid equal-arm orbits for the
-    TDI-2 delays (hybrid template), A/E/T, order 25.  Walker parameters are
-    the source's scaled by (1 + spread * N(0,1)), angles shifted by
+    TDI-2 delays (hybrid template; ``tdi_orbit_kind="keplerian"`` gives the
+    full generic response), A/E/T, order 25.  Walker parameters are the
+    source's scaled by (1 + spread * N(0,1)), angles shifted by
     spread * N(0,1)."""
     rng = np.random.default_rng(seed)
     base = inputs.draw_gb_params(rng)
@@ -182,8 +183,9 @@ def walker_batch_case(n_walkers=256, seed=5, spread=1e-6):
     params[:, :3] *= 1.0 + spread * rng.standard_normal((n_walkers, 3))
     params[:, 3:] += spread * rng.standard_normal((n_walkers, 5))
     n = int(round(inputs.YEAR / 15.0))
-    return make_batch_case("walkers%d_hybrid_dt15" % n_walkers, [n] * n_walkers, 15.0, 25, 2,
-                           "AET", seed, params=params, tdi_orbit_kind="rigid")
+    name = "hybrid" if tdi_orbit_kind == "rigid" else tdi_orbit_kind
+    return make_batch_case("walkers%d_%s_dt15" % (n_walkers, name), [n] * n_walkers, 15.0, 25, 2,
+                           "AET", seed, params=params, tdi_orbit_kind=tdi_orbit_kind)
 
 
 def device_polarizations(bc: BatchCase, device, params=None):

@@ -316,3 +316,44 @@ def test_waveform_mode_forward_and_parameter_adjoint(torch_cuda):
         rhp, rhc = oracle.response_adjoint(op, ot, g, p[6], p[7], 25, 2, go, "AET")
         vjp = owf.polarizations_vjp(p, g.waveform_times(), rhp, rhc)
         assert np.all(np.abs(got[:6] - vjp[:6]) <= 1e-9 * np.abs(vjp[:6])), (k, got, vjp)
+
+
+def test_waveform_mode_every_compiled_shape_and_the_rest_refused(torch_cuda):
+    """Waveform mode is its own kernel variant, compiled for groups of 1 and
+    2 at 512 link samples and of 2 at 1024: each of those equals the array
+    mode fed with lr_gb_polarizations bit for bit; a batch prepared with
+    another shape gets LR_E_UNSUPPORTED from lr_response_gb, before any
+    launch."""
+    torch = torch_cuda
+    from paper_2204_06633_amd import autotune, native
+    n_out_list = [900, 1500, 333]
+    B = _build(torch, n_out_list, group=1, seed=31)
+    params = _t(torch, B["params"])
+    gp, gt = B["orbs"]
+    tpl = B["lay"].templates()
+    hp = torch.zeros(max(B["lay"].n_h_total, 1), dtype=torch.float64, device="cuda")
+    hc = torch.zeros_like(hp)
+    for k, g in enumerate(B["grids"]):
+        ho = B["lay"].h_offsets[k]
+        a, b = native.gb_polarizations(params[k:k + 1].contiguous(), -g.out_start, g.n_h, g.dt)
+        hp[ho:ho + g.n_h] = a[0]
+        hc[ho:ho + g.n_h] = b[0]
+    sky = params[:, 6:8].contiguous()
+    t0 = B["grids"][0].t_start
+    ref = None
+    for g in autotune.GROUPS:
+        for tile in autotune.TILES:
+            if not autotune.variant_exists(g, tile):
+                continue
+            b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g, tile=tile)
+            out = b.response(hp, hc, sky)
+            if ref is None:
+                ref = out.clone()
+            if autotune.variant_exists(g, tile, wave=True):
+                out_gb = b.response_gb(params)
+                torch.cuda.synchronize()
+                assert torch.equal(out_gb[:b.out_extent], ref[:b.out_extent]), (g, tile)
+            else:
+                with pytest.raises(native.LisaRespError) as e:
+                    b.response_gb(params)
+                assert e.value.status == native.LR_E_UNSUPPORTED, (g, tile)
