@@ -14,7 +14,7 @@
 extern "C" const char* lr_build_config(void) {
   return LR_ITEM(LR_PROJ_PIPE) LR_ITEM(LR_PROJ_MIN_WAVES) LR_ITEM(LR_TDI_MIN_WAVES)
       LR_ITEM(LR_FUSED_MIN_WAVES) LR_ITEM(LR_FUSED2_MIN_WAVES) LR_ITEM(LR_FUSED2W_MIN_WAVES)
-          LR_ITEM(LR_TDI_CARRY_MIN_WAVES) LR_ITEM(LR_PADJ_CARRY_MIN_WAVES)
+          LR_ITEM(LR_TDI_CARRY_MIN_WAVES) LR_ITEM(LR_PADJ_CARRY_MIN_WAVES) LR_ITEM(LR_TDI_CARRY_KEEP_NU)
               LR_ITEM(LR_TDI_ADJ_FOLD) LR_ITEM(LR_PADJ_MIN_WAVES) LR_ITEM(LR_SKY_MIN_WAVES)
                   LR_ITEM(LR_FD_LS_EXTRA);
 }

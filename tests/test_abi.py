@@ -293,6 +293,7 @@ def test_gb_rejections_before_launch():
 PRODUCT_SWITCHES = {"LR_PROJ_PIPE": 2, "LR_PROJ_MIN_WAVES": 1, "LR_TDI_MIN_WAVES": 4,
                     "LR_FUSED_MIN_WAVES": 2, "LR_FUSED2_MIN_WAVES": 3, "LR_FUSED2W_MIN_WAVES": 2,
                     "LR_TDI_CARRY_MIN_WAVES": 2, "LR_PADJ_CARRY_MIN_WAVES": 2,
+                    "LR_TDI_CARRY_KEEP_NU": 1,
                     "LR_TDI_ADJ_FOLD": 1, "LR_PADJ_MIN_WAVES": 1, "LR_SKY_MIN_WAVES": 1,
                     "LR_FD_LS_EXTRA": 1}
 
