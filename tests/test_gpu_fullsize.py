@@ -159,3 +159,74 @@ def test_walkers_256_against_oracle(torch_cuda):
     rest = [k for k in range(batch.n) if k not in sel]
     assert float(ghp[mask].abs().max()) == 0.0 and float(ghc[mask].abs().max()) == 0.0
     assert np.all(gsky_np[rest] == 0.0)
+
+
+def test_walkers_256_keplerian_waveform_mode_against_oracle(torch_cuda):
+    """The walker workload with the full generic response (Keplerian orbits
+    for the projection and the TDI delays) in waveform mode, all 256 walkers
+    in one launch at the tuned waveform-mode shape:
+      * forward (h+ / hx synthesised in the fused kernel): sampled outputs of
+        two walkers against the oracle fed with the oracle's own waveform;
+      * gradient to the 8 parameters (lr_response_adjoint_gb) of a channel
+        gradient that is zero except at those outputs: the six waveform
+        parameters against the oracle's transposed response at exactly those
+        outputs followed by the waveform's vector-Jacobian product, the sky
+        angles against central differences of the oracle's <g, response>;
+        every other walker's gradient exactly zero."""
+    torch = torch_cuda
+    from oracle import waveform as owf
+    from paper_2204_06633_amd import autotune, native
+    dev = torch.device("cuda:0")
+    bc = workloads.walker_batch_case(tdi_orbit_kind="keplerian")
+    assert bc.orbits_tdi is bc.orbits_proj
+    orb = native.Orbits.from_samples(bc.orbits_proj, device=dev)
+    params = torch.tensor(bc.params, dtype=torch.float64, device=dev).contiguous()
+    tpl = bc.layout.templates()
+    tuned = autotune.tune(tpl, orb, orb, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                          None, None, None, params=params, use_cache=False, reps=1,
+                          max_templates=16)
+    assert autotune.variant_exists(tuned["group"], tuned["tile"], wave=True)
+    batch = native.Batch(tpl, orb, orb, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
+                         group=tuned["group"], tile=tuned["tile"], adjoint=True, device=dev)
+    batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
+    out = batch.response_gb(params)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    op = oracle.Orbits.from_samples(bc.orbits_proj)
+    rng = np.random.default_rng(77)
+    g_out = torch.zeros_like(out)
+    sel = {}
+    for k in (3, 200):
+        g = bc.grids[k]
+        off = bc.layout.out_offsets[k]
+        hp_o, hc_o = owf.polarizations(bc.params[k], g.waveform_times())
+        case = workloads.Case("walker_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
+                              hp_o, hc_o, bc.order, bc.generation, bc.channels)
+        idx = cases.sample_indices(g.n_out, 120, seed=700 + k, edge=3)
+        ref = cases.sampled_response(op, op, case, idx)
+        got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
+        cases.check(got, ref, 1e-11, "waveform-mode forward walker %d" % k)
+        gs = rng.standard_normal((3, idx.size))
+        blk = g_out[off:off + 3 * g.n_out].view(3, g.n_out)
+        blk[:, torch.from_numpy(idx).to(dev)] = torch.tensor(gs, dtype=torch.float64, device=dev)
+        sel[k] = (case, idx, gs)
+    g_par = batch.adjoint_gb(params, g_out).cpu().numpy()
+    for k, (case, idx, gs) in sel.items():
+        g = case.grid
+        rhp, rhc = cases.sampled_adjoint(op, op, case, idx, gs)
+        vjp = owf.polarizations_vjp(case.params, g.waveform_times(), rhp, rhc)
+        assert np.all(np.abs(g_par[k, :6] - vjp[:6]) <= 1e-9 * np.abs(vjp[:6])), \
+            (k, g_par[k], vjp)
+
+        def J(lam, beta, case=case, idx=idx, gs=gs):
+            c = workloads.Case(case.name, case.orbits_proj, case.orbits_tdi, case.grid,
+                               np.concatenate([case.params[:6], [lam, beta]]), case.hp, case.hc,
+                               case.order, case.generation, case.channels)
+            return float(np.sum(cases.sampled_response(op, op, c, idx) * gs))
+
+        fd_lam = _fd_richardson(lambda x: J(x, case.beta), case.lam, 1e-4)
+        fd_beta = _fd_richardson(lambda x: J(case.lam, x), case.beta, 1e-4)
+        assert abs(g_par[k, 6] - fd_lam) <= 1e-6 * abs(fd_lam), (k, g_par[k, 6], fd_lam)
+        assert abs(g_par[k, 7] - fd_beta) <= 1e-6 * abs(fd_beta), (k, g_par[k, 7], fd_beta)
+    rest = [k for k in range(batch.n) if k not in sel]
+    assert np.all(g_par[rest] == 0.0)
