@@ -357,3 +357,38 @@ def test_waveform_mode_every_compiled_shape_and_the_rest_refused(torch_cuda):
                 with pytest.raises(native.LisaRespError) as e:
                     b.response_gb(params)
                 assert e.value.status == native.LR_E_UNSUPPORTED, (g, tile)
+
+
+@pytest.mark.parametrize("order,gen,group", [(1, 1, 1), (7, 2, 2), (31, 2, 2), (13, 1, 2)])
+def test_waveform_mode_other_orders_and_generations(torch_cuda, order, gen, group):
+    """The waveform-mode kernel variants of other tap counts and of TDI-1:
+    lr_response_gb equals lr_gb_polarizations + lr_response bit for bit,
+    and one template against the oracle fed with the oracle's waveform."""
+    torch = torch_cuda
+    from oracle import waveform as owf
+    from paper_2204_06633_amd import native
+    channels = "XYZ" if gen == 1 else "AET"
+    B = _build(torch, [700, 1234], order=order, gen=gen, channels=channels, group=group,
+               seed=40 + order)
+    batch = B["batch"]
+    params = _t(torch, B["params"])
+    hp = torch.zeros(max(batch.h_extent, 1), dtype=torch.float64, device="cuda")
+    hc = torch.zeros_like(hp)
+    for k, g in enumerate(B["grids"]):
+        ho = B["lay"].h_offsets[k]
+        a, b = native.gb_polarizations(params[k:k + 1].contiguous(), -g.out_start, g.n_h, g.dt)
+        hp[ho:ho + g.n_h] = a[0]
+        hc[ho:ho + g.n_h] = b[0]
+    out_ref = batch.response(hp, hc, params[:, 6:8].contiguous())
+    out_gb = batch.response_gb(params)
+    torch.cuda.synchronize()
+    assert torch.equal(out_gb[:batch.out_extent], out_ref[:batch.out_extent])
+    k = 1
+    g = B["grids"][k]
+    oo = B["lay"].out_offsets[k]
+    p = B["params"][k]
+    op = oracle.Orbits.from_samples(B["sp"])
+    h_p, h_c = owf.polarizations(p, g.waveform_times())
+    ref = oracle.response(op, op, g, h_p, h_c, p[6], p[7], order, gen, channels)
+    cases.check(out_gb[oo:oo + 3 * g.n_out].view(3, g.n_out).cpu().numpy(), ref, TOL,
+                "waveform mode, order %d, TDI-%d" % (order, gen))
