@@ -734,6 +734,10 @@ def main():
         torch.cuda.empty_cache()
         result["walkers_keplerian"], _ = bench_walkers(3, 1, {}, tdi_orbit_kind="keplerian")
         torch.cuda.empty_cache()
+        # the batched forward + adjoint against the plain per-template forward
+        plain = head["plain_per_template"]["value"]
+        for leg in ("walkers", "walkers_keplerian"):
+            result[leg]["vs_plain_per_template_forward"] = result[leg]["value"] / plain
         single, st = bench_single_template(args.steps)
         result["single_template"] = single
         result.update(bench_widened(args.steps, st))
