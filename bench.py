@@ -204,7 +204,8 @@ def bench_headline(steps, warmup, keep):
     del graph, out, hp, hc
     res = {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
            "value": rate, "ms_per_step": ms_step, "ms_per_launch_events": ms_launch,
-           "group": group, "tile": batch.tile, "grid_scale": tuned["grid_scale"],
+           "group": group, "tile": batch.tile, "segment": batch.segment,
+           "grid_scale": tuned["grid_scale"],
            "blocks": batch.blocks,
            "roofline": roof,
            "plain_per_template": {"value": plain_rate, "unit": UNIT, "templates_timed": len(pick),
@@ -279,6 +280,7 @@ def bench_walkers(steps, warmup, keep, tdi_orbit_kind="rigid"):
     return {"workload": bc.name, "templates": len(bc.grids), "time_samples": n,
             "value": 6.0 * n / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms,
             "steps": steps, "graph": True, "group": tuned["group"], "tile": batch.tile,
+            "segment": batch.segment,
             "stage_ms": {"forward": ms_fwd, "likelihood": ms_like, "adjoint": ms_adj},
             "step_over_forward": ms / ms_fwd, "gradients_finite": finite,
             "roofline": _roofline(ops, ms, "whole step (fused forward with in-kernel waveform, "

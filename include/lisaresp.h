@@ -247,7 +247,7 @@ typedef struct {
     double t0, dt;
     int order, generation, channels, group;
     int front, tile_out, blocks, adjoint;
-    int tile, reserved;  /* link samples per forward work item; padding */
+    int tile, segment;   /* link samples per forward tile; tiles per forward work item */
     int64_t n_templates, n_items, n_tdi_items, n_proj_items, n_like_items;
     int64_t n_tdi_citems, n_padj_citems;
     int64_t gy_doubles, h_extent, out_extent;
@@ -260,22 +260,26 @@ typedef struct {
  * every template). */
 size_t lr_batch_workspace(const lr_template *t, int64_t n, const lr_orbits *tdi, double dt,
                           int order, int generation, int channels, int group, int tile,
-                          int adjoint);
+                          int segment, int adjoint);
 
 /* Validate a batch (per-template padding from lr_projection_padding /
  * lr_tdi_padding, orbit coverage, output blocks), build the work lists and
  * copy them into ws (synchronises `stream` once; call it outside graph
  * capture).  t: [host][n]; group = templates per work item (1, 2 or 4);
- * tile = link samples per forward work item (256, 512 or 1024, not 1024
- * with group 4; 0 = 512): the autotuner's tile-length knob; results do not
- * depend on group, tile or grid.  t0: absolute time of output sample 0.
+ * tile = link samples per forward tile (256, 512 or 1024, not 1024 with
+ * group 4; 0 = 512): the autotuner's tile-length knob; segment = tiles per
+ * forward work item (1..64; 0 = automatic): consecutive tiles of a work item
+ * pass the TDI halo on in LDS, so that only the first computes the halo's
+ * link samples (taken as 1 where the halo exceeds what the kernel carries;
+ * lr_batch.segment holds the value used).  Results do not depend on group,
+ * tile, segment or grid.  t0: absolute time of output sample 0.
  * Errors: LR_E_ARG, LR_E_RANGE, LR_E_UNSUPPORTED (dt so small that the TDI
  * stencil does not fit a tile, or an uncompiled group/tile pair),
  * LR_E_WORKSPACE, LR_E_HIP. */
 int lr_batch_prepare(const lr_template *t, int64_t n, const lr_orbits *proj,
                      const lr_orbits *tdi, double t0, double dt, int order, int generation,
-                     int channels, int group, int tile, int adjoint, void *ws, size_t ws_bytes,
-                     lr_batch *out, void *stream);
+                     int channels, int group, int tile, int segment, int adjoint, void *ws,
+                     size_t ws_bytes, lr_batch *out, void *stream);
 
 /* Forward response of every template (Sec. IV.B-IV.C): hp, hc hold the
  * templates' h arrays at their offsets, sky is device [n][2] (lam, beta),

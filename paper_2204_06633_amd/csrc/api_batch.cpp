@@ -17,7 +17,8 @@ namespace {
 
 using lr::set_error;
 
-constexpr int kYTileDefault = 512;    // link samples per fused work item (2 per lane)
+constexpr int kYTileDefault = 512;    // link samples per fused tile (2 per lane)
+constexpr int kMaxSegment = 64;       // tiles per fused work item (segment)
 constexpr int64_t kAdjTile = 256;     // samples per adjoint work item (atomic kernels, sky)
 constexpr int64_t kCarryTile = 512;   // samples per work item of the carry adjoint kernels
 constexpr int64_t kLikeChunk = 8192;  // elements per likelihood work item
@@ -32,7 +33,7 @@ static_assert(R_COUNT <= (int)(sizeof(((lr_batch*)nullptr)->off) / sizeof(size_t
               "lr_batch.off has a slot per workspace region");
 
 struct Plan {
-  int F = 0, B = 0, T_out = 0, Y = 0;
+  int F = 0, B = 0, T_out = 0, Y = 0, K = 1;
   std::vector<lr::BatchTemplate> tpl;
   std::vector<int> items;
   std::vector<lr::BatchAdjTemplate> adj;
@@ -58,7 +59,8 @@ bool fused_variant_exists(int group, int tile, bool wave) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, int order,
-              int generation, int channels, int group, int tile, int adjoint, Plan& P) {
+              int generation, int channels, int group, int tile, int segment, int adjoint,
+              Plan& P) {
   if (n < 0 || (n > 0 && !t)) return set_error(LR_E_ARG, "bad template list");
   if (group != 1 && group != 2 && group != 4)
     return set_error(LR_E_UNSUPPORTED, "group %d (1, 2 or 4 templates per work item)", group);
@@ -67,6 +69,8 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
     return set_error(LR_E_UNSUPPORTED, "tile %d with group %d (tiles of 256, 512 or 1024 link "
                                        "samples; 1024 not with groups of 4)", tile, group);
   P.Y = tile;
+  if (segment < 0 || segment > kMaxSegment)
+    return set_error(LR_E_ARG, "segment %d (0 = automatic, or 1..%d tiles)", segment, kMaxSegment);
   if (channels != LR_XYZ && channels != LR_AET && channels != LR_XYZ_AET)
     return set_error(LR_E_UNSUPPORTED, "channels %d", channels);
   if (!valid_order(order)) return set_error(LR_E_UNSUPPORTED, "order %d (odd 1..31)", order);
@@ -88,20 +92,31 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
                    [&](int64_t a, int64_t b) { return t[a].n_out > t[b].n_out; });
   const int64_t n_groups = (n + group - 1) / group;
   P.tpl.assign(n_groups * group, lr::BatchTemplate{0, 0, 0, 0, 0, -1});
+  std::vector<int64_t> gmax(n_groups, 0);
+  int64_t tiles1 = 0;                       // work items at one tile per segment
   for (int64_t g = 0; g < n_groups; ++g) {
-    int64_t gmax = 0;
     for (int k = 0; k < group; ++k) {
       const int64_t s = g * group + k;
       if (s >= n) break;
       const lr_template& T = t[order_idx[s]];
       P.tpl[s] = lr::BatchTemplate{T.h_offset, T.n_h, T.out_start, T.n_out, T.out_offset,
                                    order_idx[s]};
-      gmax = std::max(gmax, T.n_out);
+      gmax[g] = std::max(gmax[g], T.n_out);
     }
-    const int64_t tiles = (gmax + P.T_out - 1) / P.T_out;
-    for (int64_t tl = 0; tl < tiles; ++tl) {
+    tiles1 += (gmax[g] + P.T_out - 1) / P.T_out;
+  }
+  // Segments of K tiles carry the TDI halo from tile to tile (every tile
+  // after the first has `tile` outputs) when the halo fits the kernel's
+  // rows; automatic K: up to 8 while the batch keeps >= 2048 work items.
+  if (tile - P.T_out > lr::fused_halo_cap(group, tile / 2)) P.K = 1;   // workgroup: tile / 2
+  else if (segment > 0) P.K = segment;
+  else P.K = (int)std::max<int64_t>(1, std::min<int64_t>(8, tiles1 / 2048));
+  const int64_t seg_out = P.T_out + (int64_t)(P.K - 1) * tile;
+  for (int64_t g = 0; g < n_groups; ++g) {
+    const int64_t segs = (gmax[g] + seg_out - 1) / seg_out;
+    for (int64_t sg = 0; sg < segs; ++sg) {
       P.items.push_back((int)g);
-      P.items.push_back((int)tl);
+      P.items.push_back((int)sg);
     }
   }
   if ((int64_t)P.items.size() / 2 > (int64_t)0x7fffffff)
@@ -238,6 +253,8 @@ int launch_forward(const lr_batch* b, const double* hp, const double* hc, const 
   a.inv_dt = 1.0 / b->dt;
   a.F = b->front;
   a.T_out = b->tile_out;
+  a.HP = b->segment > 1 ? b->tile - b->tile_out : 0;
+  a.seg_tiles = b->segment;
   a.hp = hp;
   a.hc = hc;
   a.sky = sky;
@@ -262,20 +279,22 @@ extern "C" {
 
 size_t lr_batch_workspace(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt,
                           int order, int generation, int channels, int group, int tile,
-                          int adjoint) {
+                          int segment, int adjoint) {
   Plan P;
-  if (make_plan(t, n, tdi, dt, order, generation, channels, group, tile, adjoint, P)) return 0;
+  if (make_plan(t, n, tdi, dt, order, generation, channels, group, tile, segment, adjoint, P))
+    return 0;
   return P.total;
 }
 
 int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
                      const lr_orbits* tdi, double t0, double dt, int order, int generation,
-                     int channels, int group, int tile, int adjoint, void* ws, size_t ws_bytes,
-                     lr_batch* out, void* stream) {
+                     int channels, int group, int tile, int segment, int adjoint, void* ws,
+                     size_t ws_bytes, lr_batch* out, void* stream) {
   if (!out || !proj || !tdi) return set_error(LR_E_ARG, "null pointer");
   if (!std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt)) return set_error(LR_E_ARG, "bad t0 or dt");
   Plan P;
-  if (int st = make_plan(t, n, tdi, dt, order, generation, channels, group, tile, adjoint, P))
+  if (int st = make_plan(t, n, tdi, dt, order, generation, channels, group, tile, segment,
+                         adjoint, P))
     return st;
   if (!ws || ws_bytes < P.total)
     return set_error(LR_E_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, P.total);
@@ -349,7 +368,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
   out->front = P.F;
   out->tile_out = P.T_out;
   out->tile = P.Y;
-  out->reserved = 0;
+  out->segment = P.K;
   out->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)cus * per_cu));
   out->adjoint = adjoint ? 1 : 0;
   out->n_templates = n;

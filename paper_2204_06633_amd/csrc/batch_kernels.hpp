@@ -161,13 +161,17 @@ template <int N, int GEN, int M, int BLOCK, bool WAVE>
 __global__ __launch_bounds__(BLOCK, M == 2 ? (WAVE ? LR_FUSED2W_MIN_WAVES : LR_FUSED2_MIN_WAVES)
                                            : LR_FUSED_MIN_WAVES)
 void fused_forward_kernel(BatchFwdArgs a) {
-  constexpr int YT = kPerLane * BLOCK;                // link samples per work item
+  constexpr int YT = kPerLane * BLOCK;                // new link samples per tile
+  constexpr int HPX = fused_halo_cap(M, BLOCK);       // halo a row can carry
+  constexpr int YR = YT + HPX;                        // row length
+  constexpr int NST = (M * 6 * HPX + BLOCK - 1) / BLOCK;   // halo values per lane (<= 2)
   constexpr int CAPH = YT + N + kSlack;
   // Template k's h window lives in its own link rows until its projection
   // ends (the rows are written only after a barrier), so the window costs no
   // LDS of its own.
-  static_assert(CAPH * sizeof(double2) <= 6 * YT * sizeof(double), "h window fits a row block");
-  __shared__ __align__(16) double ylds[M * 6 * YT];
+  static_assert(CAPH * sizeof(double2) <= 6 * YR * sizeof(double), "h window fits a row block");
+  static_assert(NST <= 2, "two halo values per lane");
+  __shared__ __align__(16) double ylds[M * 6 * YR];
   __shared__ int red[2][BLOCK / 64];
   __shared__ int s_item;
 
@@ -179,85 +183,120 @@ void fused_forward_kernel(BatchFwdArgs a) {
     asm volatile("" : "+v"(tid));
     if (tid == 0) s_item = atomicAdd(a.counter, 1);
     __syncthreads();
-    // uniform values in scalar registers: the item, its group and tile, and
-    // (below) the templates' records come through scalar loads
+    // uniform values in scalar registers: the item, its group and segment,
+    // and (below) the templates' records come through scalar loads
     const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= a.n_items) break;
     const int grp = __builtin_amdgcn_readfirstlane(a.items[2 * item]);
-    const int tile = __builtin_amdgcn_readfirstlane(a.items[2 * item + 1]);
-    const int64_t o0 = (int64_t)tile * a.T_out;       // output index of the tile's first output
-    const int64_t i_base = o0 - a.F;                  // output index of tile element 0
-
-    // 1. link series of each template of the group into LDS (one copy of the
-    // projection code, templates in a rolled loop)
-    bool live[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const BatchTemplate T = a.tpl[grp * M + k];
-      live[k] = T.index >= 0 && o0 < T.n_out;
-    }
+    const int seg = __builtin_amdgcn_readfirstlane(a.items[2 * item + 1]);
+    const int hp = a.HP;                              // 0: one tile per segment
+    const int64_t S = (int64_t)seg * (a.T_out + (int64_t)(a.seg_tiles - 1) * YT);
+    const int64_t n_long = a.tpl[grp * M].n_out;      // the group's longest template
+    // A segment is seg_tiles consecutive tiles.  Row r of a tile holds link
+    // sample rb + r (output-index space, rb = first output - F - ro): the
+    // tile's YT new link samples go to rows [hp, hp + YT); from the second
+    // tile on, rows [0, hp) hold the previous tile's last hp samples (rows
+    // [YT, YT + hp) there), so every tile after the first has YT outputs.
+    double halo[NST > 0 ? NST : 1];
 #pragma unroll 1
-    for (int k = 0; k < M; ++k) {
-      const BatchTemplate T = a.tpl[grp * M + k];
-      if (!(T.index >= 0 && o0 < T.n_out)) continue;  // uniform
-      const int64_t n_valid = min((int64_t)a.T_out, T.n_out - o0);
-      const int r_end = (int)min((int64_t)YT, a.F + n_valid + (YT - a.F - a.T_out));
-      const int last = r_end - 1;
-      const bool act_a = 2 * tid <= last, act_b = 2 * tid + 1 <= last;
-      const int ra = act_a ? 2 * tid : (last & ~1);
-      // sin, cos of the sky angles, tabulated per template before the launch
-      // (no trigonometry, and none of its constants, in this loop)
-      const double* tr = a.trig + 4 * T.index;
-      const Sky sk = sky_from_trig(tr[0], tr[1], tr[2], tr[3]);
-      double ya[6], yb[6];
-      double2* hwin = reinterpret_cast<double2*>(ylds + k * 6 * YT);
-      // h+ / hx: the caller's arrays, or the waveform synthesised into the
-      // window from the template's parameter row (waveform time 0 at output
-      // sample 0)
-      HSource hs;
-      if constexpr (WAVE)
-        hs = HSource::waveform(a.params + 8 * T.index, -T.out_start, a.dt, T.n_h);
-      else
-        hs = HSource::arrays(a.hp + T.h_off, a.hc + T.h_off, T.n_h);
-      project_pair<N, BLOCK>(a.orb_p, a.t_off_p, i_base, a.dt, a.inv_dt, hs,
-                             T.out_start + i_base, sk, ra, hwin, red, ya, yb);
-      __syncthreads();                                // the window is read; rows may be written
-#pragma unroll
-      for (int l = 0; l < 6; ++l) {
-        double* row = ylds + (k * 6 + l) * YT;
-        if (act_a) row[par<YT>(ra)] = ya[l];
-        if (act_b) row[par<YT>(ra + 1)] = yb[l];
-      }
-    }
-    __syncthreads();
+    for (int t = 0; t < a.seg_tiles; ++t) {
+      const int64_t o0 = t == 0 ? S : S + a.T_out + (int64_t)(t - 1) * YT;
+      if (o0 >= n_long) break;                        // uniform
+      const int cnt = t == 0 ? a.T_out : YT;          // outputs of this tile
+      const int ro = t == 0 ? hp : 0;
+      const int64_t i_new = o0 - a.F + (t == 0 ? 0 : hp);   // link sample of row hp
 
-    // 2. TDI of the tile's outputs for all live templates
-    const int oa = 2 * tid;                           // tile-relative output of sample a
-    const bool out_a = oa < a.T_out;
-    const int ob = out_a ? oa : a.T_out - 2;          // idle lanes mirror the last pair
-    double La[6], Lb[6];
-    light_times(a.orb_t, a.t_off_t + (double)(o0 + ob) * a.dt, La);
-    light_times(a.orb_t, a.t_off_t + (double)(o0 + ob + 1) * a.dt, Lb);
-    double acc[M][2][3];
-    fused_tdi<N, GEN, M, YT>(a, ylds, La, Lb, a.F + ob, live, acc);
-
-    // 3. store (the template records read again rather than kept live
-    // through the TDI: an opaque copy of the group index stops the compiler
-    // from reusing the first loads)
-    int grp_s = grp;
-    asm volatile("" : "+s"(grp_s));
-    if (out_a) {
+      // 1. link series of each template of the group into LDS (one copy of the
+      // projection code, templates in a rolled loop)
+      bool live[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        if (!live[k]) continue;
-        const BatchTemplate T = a.tpl[grp_s * M + k];
-        const int64_t i = o0 + oa;
-        if (i < T.n_out) store_channels(acc[k][0], a.channels, a.out + T.out_off, T.n_out, i);
-        if (i + 1 < T.n_out)
-          store_channels(acc[k][1], a.channels, a.out + T.out_off, T.n_out, i + 1);
+        const BatchTemplate T = a.tpl[grp * M + k];
+        live[k] = T.index >= 0 && o0 < T.n_out;
       }
+#pragma unroll 1
+      for (int k = 0; k < M; ++k) {
+        const BatchTemplate T = a.tpl[grp * M + k];
+        if (!(T.index >= 0 && o0 < T.n_out)) continue;  // uniform
+        const int64_t n_valid = min((int64_t)cnt, T.n_out - o0);
+        // new rows up to the last valid output's stencil (the padding B
+        // rounded to the even halo YT - T_out)
+        const int r_end =
+            (int)min((int64_t)YT, n_valid + (YT - a.T_out) - (t == 0 ? 0 : hp));
+        const int last = r_end - 1;
+        const bool act_a = 2 * tid <= last, act_b = 2 * tid + 1 <= last;
+        const int ra = act_a ? 2 * tid : (last & ~1);
+        // sin, cos of the sky angles, tabulated per template before the launch
+        // (no trigonometry, and none of its constants, in this loop)
+        const double* tr = a.trig + 4 * T.index;
+        const Sky sk = sky_from_trig(tr[0], tr[1], tr[2], tr[3]);
+        double ya[6], yb[6];
+        double2* hwin = reinterpret_cast<double2*>(ylds + k * 6 * YR);
+        // h+ / hx: the caller's arrays, or the waveform synthesised into the
+        // window from the template's parameter row (waveform time 0 at output
+        // sample 0)
+        HSource hs;
+        if constexpr (WAVE)
+          hs = HSource::waveform(a.params + 8 * T.index, -T.out_start, a.dt, T.n_h);
+        else
+          hs = HSource::arrays(a.hp + T.h_off, a.hc + T.h_off, T.n_h);
+        project_pair<N, BLOCK>(a.orb_p, a.t_off_p, i_new, a.dt, a.inv_dt, hs,
+                               T.out_start + i_new, sk, ra, hwin, red, ya, yb);
+        __syncthreads();                              // the window is read; rows may be written
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+          double* row = ylds + (k * 6 + l) * YR;
+          if (act_a) row[par<YR>(hp + ra)] = ya[l];
+          if (act_b) row[par<YR>(hp + ra + 1)] = yb[l];
+        }
+        if (t > 0) {
+          // the carried halo of this template back into its rows
+#pragma unroll
+          for (int q = 0; q < NST; ++q) {
+            const int e = tid + BLOCK * q, rho = e / max(HPX, 1), j = e - rho * HPX;
+            if (rho / 6 == k && rho < M * 6 && j < hp) ylds[rho * YR + par<YR>(j)] = halo[q];
+          }
+        }
+      }
+      __syncthreads();
+
+      // 2. TDI of the tile's outputs for all live templates
+      const int oa = 2 * tid;                         // tile-relative output of sample a
+      const bool out_a = oa < cnt;
+      const int ob = out_a ? oa : cnt - 2;            // idle lanes mirror the last pair
+      double La[6], Lb[6];
+      light_times(a.orb_t, a.t_off_t + (double)(o0 + ob) * a.dt, La);
+      light_times(a.orb_t, a.t_off_t + (double)(o0 + ob + 1) * a.dt, Lb);
+      double acc[M][2][3];
+      fused_tdi<N, GEN, M, YR>(a, ylds, La, Lb, a.F + ro + ob, live, acc);
+
+      // 3. store (the template records read again rather than kept live
+      // through the TDI: an opaque copy of the group index stops the compiler
+      // from reusing the first loads)
+      int grp_s = grp;
+      asm volatile("" : "+s"(grp_s));
+      if (out_a) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          if (!live[k]) continue;
+          const BatchTemplate T = a.tpl[grp_s * M + k];
+          const int64_t i = o0 + oa;
+          if (i < T.n_out) store_channels(acc[k][0], a.channels, a.out + T.out_off, T.n_out, i);
+          if (i + 1 < T.n_out)
+            store_channels(acc[k][1], a.channels, a.out + T.out_off, T.n_out, i + 1);
+        }
+      }
+      if (t + 1 < a.seg_tiles) {
+        // the next tile's halo: this tile's rows [YT, YT + hp), read before
+        // the next tile's projection windows overwrite them
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+          const int e = tid + BLOCK * q, rho = e / max(HPX, 1), j = e - rho * HPX;
+          if (rho < M * 6 && j < hp) halo[q] = ylds[rho * YR + par<YR>(YT + j)];
+        }
+      }
+      __syncthreads();                                // LDS free for the next tile
     }
-    __syncthreads();                                  // LDS free for the next item
   }
 }
 

@@ -17,16 +17,31 @@ struct BatchTemplate {
   int64_t index;       // position in the caller's template list (sky row); < 0: empty slot
 };
 
+// Link samples of TDI halo that a fused work item of m templates and
+// workgroups of `block` lanes carries from one tile to the next: the halo of
+// every link row passes the next tile's projection in two registers per lane,
+// and the rows are that much longer.  0 (no carrying) when fewer than 32
+// samples would fit, at most 64.
+constexpr int fused_halo_cap(int m, int block) {
+  const int c = (2 * block / (6 * m)) & ~1;
+  return c < 32 ? 0 : (c < 64 ? c : 64);
+}
+
 struct BatchFwdArgs {
   OrbitView orb_p, orb_t;
-  const BatchTemplate* tpl;  // [n_groups * M], grouped
-  const int* items;          // [n_items][2]: group, tile
+  const BatchTemplate* tpl;  // [n_groups * M], grouped, longest template first
+  const int* items;          // [n_items][2]: group, segment
   int n_items;
   int* counter;              // work-item counter, zero before the launch
   double t_off_p, t_off_t;   // time of output sample 0 minus each orbit grid's first sample
   double dt, inv_dt;
   int F;                     // link samples before the first output of a tile
-  int T_out;                 // outputs per tile (even)
+  int T_out;                 // outputs of a segment's first tile (even): link samples per
+                             // tile minus the TDI halo
+  int HP;                    // halo carried from tile to tile (link samples per tile -
+                             // T_out), 0 for segments of one tile
+  int seg_tiles;             // tiles per segment: T_out + (seg_tiles - 1) * link samples per
+                             // tile outputs
   const double* hp;
   const double* hc;
   const double* sky;         // lam, beta of template k at sky[sky_stride * k + 0, 1]

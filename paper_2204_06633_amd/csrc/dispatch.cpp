@@ -67,6 +67,11 @@ hipError_t run_project_adjoint(int order, const ProjAdjArgs& a, hipStream_t s) {
 
 hipError_t run_fused_forward(int order, int gen, int group, int tile, bool wave,
                              const BatchFwdArgs& a, int blocks, hipStream_t s) {
+  // the kernel's rows hold at most fused_halo_cap(group, workgroup) carried
+  // samples, and a segment of one tile carries none
+  if (a.seg_tiles < 1 || a.HP < 0 || a.HP > fused_halo_cap(group, tile / 2) ||
+      (a.seg_tiles > 1) != (a.HP > 0) || (a.HP > 0 && a.HP != tile - a.T_out))
+    return hipErrorInvalidValue;
   switch (order) {
 #define X(ORD, NT)                                                                        \
   case ORD:                                                                               \

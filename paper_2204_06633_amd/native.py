@@ -391,7 +391,7 @@ class lr_batch(ctypes.Structure):
                 ("dt", ctypes.c_double), ("order", ctypes.c_int), ("generation", ctypes.c_int),
                 ("channels", ctypes.c_int), ("group", ctypes.c_int), ("front", ctypes.c_int),
                 ("tile_out", ctypes.c_int), ("blocks", ctypes.c_int), ("adjoint", ctypes.c_int),
-                ("tile", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("tile", ctypes.c_int), ("segment", ctypes.c_int),
                 ("n_templates", ctypes.c_int64), ("n_items", ctypes.c_int64),
                 ("n_tdi_items", ctypes.c_int64), ("n_proj_items", ctypes.c_int64),
                 ("n_like_items", ctypes.c_int64), ("n_tdi_citems", ctypes.c_int64),
@@ -408,8 +408,8 @@ def _batch_lib():
     P = ctypes.POINTER
     pt, po, pb = P(lr_template), P(lr_orbits), P(lr_batch)
     L.lr_batch_workspace.restype = ctypes.c_size_t
-    L.lr_batch_workspace.argtypes = [pt, i64, po, d, i32, i32, i32, i32, i32, i32]
-    L.lr_batch_prepare.argtypes = [pt, i64, po, po, d, d, i32, i32, i32, i32, i32, i32, vp,
+    L.lr_batch_workspace.argtypes = [pt, i64, po, d, i32, i32, i32, i32, i32, i32, i32]
+    L.lr_batch_prepare.argtypes = [pt, i64, po, po, d, d, i32, i32, i32, i32, i32, i32, i32, vp,
                                    ctypes.c_size_t, pb, vp]
     L.lr_response.argtypes = [pb, vp, vp, vp, vp, vp]
     L.lr_response_gb.argtypes = [pb, vp, vp, vp]
@@ -431,13 +431,14 @@ class Batch:
 
     ``templates``: sequence of (h_offset, n_h, out_start, n_out, out_offset).
     ``group``: templates per forward work item; ``tile``: link samples per
-    forward work item (256, 512, 1024; 0 = 512).
+    forward tile (256, 512, 1024; 0 = 512); ``segment``: tiles per forward
+    work item, which pass the TDI halo on (1..64; 0 = automatic).
     The orbit objects must outlive the batch (it holds their device pointers).
     """
 
     def __init__(self, templates, orb_proj: Orbits, orb_tdi: Orbits, t0, dt, order=25,
                  generation=2, channels="XYZ", group=2, adjoint=False, device="cuda",
-                 stream=None, tile=0):
+                 stream=None, tile=0, segment=0):
         import torch
         L = _batch_lib()
         n = len(templates)
@@ -449,7 +450,7 @@ class Batch:
         self.channels = channels
         self.rows = 6 if channels == "XYZAET" else 3
         nbytes = L.lr_batch_workspace(arr, n, orb_tdi.ref, float(dt), int(order), int(generation),
-                                      CHANNELS[channels], int(group), int(tile),
+                                      CHANNELS[channels], int(group), int(tile), int(segment),
                                       int(bool(adjoint)))
         if nbytes == 0:
             raise LisaRespError(1, "lr_batch_workspace", L.lr_last_error().decode())
@@ -457,7 +458,8 @@ class Batch:
         self.c = lr_batch()
         _check(L.lr_batch_prepare(arr, n, orb_proj.ref, orb_tdi.ref, float(t0), float(dt),
                                   int(order), int(generation), CHANNELS[channels], int(group),
-                                  int(tile), int(bool(adjoint)), ctypes.c_void_p(self.ws.data_ptr()),
+                                  int(tile), int(segment), int(bool(adjoint)),
+                                  ctypes.c_void_p(self.ws.data_ptr()),
                                   self.ws.numel() * 8, ctypes.byref(self.c), _stream(stream)),
                "lr_batch_prepare")
 
@@ -478,8 +480,13 @@ class Batch:
 
     @property
     def tile(self):
-        """Link samples per forward work item."""
+        """Link samples per forward tile."""
         return int(self.c.tile)
+
+    @property
+    def segment(self):
+        """Tiles per forward work item (the value the plan used)."""
+        return int(self.c.segment)
 
     def set_grid(self, blocks):
         _check(_batch_lib().lr_batch_set_grid(ctypes.byref(self.c), int(blocks)),

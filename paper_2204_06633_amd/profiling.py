@@ -36,7 +36,9 @@ def main(argv=None):
                     default="forward")
     ap.add_argument("--templates", type=int, default=64)
     ap.add_argument("--group", type=int, default=2)
-    ap.add_argument("--tile", type=int, default=0, help="link samples per fused work item")
+    ap.add_argument("--tile", type=int, default=0, help="link samples per fused tile")
+    ap.add_argument("--segment", type=int, default=0,
+                    help="fused tiles per work item (0: the plan's automatic choice)")
     ap.add_argument("--grid-scale", type=float, default=1.0)
     ap.add_argument("--waveform", action="store_true",
                     help="waveform mode (lr_response_gb / lr_response_adjoint_gb)")
@@ -117,7 +119,8 @@ def run_batch(args, dev):
         hp, hc = workloads.device_polarizations(bc, dev)
         sky = torch.tensor(bc.params[:, 6:8], dtype=torch.float64, device=dev).contiguous()
     b = native.Batch(bc.layout.templates(), orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation,
-                     bc.channels, group=args.group, tile=args.tile, adjoint=adj, device=dev)
+                     bc.channels, group=args.group, tile=args.tile, segment=args.segment,
+                     adjoint=adj, device=dev)
     b.set_grid(max(1, int(round(b.blocks * args.grid_scale))))
     out = torch.empty(b.out_extent, dtype=torch.float64, device=dev)
     data = torch.zeros_like(out) if adj else None

@@ -97,39 +97,47 @@ int main() {
     t.push_back(T);
   }
   for (int group : {1, 2, 4})
-    for (int tile : {0, 256, 512, 1024}) {
-      const size_t ws = lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2,
-                                           LR_AET, group, tile, 1);
-      if (group == 4 && tile == 1024) {               // not compiled
-        CHECK(ws == 0);
-        continue;
+    for (int tile : {0, 256, 512, 1024})
+      for (int segment : {0, 1, 3, 64}) {
+        const size_t ws = lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2,
+                                             LR_AET, group, tile, segment, 1);
+        if (group == 4 && tile == 1024) {             // not compiled
+          CHECK(ws == 0);
+          continue;
+        }
+        CHECK(ws > 0);
+        std::vector<char> w(ws);
+        lr_batch bt_{};
+        const int s2 = lr_batch_prepare(t.data(), (int64_t)t.size(), &orb, &orb, 2e4, 10.0, 25,
+                                        2, LR_AET, group, tile, segment, 1, w.data(), ws, &bt_,
+                                        nullptr);
+        CHECK(s2 == LR_OK || s2 == LR_E_HIP);
+        // too small a workspace, bad group, overlapping outputs, short h
+        CHECK(lr_batch_prepare(t.data(), (int64_t)t.size(), &orb, &orb, 2e4, 10.0, 25, 2, LR_AET,
+                               group, tile, segment, 1, w.data(), ws - 1, &bt_,
+                               nullptr) == LR_E_WORKSPACE);
       }
-      CHECK(ws > 0);
-      std::vector<char> w(ws);
-      lr_batch bt_{};
-      const int s2 = lr_batch_prepare(t.data(), (int64_t)t.size(), &orb, &orb, 2e4, 10.0, 25, 2,
-                                      LR_AET, group, tile, 1, w.data(), ws, &bt_, nullptr);
-      CHECK(s2 == LR_OK || s2 == LR_E_HIP);
-      // too small a workspace, bad group, overlapping outputs, short h
-      CHECK(lr_batch_prepare(t.data(), (int64_t)t.size(), &orb, &orb, 2e4, 10.0, 25, 2, LR_AET,
-                             group, tile, 1, w.data(), ws - 1, &bt_, nullptr) == LR_E_WORKSPACE);
-    }
-  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 3, 0, 0) == 0);
-  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 2, 768, 0) ==
+  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 3, 0, 0, 0) ==
         0);
+  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 2, 768, 0,
+                           0) == 0);
+  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 2, 0, 65,
+                           0) == 0);
+  CHECK(lr_batch_workspace(t.data(), (int64_t)t.size(), &orb, 10.0, 25, 2, LR_AET, 2, 0, -1,
+                           0) == 0);
   std::vector<lr_template> bad = t;
   bad[2].out_offset = bad[0].out_offset;
   {
     const size_t ws = lr_batch_workspace(bad.data(), (int64_t)bad.size(), &orb, 10.0, 25, 2,
-                                         LR_AET, 2, 0, 0);
+                                         LR_AET, 2, 0, 0, 0);
     std::vector<char> w(ws);
     lr_batch bt_{};
     CHECK(lr_batch_prepare(bad.data(), (int64_t)bad.size(), &orb, &orb, 2e4, 10.0, 25, 2,
-                           LR_AET, 2, 0, 0, w.data(), ws, &bt_, nullptr) == LR_E_ARG);
+                           LR_AET, 2, 0, 0, 0, w.data(), ws, &bt_, nullptr) == LR_E_ARG);
     bad = t;
     bad[0].n_h -= 1;
     CHECK(lr_batch_prepare(bad.data(), (int64_t)bad.size(), &orb, &orb, 2e4, 10.0, 25, 2,
-                           LR_AET, 2, 0, 0, w.data(), ws, &bt_, nullptr) == LR_E_RANGE);
+                           LR_AET, 2, 0, 0, 0, w.data(), ws, &bt_, nullptr) == LR_E_RANGE);
   }
   CHECK(lr_status_str(LR_E_RANGE) != nullptr && lr_status_str(99) != nullptr);
   CHECK(lr_last_error() != nullptr);

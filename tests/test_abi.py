@@ -191,21 +191,26 @@ def test_batch_workspace_and_rejections():
     arr, tpl, sp = _batch_templates()
     o = _fake_orbits(n=sp.n, dt=sp.dt, t0=sp.t0)
     aet = native.CHANNELS["AET"]
-    nb = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, 1)
+    nb = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, 0, 1)
     assert nb > 0 and nb % 256 == 0
-    nb0 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, 0)
+    nb0 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, 0, 0)
     assert 0 < nb0 < nb                       # the adjoint adds the link-gradient scratch
     # tile lengths: shorter tiles mean more work items (a larger list)
-    n256 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 256, 0)
-    n1024 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 1024, 0)
+    n256 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 256, 0, 0)
+    n1024 = L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 1024, 0, 0)
     assert n256 >= nb0 >= n1024 > 0
+    # tiles per work item: 1..64, 0 automatic
+    for seg in (1, 2, 64):
+        assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, seg, 0) > 0
+    for seg in (-1, 65):
+        assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, aet, 2, 0, seg, 0) == 0
     # unsupported group size, order, channels, tile; dt too small for a tile
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 3, 0, 0) == 0
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 24, 2, 1, 2, 0, 0) == 0
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 7, 2, 0, 0) == 0
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 4, 1024, 0) == 0
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 2, 300, 0) == 0
-    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 0.05, 25, 2, 1, 2, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 3, 0, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 24, 2, 1, 2, 0, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 7, 2, 0, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 4, 1024, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 10.0, 25, 2, 1, 2, 300, 0, 0) == 0
+    assert L.lr_batch_workspace(arr, 3, ctypes.byref(o), 0.05, 25, 2, 1, 2, 0, 0, 0) == 0
     assert b"too small" in L.lr_last_error()
     # prepare rejects bad h coverage, overlapping outputs and a short workspace
     # before any device work
@@ -213,15 +218,15 @@ def test_batch_workspace_and_rejections():
     bad = (native.lr_template * 3)(*[native.lr_template(*t) for t in tpl])
     bad[0].n_h = 10
     assert L.lr_batch_prepare(bad, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
-                              1, 2, 0, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
+                              1, 2, 0, 0, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
                               None) == native.LR_E_RANGE
     bad = (native.lr_template * 3)(*[native.lr_template(*t) for t in tpl])
     bad[2].out_offset = 5
     assert L.lr_batch_prepare(bad, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
-                              1, 2, 0, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
+                              1, 2, 0, 0, 0, ctypes.c_void_p(0x1000), 1 << 30, ctypes.byref(b),
                               None) == native.LR_E_ARG
     assert L.lr_batch_prepare(arr, 3, ctypes.byref(o), ctypes.byref(o), 1.0e6, 10.0, 25, 2,
-                              1, 2, 0, 0, ctypes.c_void_p(0x1000), 64, ctypes.byref(b),
+                              1, 2, 0, 0, 0, ctypes.c_void_p(0x1000), 64, ctypes.byref(b),
                               None) == native.LR_E_WORKSPACE
 
 

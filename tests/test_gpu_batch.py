@@ -45,6 +45,14 @@ def _build(torch, n_out_list, order=25, gen=2, channels="AET", group=2, adjoint=
                 sky=sky, orbs=(gp, gt), order=order, gen=gen, channels=channels)
 
 
+def _halo_cap(group, tile):
+    """TDI halo the fused kernel's rows carry from tile to tile for a group
+    and tile length: two values per lane over 6 * group rows, 0 below 32,
+    at most 64."""
+    c = (tile // (6 * group)) & ~1
+    return 0 if c < 32 else min(c, 64)
+
+
 def _oracle_out(B, k):
     g = B["grids"][k]
     ho = B["lay"].h_offsets[k]
@@ -175,10 +183,12 @@ def test_graph_capture_replays_match_eager(torch_cuda):
 
 
 def test_group_tile_and_grid_do_not_change_results(torch_cuda, tmp_path):
-    """Each template's arithmetic is the same whatever the group size and the
-    persistent grid, and the tile length (256, 512, 1024 link samples per work
-    item): the outputs agree bit for bit; the autotuner returns one of the
-    candidates and caches it."""
+    """Each template's arithmetic is the same whatever the group size, the
+    persistent grid, the tile length (256, 512, 1024 link samples) and the
+    segment length (tiles per work item passing the TDI halo on in LDS;
+    templates ending inside a segment, segments cut short by the longest
+    template's end): the outputs agree bit for bit; the autotuner returns
+    one of the candidates and caches it."""
     torch = torch_cuda
     from paper_2204_06633_amd import autotune, native
     n_out_list = [1200, 300, 2500, 777, 1, 1600]
@@ -192,13 +202,17 @@ def test_group_tile_and_grid_do_not_change_results(torch_cuda, tmp_path):
         for tile in autotune.TILES:
             if not autotune.variant_exists(g, tile):
                 continue
-            b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g, tile=tile)
-            assert b.tile == tile
-            for blocks in (1, 3, b.blocks, 2 * b.blocks):
-                b.set_grid(blocks)
-                out = b.response(hp, hc, sky)
-                torch.cuda.synchronize()
-                assert torch.equal(out, ref), (g, tile, blocks)
+            for seg in (1, 2, 3, 64):
+                b = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g, tile=tile,
+                                 segment=seg)
+                assert b.tile == tile
+                carries = tile - b.c.tile_out <= _halo_cap(g, tile)
+                assert b.segment == (seg if carries else 1), (g, tile, seg, b.segment)
+                for blocks in (1, 3, b.blocks, 2 * b.blocks):
+                    b.set_grid(blocks)
+                    out = b.response(hp, hc, sky)
+                    torch.cuda.synchronize()
+                    assert torch.equal(out, ref), (g, tile, seg, blocks)
     cache = str(tmp_path / "tune.json")
     r = autotune.tune(tpl, gp, gt, t0, 10.0, 25, 2, "AET", hp, hc, sky, reps=2, cache_path=cache)
     assert r["group"] in autotune.GROUPS and r["grid_scale"] in autotune.GRID_SCALES
@@ -353,6 +367,13 @@ def test_waveform_mode_every_compiled_shape_and_the_rest_refused(torch_cuda):
                 out_gb = b.response_gb(params)
                 torch.cuda.synchronize()
                 assert torch.equal(out_gb[:b.out_extent], ref[:b.out_extent]), (g, tile)
+                # segments of several tiles carrying the TDI halo
+                b3 = native.Batch(tpl, gp, gt, t0, 10.0, 25, 2, "AET", group=g, tile=tile,
+                                  segment=3)
+                assert b3.segment == 3
+                out_gb = b3.response_gb(params)
+                torch.cuda.synchronize()
+                assert torch.equal(out_gb[:b.out_extent], ref[:b.out_extent]), (g, tile, 3)
             else:
                 with pytest.raises(native.LisaRespError) as e:
                     b.response_gb(params)

@@ -12,14 +12,20 @@ workloads and replays the index arithmetic of the kernels on them:
   H = N / 2;
 * plain path: every TDI tap of an output and every projection tap of a link
   sample lies inside the series padded by the library's rule;
-* fused batched forward (Sec. IV.C on a work item's link rows): output r of a
-  work item sits at row F + r of rows of `tile` link samples; a stencil
-  start is clamped into [0, tile - 1 - N] (a lane's pair of samples reads one
-  element past its last tap), which only a wrong padding would hit -- so no
-  stored output may need the clamp, for every tile length the tuner offers;
-* the fused projection stages one window of tile + N + 64 samples per work
-  item; the test checks the benchmark workloads fit it (else the kernel takes
-  its slower global-memory path, correct but not what is measured).
+* fused batched forward (Sec. IV.C on a work item's link rows): a work item
+  is a segment of K tiles; the first tile's outputs r sit at row
+  F + ro + r (ro = the carried halo HP = tile - T_out when K > 1, else 0),
+  a later tile's at row F + r, in rows of tile + cap link samples (cap: the
+  halo the kernel carries for the group and tile); a stencil start is
+  clamped into [0, rows - 1 - N] (a lane's pair of samples reads one element
+  past its last tap), which only a wrong padding would hit -- so no stored
+  output may need the clamp, and every tap lies in a row the tile has
+  written, for every tile length, group and segment length;
+* the fused projection stages one window of tile + N + 64 samples per tile
+  (tile new link samples starting at link index s * seg_out + t * tile for
+  tile t of segment s); the test checks the benchmark workloads fit it (else
+  the kernel takes its slower global-memory path, correct but not what is
+  measured).
 
 The TDI delays are the chained sums of light times of eqs. (tdi1)/(tdi2)
 (the oracle's term lists), the projection delays L_ij + k.x_j / c and
@@ -36,7 +42,25 @@ from paper_2204_06633_amd import native, workloads
 
 C_LIGHT = 299792458.0
 TILES = (256, 512, 1024)
+GROUPS = (1, 2)
+SEGMENTS = (1, 3, 8)
 SLACK = 64          # window samples beyond tile + taps in the fused projection
+
+
+def _halo_cap(group, tile):
+    """Halo samples the fused kernel's rows carry (fused_halo_cap)."""
+    c = (2 * (tile // 2) // (6 * group)) & ~1
+    return 0 if c < 32 else min(c, 64)
+
+
+def _segment_plan(F, B, tile, group, K):
+    """(T_out, HP carried or 0, K used, outputs per segment) of the batch
+    plan's rule."""
+    T_out = (tile - F - B) & ~1
+    HP = tile - T_out
+    if HP > _halo_cap(group, tile):
+        K = 1
+    return T_out, (HP if K > 1 else 0), K, T_out + (K - 1) * tile
 CHUNK = 1 << 20
 
 
@@ -139,14 +163,23 @@ def _check_tdi(orb_samples, t_start, dt, n_out, order, generation, check_tiles):
         return F, B
     o = np.arange(n_out, dtype=np.int64)
     for tile in TILES:
-        T_out = (tile - F - B) & ~1          # outputs per work item (the batch plan's rule)
-        assert T_out >= 2
-        r = o % T_out
-        top = tile - 1 - n_taps
-        start_lo = F + r + lo - (H - 1)
-        start_hi = F + r + hi - (H - 1)
-        assert start_lo.min() >= 0, (tile, int(start_lo.min()))
-        assert start_hi.max() <= top, (tile, int(start_hi.max()), top)
+        for group in GROUPS:
+            for K in SEGMENTS:
+                T_out, HP, K, seg_out = _segment_plan(F, B, tile, group, K)
+                assert T_out >= 2
+                r = o % seg_out                      # position in the segment
+                first = r < T_out
+                row = np.where(first, F + HP + r, F + (r - T_out) % tile)
+                # rows written for the tile: [HP, HP + tile) in the first,
+                # [0, HP + tile) (carried halo, new samples) in later ones;
+                # the pair reads taps start .. start + N
+                lo_ok = np.where(first, HP, 0)
+                start_lo = row + lo - (H - 1)
+                start_hi = row + hi - (H - 1)
+                assert (start_lo - lo_ok).min() >= 0, (tile, group, K)
+                assert (start_hi + n_taps).max() <= HP + tile - 1, (tile, group, K)
+                # inside the clamp range of the kernel's rows
+                assert start_hi.max() <= tile + _halo_cap(group, tile) - 1 - n_taps
     return F, B
 
 
@@ -170,14 +203,17 @@ def _check_projection(orb_samples, t_start, dt, F, B, n_out, order, skies):
         a = i + lo - (H - 1)
         b = i + hi + H
         for tile in TILES:
-            # work item tl holds link samples tl*T_out .. tl*T_out + tile - 1
-            # and stages the window of their taps
-            T_out = (tile - F - B) & ~1
-            w = min(tile, n_y)
-            a_min = np.lib.stride_tricks.sliding_window_view(a, w)[::T_out].min(axis=1)
-            b_max = np.lib.stride_tricks.sliding_window_view(b, w)[::T_out].max(axis=1)
-            worst = int((b_max - a_min).max() + 1)
-            assert worst <= tile + n_taps + SLACK, (tile, worst)
+            for K in SEGMENTS:
+                # tile t of segment s projects link samples from
+                # s * seg_out + t * tile on, and stages the window of their taps
+                _, _, K, seg_out = _segment_plan(F, B, tile, 2, K)
+                w = min(tile, n_y)
+                st = (np.arange(0, n_y, seg_out)[:, None] + tile * np.arange(K)[None, :]).ravel()
+                st = np.unique(np.minimum(st, n_y - w))
+                a_min = np.lib.stride_tricks.sliding_window_view(a, w)[st].min(axis=1)
+                b_max = np.lib.stride_tricks.sliding_window_view(b, w)[st].max(axis=1)
+                worst = int((b_max - a_min).max() + 1)
+                assert worst <= tile + n_taps + SLACK, (tile, K, worst)
 
 
 def test_year_template_taps_in_bounds():
