@@ -5,10 +5,13 @@ Knobs, timed on the caller's own batch (or an evenly spread subset of it):
 * ``group``: templates per work item (1, 2 or 4).  Larger groups share each
   TDI Lagrange coefficient sequence among more templates but hold more link
   series in LDS, so fewer work-groups fit on a CU.
-* ``tile``: link samples per work item (256, 512 or 1024; workgroups of 128,
-  256 or 512 lanes, two samples per lane).  Longer tiles spend less of each
-  item on the TDI halo (about 32 link samples at dt = 10 s) and on set-up,
-  but hold more LDS per work-group.
+* ``tile``: link samples per tile (256, 512 or 1024; workgroups of 128,
+  256 or 512 lanes, two samples per lane).  Longer tiles hold more LDS per
+  work-group; a work item is a segment of consecutive tiles, of which only
+  the first computes the TDI halo (about 34 link samples at dt = 10 s), the
+  others take it from the tile before.  The segment length is the plan's
+  automatic choice (up to 8 tiles, enough work items for the grid), not a
+  tuned knob.
 * ``grid``: work-groups of the persistent launch, as a multiple of the
   resident count that ``lr_batch_prepare`` picks.
 
