@@ -1,7 +1,9 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
 times: the 512-template uneven batch (1.0e9 output samples) checked on
-sampled outputs of several templates against the oracle, and the
-256-walker forward + adjoint checked by the dot-product identity, which
+sampled outputs of several templates against the oracle (the samples include
+the outputs at the fused forward's tile edges, where a tile takes over the
+TDI halo of the one before), the 256-walker forward + adjoint against the
+oracle on sampled outputs, and checked by the dot-product identity, which
 holds at any size."""
 import numpy as np
 import pytest
@@ -11,6 +13,24 @@ from paper_2204_06633_amd import workloads
 from tests import cases
 
 pytestmark = pytest.mark.gpu
+
+
+def _with_segment_edges(idx, batch, n_out):
+    """The sampled outputs plus those at the fused forward's tile edges in a
+    few segments (first, second, middle, last): a segment's first tile has
+    T_out outputs, each later tile `tile`, after the halo carried over."""
+    T_out, tile, K = int(batch.c.tile_out), batch.tile, batch.segment
+    seg_out = T_out + (K - 1) * tile
+    n_seg = -(-n_out // seg_out)
+    edges = []
+    for sg in sorted({0, 1, n_seg // 2, n_seg - 1}):
+        base = sg * seg_out
+        for t in range(K):
+            start = base + (0 if t == 0 else T_out + (t - 1) * tile)
+            edges += [start - 1, start, start + 1]
+        edges += [base + seg_out - 1]
+    edges = [e for e in edges if 0 <= e < n_out]
+    return np.unique(np.concatenate([idx, np.array(edges, dtype=idx.dtype)]))
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +51,7 @@ def test_uneven_batch_512_sampled(torch_cuda):
     batch, _ = autotune.tuned_batch(bc.layout.templates(), orb, orb, bc.t0, bc.dt, bc.order,
                                     bc.generation, bc.channels, hp, hc, sky, use_cache=False,
                                     reps=1, max_templates=16)
+    assert batch.segment > 1                  # work items carrying the TDI halo
     out = batch.response(hp, hc, sky)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(out).all())
@@ -44,7 +65,8 @@ def test_uneven_batch_512_sampled(torch_cuda):
         case = workloads.Case("uneven_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
                               hp[ho:ho + g.n_h].cpu().numpy(), hc[ho:ho + g.n_h].cpu().numpy(),
                               bc.order, bc.generation, bc.channels)
-        idx = cases.sample_indices(g.n_out, 40, seed=k, edge=3)
+        idx = _with_segment_edges(cases.sample_indices(g.n_out, 40, seed=k, edge=3), batch,
+                                  g.n_out)
         ref = cases.oracle_sampled_response(op, op, case, idx)
         got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
         cases.check(got, ref, 1e-11, str(k))
@@ -111,6 +133,7 @@ def test_walkers_256_against_oracle(torch_cuda):
     batch = native.Batch(tpl, orb_p, orb_t, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
                          group=tuned["group"], adjoint=True, device=dev)
     batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
+    assert batch.segment > 1
     out = batch.response(hp, hc, sky)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(out).all())
@@ -126,7 +149,8 @@ def test_walkers_256_against_oracle(torch_cuda):
         case = workloads.Case("walker_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
                               hp[ho:ho + g.n_h].cpu().numpy(), hc[ho:ho + g.n_h].cpu().numpy(),
                               bc.order, bc.generation, bc.channels)
-        idx = cases.sample_indices(g.n_out, 150, seed=500 + k, edge=3)
+        idx = _with_segment_edges(cases.sample_indices(g.n_out, 150, seed=500 + k, edge=3),
+                                  batch, g.n_out)
         ref = cases.sampled_response(op, ot, case, idx)
         got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
         cases.check(got, ref, 1e-11, "forward walker %d" % k)
@@ -189,6 +213,7 @@ def test_walkers_256_keplerian_waveform_mode_against_oracle(torch_cuda):
     batch = native.Batch(tpl, orb, orb, bc.t0, bc.dt, bc.order, bc.generation, bc.channels,
                          group=tuned["group"], tile=tuned["tile"], adjoint=True, device=dev)
     batch.set_grid(max(1, int(round(batch.blocks * tuned["grid_scale"]))))
+    assert batch.segment > 1
     out = batch.response_gb(params)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(out).all())
@@ -202,7 +227,8 @@ def test_walkers_256_keplerian_waveform_mode_against_oracle(torch_cuda):
         hp_o, hc_o = owf.polarizations(bc.params[k], g.waveform_times())
         case = workloads.Case("walker_%d" % k, bc.orbits_proj, bc.orbits_tdi, g, bc.params[k],
                               hp_o, hc_o, bc.order, bc.generation, bc.channels)
-        idx = cases.sample_indices(g.n_out, 120, seed=700 + k, edge=3)
+        idx = _with_segment_edges(cases.sample_indices(g.n_out, 120, seed=700 + k, edge=3),
+                                  batch, g.n_out)
         ref = cases.sampled_response(op, op, case, idx)
         got = batch.output_block(out, k)[:, torch.from_numpy(idx).to(dev)].cpu().numpy()
         cases.check(got, ref, 1e-11, "waveform-mode forward walker %d" % k)
