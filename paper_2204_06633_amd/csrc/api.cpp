@@ -12,6 +12,7 @@
 
 #include "../../include/lisaresp.h"
 #include "internal.hpp"
+#include "trace.hpp"
 
 namespace {
 thread_local std::string g_err;
@@ -283,6 +284,7 @@ int lr_orbits_bounds(double t0, double dt, int64_t n, const double* x_sc, const 
 
 int lr_orbits_init(double t0, double dt, int64_t n, const double* x_sc, const double* ltt,
                    void* d_storage, size_t bytes, lr_orbits* out, void* stream) {
+  LR_CALL_RANGE();
   if (!out || !x_sc || !ltt || !d_storage) return fail(LR_E_ARG, "null pointer");
   if (n < 4) return fail(LR_E_ARG, "need at least 4 coarse orbit samples (got %lld)", (long long)n);
   if (!(dt > 0.0) || !is_finite(dt) || !is_finite(t0)) return fail(LR_E_ARG, "bad orbit grid t0/dt");
@@ -339,6 +341,7 @@ int lr_tdi_padding(const lr_orbits* orb, int order, int generation, double dt, i
 int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, const double* hp,
                      const double* hc, const double* sky, int order, int64_t y_start,
                      int64_t n_y, double* y, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_projection(orb, t0_h, dt, n_h, order, y_start, n_y)) return st;
   if (n_y == 0) return LR_OK;
   if (!hp || !hc || !y || !sky) return fail(LR_E_ARG, "null pointer");
@@ -368,6 +371,7 @@ int lr_project_links(const lr_orbits* orb, double t0_h, double dt, int64_t n_h, 
 int lr_tdi_combine(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, const double* y,
                    int generation, int order, int channels, int64_t out_start, int64_t n_out,
                    double* out, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_tdi(orb, t0_y, dt, n_y, generation, order, channels, out_start, n_out))
     return st;
   if (n_out == 0) return LR_OK;
@@ -396,6 +400,7 @@ int lr_tdi_combine(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, co
 int lr_tdi_adjoint(const lr_orbits* orb, double t0_y, double dt, int64_t n_y, int generation,
                    int order, int channels, int64_t out_start, int64_t n_out,
                    const double* g_out, double* g_y, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_tdi(orb, t0_y, dt, n_y, generation, order, channels, out_start, n_out))
     return st;
   if (n_y == 0) return LR_OK;
@@ -434,6 +439,7 @@ int lr_project_adjoint(const lr_orbits* orb, double t0_h, double dt, int64_t n_h
                        int64_t y_start, int64_t n_y, const double* g_y, double* g_hp,
                        double* g_hc, double* g_sky, void* work, size_t work_bytes,
                        void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_projection(orb, t0_h, dt, n_h, order, y_start, n_y)) return st;
   if (!g_hp || !g_hc || !sky || (n_y > 0 && !g_y)) return fail(LR_E_ARG, "null pointer");
   if (g_sky && (!hp || !hc)) return fail(LR_E_ARG, "the sky gradient needs h+ and hx");
@@ -488,6 +494,7 @@ size_t lr_loglike_workspace(void) { return lr::loglike_workspace_bytes(); }
 
 int lr_loglike(const double* h, const double* data, int64_t n, double sigma, double* loglike,
                double* g_h, void* work, size_t work_bytes, void* stream) {
+  LR_CALL_RANGE();
   if (n < 0) return fail(LR_E_ARG, "negative size");
   if (!(sigma > 0.0) || !is_finite(sigma)) return fail(LR_E_ARG, "sigma must be positive");
   if (!loglike || !work || (n > 0 && (!h || !data))) return fail(LR_E_ARG, "null pointer");

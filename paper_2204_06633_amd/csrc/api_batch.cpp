@@ -12,6 +12,7 @@
 #include "batch_types.hpp"
 #include "gb_types.hpp"
 #include "internal.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -290,6 +291,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
                      const lr_orbits* tdi, double t0, double dt, int order, int generation,
                      int channels, int group, int tile, int segment, int adjoint, void* ws,
                      size_t ws_bytes, lr_batch* out, void* stream) {
+  LR_CALL_RANGE();
   if (!out || !proj || !tdi) return set_error(LR_E_ARG, "null pointer");
   if (!std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt)) return set_error(LR_E_ARG, "bad t0 or dt");
   Plan P;
@@ -388,6 +390,7 @@ int lr_batch_prepare(const lr_template* t, int64_t n, const lr_orbits* proj,
 
 int lr_response(const lr_batch* b, const double* hp, const double* hc, const double* sky,
                 double* out, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_batch(b)) return st;
   if (b->n_items == 0) return LR_OK;
   if (!hp || !hc || !sky || !out) return set_error(LR_E_ARG, "null pointer");
@@ -395,6 +398,7 @@ int lr_response(const lr_batch* b, const double* hp, const double* hc, const dou
 }
 
 int lr_response_gb(const lr_batch* b, const double* params, double* out, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_batch(b)) return st;
   if (b->n_items == 0) return LR_OK;
   if (!params || !out) return set_error(LR_E_ARG, "null pointer");
@@ -407,6 +411,7 @@ int lr_response_gb(const lr_batch* b, const double* params, double* out, void* s
 int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
                         const double* sky, const double* g_out, double* g_hp, double* g_hc,
                         double* g_sky, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_batch(b)) return st;
   if (!b->adjoint) return set_error(LR_E_WORKSPACE, "batch prepared without adjoint workspace");
   if (!g_hp || !g_hc || !sky || (b->n_tdi_items > 0 && !g_out))
@@ -465,6 +470,7 @@ int lr_response_adjoint(const lr_batch* b, const double* hp, const double* hc,
 
 int lr_response_adjoint_gb(const lr_batch* b, const double* params, const double* g_out,
                            double* g_params, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_batch(b)) return st;
   if (!b->adjoint) return set_error(LR_E_WORKSPACE, "batch prepared without adjoint workspace");
   if (!params || !g_params || (b->n_tdi_items > 0 && !g_out))
@@ -525,6 +531,7 @@ int lr_response_adjoint_gb(const lr_batch* b, const double* params, const double
 
 int lr_batch_loglike(const lr_batch* b, const double* out, const double* data, double sigma,
                      double* loglike, double* g_out, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_batch(b)) return st;
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return set_error(LR_E_ARG, "sigma must be positive");
   if (!loglike || (b->n_like_items > 0 && (!out || !data))) return set_error(LR_E_ARG, "null pointer");

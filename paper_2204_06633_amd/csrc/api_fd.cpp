@@ -9,6 +9,7 @@
 #include "../../include/lisaresp.h"
 #include "fd_types.hpp"
 #include "internal.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -117,6 +118,7 @@ size_t lr_fd_workspace(int64_t n, int channels, int64_t max_batch) {
 int lr_fd_prepare(int64_t n, int channels, double dt, const double* data, int64_t data_cstride,
                   const double* w_ae, const double* w_t, int64_t max_batch, void* ws,
                   size_t ws_bytes, lr_fd_plan* out, void* stream) {
+  LR_CALL_RANGE();
   if (!out) return set_error(LR_E_ARG, "null plan");
   *out = lr_fd_plan{};
   if (n < 1) return set_error(LR_E_ARG, "n = %lld samples", (long long)n);
@@ -159,6 +161,7 @@ int lr_fd_prepare(int64_t n, int channels, double dt, const double* data, int64_
 
 int lr_fd_loglike(const lr_fd_plan* p, int64_t n_templates, const double* h, int64_t t_stride,
                   int64_t c_stride, double* stats, double* g_h, void* stream) {
+  LR_CALL_RANGE();
   if (!p || !p->ws || p->n < 1 || p->log2n < kMinLog || p->log2n > kMaxLog)
     return set_error(LR_E_ARG, "plan not prepared");
   if (n_templates < 0) return set_error(LR_E_ARG, "negative template count");

@@ -8,6 +8,7 @@
 #include "../../include/lisaresp.h"
 #include "gb_types.hpp"
 #include "internal.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -35,6 +36,7 @@ extern "C" {
 
 int lr_gb_polarizations(const double* params, int64_t n, int64_t k0, int64_t n_h, double dt,
                         double* hp, double* hc, int64_t h_stride, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_common(n, n_h, dt, h_stride)) return st;
   if (n == 0 || n_h == 0) return LR_OK;
   if (!params || !hp || !hc) return set_error(LR_E_ARG, "null pointer");
@@ -65,6 +67,7 @@ int lr_gb_polarizations_adjoint(const double* params, int64_t n, int64_t k0, int
                                 double dt, const double* g_hp, const double* g_hc,
                                 int64_t h_stride, double* g_params, void* work,
                                 size_t work_bytes, void* stream) {
+  LR_CALL_RANGE();
   if (int st = check_common(n, n_h, dt, h_stride)) return st;
   if (n == 0) return LR_OK;
   if (!params || !g_params || !work || (n_h > 0 && (!g_hp || !g_hc)))

@@ -7,6 +7,7 @@
 
 #include "../../include/lisaresp.h"
 #include "internal.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -50,6 +51,7 @@ int lr_project_adjoint_noalloc(const lr_orbits* orb, double t0_h, double dt, int
                                const double* hp, const double* hc, const double* sky, int order,
                                int64_t y_start, int64_t n_y, const double* g_y, double* g_hp,
                                double* g_hc, double* g_sky, void* stream) {
+  LR_CALL_RANGE();
   if (!g_sky) {
     return lr_project_adjoint(orb, t0_h, dt, n_h, hp, hc, sky, order, y_start, n_y, g_y, g_hp,
                               g_hc, nullptr, nullptr, 0, stream);

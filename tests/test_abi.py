@@ -4,6 +4,8 @@ import ctypes
 import glob
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -330,3 +332,34 @@ def test_switch_defaults_in_the_headers():
                 assert m.group(1) not in found, m.group(1)
                 found[m.group(1)] = int(m.group(2))
     assert found == PRODUCT_SWITCHES
+
+
+def _c_functions(text):
+    """(name, body) of every top-level `lr_*` function definition."""
+    out = []
+    for m in re.finditer(r"\n(?:int|size_t|int64_t|const char\*) (lr_\w+)\([^;{]*\)\s*\{", text):
+        depth, i = 1, m.end()
+        while depth:
+            depth += {"{": 1, "}": -1}.get(text[i], 0)
+            i += 1
+        out.append((m.group(1), text[m.end():i]))
+    return out
+
+
+def test_every_device_call_opens_a_marker_range():
+    """Each C-ABI call that launches kernels or copies opens a roctx range
+    named after itself (rocprofv3 --marker-trace), and the library links the
+    roctx library."""
+    csrc = os.path.join(ROOT, "paper_2204_06633_amd", "csrc")
+    device = re.compile(r"\b(run_\w+|launch_\w+|hipMemcpy\w*|hipMemsetAsync|hipLaunchKernelGGL)\(")
+    seen = 0
+    for f in ("api.cpp", "api_batch.cpp", "api_fd.cpp", "api_gb.cpp", "api_noalloc.hip"):
+        for name, body in _c_functions(open(os.path.join(csrc, f)).read()):
+            if device.search(body):
+                seen += 1
+                assert body.lstrip().startswith("LR_CALL_RANGE();"), (f, name)
+    assert seen >= 15
+    nm = shutil.which("nm")
+    if nm:
+        syms = subprocess.run([nm, "-D", native.LIB_PATH], capture_output=True, text=True).stdout
+        assert "roctxRangePushA" in syms and "roctxRangePop" in syms

@@ -15,6 +15,8 @@ import subprocess
 
 import pytest
 
+from paper_2204_06633_amd.csrc import build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HC = os.path.join(ROOT, "tests", "hostcheck")
 ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
@@ -53,6 +55,7 @@ def test_library_host_code_under_sanitizers(tmp_path):
            "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
            "-I" + os.path.join(ROOT, "include"),
            os.path.join(HC, "lib_driver.cpp"), os.path.join(HC, "launch_stubs.cpp"),
-           os.path.join(csrc, "api.cpp"), os.path.join(csrc, "api_batch.cpp"), "-o", exe]
+           os.path.join(csrc, "api.cpp"), os.path.join(csrc, "api_batch.cpp"), "-o", exe,
+           *build.link_flags()]
     subprocess.check_call(cmd, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
     _run(exe)
