@@ -24,7 +24,7 @@ def _t(torch, a):
 
 
 def _build(torch, n_out_list, order=25, gen=2, channels="AET", group=2, adjoint=False, seed=3,
-           dt=10.0, tdi_orbit_kind=None):
+           dt=10.0, tdi_orbit_kind=None, segment=0):
     from paper_2204_06633_amd import native
     grids, params, sp, st = workloads.make_batch(len(n_out_list), "keplerian", n_out_list, dt,
                                                  order, gen, seed, tdi_orbit_kind=tdi_orbit_kind)
@@ -39,7 +39,7 @@ def _build(torch, n_out_list, order=25, gen=2, channels="AET", group=2, adjoint=
     gp = native.Orbits.from_samples(sp)
     gt = gp if st is sp else native.Orbits.from_samples(st)
     batch = native.Batch(lay.templates(), gp, gt, grids[0].t_start, dt, order, gen, channels,
-                         group=group, adjoint=adjoint)
+                         group=group, adjoint=adjoint, segment=segment)
     sky = np.ascontiguousarray(params[:, 6:8])
     return dict(batch=batch, lay=lay, grids=grids, params=params, sp=sp, st=st, hp=hp, hc=hc,
                 sky=sky, orbs=(gp, gt), order=order, gen=gen, channels=channels)
@@ -413,3 +413,36 @@ def test_waveform_mode_other_orders_and_generations(torch_cuda, order, gen, grou
     ref = oracle.response(op, op, g, h_p, h_c, p[6], p[7], order, gen, channels)
     cases.check(out_gb[oo:oo + 3 * g.n_out].view(3, g.n_out).cpu().numpy(), ref, TOL,
                 "waveform mode, order %d, TDI-%d" % (order, gen))
+
+
+@pytest.mark.parametrize("order,gen,dt,carries", [
+    (25, 1, 10.0, True),      # TDI-1: F + B odd, the halo rounded up to even
+    (25, 2, 4.3, True),       # halo of 42 samples: exactly what the rows of a 2 x 256 item hold
+    (25, 2, 4.0, False),      # halo of 44: one-tile work items
+    (31, 2, 10.0, True),
+    (1, 2, 10.0, True),
+])
+def test_segments_at_the_halo_limits(torch_cuda, order, gen, dt, carries):
+    """Work items of several tiles (the TDI halo passed on in LDS) equal
+    one-tile items bit for bit at other orders, TDI-1 (odd padding) and
+    halos at and beyond the kernel's capacity (where the plan falls back to
+    one tile), with templates ending inside segments; one template against
+    the oracle."""
+    torch = torch_cuda
+    channels = "XYZ" if gen == 1 else "AET"
+    n_out_list = [2600, 1900, 777, 1]
+    B1 = _build(torch, n_out_list, order=order, gen=gen, channels=channels, dt=dt, seed=60 + order,
+                segment=1)
+    B3 = _build(torch, n_out_list, order=order, gen=gen, channels=channels, dt=dt, seed=60 + order,
+                segment=3)
+    assert B1["batch"].segment == 1
+    assert B3["batch"].segment == (3 if carries else 1)
+    args = (_t(torch, B1["hp"]), _t(torch, B1["hc"]), _t(torch, B1["sky"]))
+    out1 = B1["batch"].response(*args)
+    out3 = B3["batch"].response(*args)
+    torch.cuda.synchronize()
+    n = B1["batch"].out_extent
+    assert torch.equal(out1[:n], out3[:n])
+    k = 0
+    got = B3["batch"].output_block(out3, k).cpu().numpy()
+    cases.check(got, _oracle_out(B3, k), TOL, "order %d TDI-%d dt %g" % (order, gen, dt))
