@@ -60,7 +60,9 @@ enum { LR_XYZ = 0, LR_AET = 1, LR_XYZ_AET = 2 };
 const char *lr_status_str(int status);
 /* Message of the last failing call on this thread ("" if none). */
 const char *lr_last_error(void);
-/* ABI version of this header (bumped on incompatible changes). */
+/* ABI version of this header (bumped on incompatible changes); the library
+ * returns the version it was built with. */
+#define LR_ABI_VERSION 5
 int lr_abi_version(void);
 /* The build-time tuning switches the library was compiled with, as
  * "NAME=value;NAME=value;..." (register budgets, load pipelining, the TDI

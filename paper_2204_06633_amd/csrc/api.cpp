@@ -264,7 +264,7 @@ const char* lr_status_str(int s) {
 
 const char* lr_last_error(void) { return g_err.c_str(); }
 
-int lr_abi_version(void) { return 4; }
+int lr_abi_version(void) { return LR_ABI_VERSION; }
 
 size_t lr_orbits_bytes(int64_t n) {
   if (n < 4) return 0;

@@ -13,6 +13,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # LISARESP_LIB selects another build of the same library (tuning variants).
 LIB_PATH = os.environ.get("LISARESP_LIB") or os.path.join(_HERE, "_lisaresp.so")
+# LR_ABI_VERSION of include/lisaresp.h that the argument lists below follow
+ABI_VERSION = 5
 
 LR_XYZ, LR_AET, LR_XYZ_AET = 0, 1, 2
 CHANNELS = {"XYZ": LR_XYZ, "AET": LR_AET, "XYZAET": LR_XYZ_AET}
@@ -60,6 +62,10 @@ def lib():
     L.lr_status_str.argtypes = [i32]
     L.lr_last_error.restype = ctypes.c_char_p
     L.lr_abi_version.restype = i32
+    if L.lr_abi_version() != ABI_VERSION:
+        raise RuntimeError("%s has ABI version %d, this binding expects %d: rebuild it "
+                           "(python -m paper_2204_06633_amd.csrc.build)"
+                           % (LIB_PATH, L.lr_abi_version(), ABI_VERSION))
     L.lr_build_config.restype = ctypes.c_char_p
     L.lr_build_config.argtypes = []
     L.lr_orbits_bytes.restype = ctypes.c_size_t

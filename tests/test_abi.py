@@ -40,7 +40,9 @@ def test_status_strings():
     L = native.lib()
     for s in range(6):
         assert L.lr_status_str(s).startswith(b"LR_")
-    assert L.lr_abi_version() >= 1
+    assert L.lr_abi_version() == native.ABI_VERSION
+    hdr = open(os.path.join(ROOT, "include", "lisaresp.h")).read()
+    assert "#define LR_ABI_VERSION %d\n" % native.ABI_VERSION in hdr
 
 
 def _fake_orbits(n=20, dt=1e4, t0=0.0, lmin=8.0, lmax=8.7, rmax=1.6e11):
