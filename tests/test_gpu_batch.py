@@ -135,13 +135,16 @@ def test_batch_adjoint_and_loglike(torch_cuda):
     cases.check(got, np.stack([rhp, rhc]), 1e-10, "batch adjoint")
 
 
-def test_graph_capture_replays_match_eager(torch_cuda):
+@pytest.mark.parametrize("segment", [0, 3])
+def test_graph_capture_replays_match_eager(torch_cuda, segment):
     """Forward, likelihood and adjoint captured in one HIP graph; replays with
-    new sky angles and new polarisations match eager calls each time."""
+    new sky angles and new polarisations match eager calls each time (work
+    items of one tile, and of three passing the TDI halo on)."""
     torch = torch_cuda
     n_out_list = [1300, 800, 1000]
-    B = _build(torch, n_out_list, group=2, adjoint=True, seed=9)
+    B = _build(torch, n_out_list, group=2, adjoint=True, seed=9, segment=segment)
     batch = B["batch"]
+    assert batch.segment == (segment or 1)
     hp, hc, sky = _t(torch, B["hp"]), _t(torch, B["hc"]), _t(torch, B["sky"])
     out = torch.empty(batch.out_extent, dtype=torch.float64, device="cuda")
     data = torch.zeros_like(out)
