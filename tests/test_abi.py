@@ -365,3 +365,29 @@ def test_every_device_call_opens_a_marker_range():
     if nm:
         syms = subprocess.run([nm, "-D", native.LIB_PATH], capture_output=True, text=True).stdout
         assert "roctxRangePushA" in syms and "roctxRangePop" in syms
+
+
+def test_segment_rule_in_the_work_list():
+    """The plan's segments, seen through the size of the work list: items of
+    8 tiles make the list of a long batch ~8 times shorter than items of one;
+    the automatic choice takes 8 when the batch keeps >= 2048 items; where
+    the TDI halo exceeds what the kernel's rows carry (groups of 4), every
+    segment length gives one-tile items."""
+    L = native._batch_lib()
+    o = _fake_orbits(n=400, dt=1e5)
+    aet = native.CHANNELS["AET"]
+    n, n_out = 64, 300000                     # 64 templates of 300000 outputs at dt = 10 s
+    arr = (native.lr_template * n)(*[native.lr_template(k * (n_out + 4000), n_out + 4000, 2000,
+                                                        n_out, 3 * n_out * k) for k in range(n)])
+
+    def ws(group, tile, seg):
+        return L.lr_batch_workspace(arr, n, ctypes.byref(o), 10.0, 25, 2, aet, group, tile, seg, 0)
+
+    base = ws(2, 512, 64)                     # a handful of items: everything else
+    items = lambda group, tile, seg: ws(group, tile, seg) - base
+    i1, i8 = items(2, 512, 1), items(2, 512, 8)
+    assert i1 > 6 * i8 > 0
+    # automatic: 32 groups x 628 one-tile items = 20096 >= 8 x 2048, so 8
+    assert ws(2, 512, 0) == ws(2, 512, 8)
+    for seg in (0, 2, 8):
+        assert ws(4, 512, seg) == ws(4, 512, 1)
