@@ -112,6 +112,9 @@ int make_plan(const lr_template* t, int64_t n, const lr_orbits* tdi, double dt, 
   if (tile - P.T_out > lr::fused_halo_cap(group, tile / 2)) P.K = 1;   // workgroup: tile / 2
   else if (segment > 0) P.K = segment;
   else P.K = (int)std::max<int64_t>(1, std::min<int64_t>(8, tiles1 / 2048));
+  // Every segment starts before its group's longest template ends: the
+  // fused kernel relies on it (an item without a tile would skip the barrier
+  // that orders the reads of the item index before the next fetch).
   const int64_t seg_out = P.T_out + (int64_t)(P.K - 1) * tile;
   for (int64_t g = 0; g < n_groups; ++g) {
     const int64_t segs = (gmax[g] + seg_out - 1) / seg_out;
